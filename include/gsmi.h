@@ -1,0 +1,278 @@
+/*
+ * gsmi — differentiable 16x16-tile Gaussian-splatting rasterizer with
+ * view-level active-set reduction, for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Conventions shared by every entry point:
+ *  - Array pointers are DEVICE pointers owned by the caller; the library never
+ *    allocates, frees or keeps them.  Structs (gs_scene, gs_camera, ...) are
+ *    HOST memory read during the call only.
+ *  - Layouts are structure-of-arrays, component-major: a [C][n] array holds
+ *    component c of element i at index c*n + i.  Images are [3][H][W] float32,
+ *    per-pixel maps [H][W].  Bitmaps hold bit i in bit (i % 32) of 32-bit word
+ *    i / 32.
+ *  - Every call is asynchronous on `stream` (NULL = the null stream).  Counts
+ *    the host may want (pairs, active Gaussians) are written to device int64
+ *    slots; reading them is the caller's only synchronisation.
+ *  - Scratch memory is a caller-owned device workspace `ws` of `ws_bytes`
+ *    bytes (256-byte aligned), sized with gs_workspace_size().  Its contents
+ *    are undefined between calls; calls that share one workspace must not
+ *    overlap.
+ *  - Return value: GS_OK or a negative GS_ERR_* code; nothing aborts or
+ *    throws.  gs_last_error() returns a thread-local message for the last
+ *    failing call.  Argument checks happen on the host before any launch; a
+ *    call that returns an error has launched nothing.
+ *
+ * The rasterizer follows the paper's 3DGS preliminaries (Appendix A, the
+ * Gaussian-kernel and the front-to-back alpha-compositing equations) with the
+ * standard constants of the 3DGS rasterizer it keeps: 16x16 tiles, 64-bit
+ * (tile | depth) keys, alpha = min(0.99, o G), Gaussians with alpha < 1/255
+ * skipped, a pixel stops before its transmittance would fall below 1e-4,
+ * 0.3 px^2 screen-space dilation, 3-sigma radius, SH degree 3.
+ */
+#ifndef GSMI_H
+#define GSMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GS_OK = 0,
+    GS_ERR_INVALID_ARG = -1, /* null/misaligned pointer, bad size or count */
+    GS_ERR_CAPACITY = -2,    /* reserved for host-checked capacity misses */
+    GS_ERR_WORKSPACE = -3,   /* ws_bytes below gs_workspace_size() */
+    GS_ERR_HIP = -4          /* a HIP launch failed; see gs_last_error() */
+};
+
+#define GS_TILE 16
+#define GS_SH_COEFFS 16
+#define GS_MAX_CAMS 8
+#define GS_MAX_PAIRS ((int64_t)1 << 30)
+
+/* Pinhole camera.  x_cam = R x_world + t (R row-major, rows = camera right,
+ * down, forward).  Pixel (u, v) samples the image plane at (u+0.5, v+0.5);
+ * Gaussians with camera depth <= znear are culled. */
+typedef struct gs_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float znear;
+} gs_camera;
+
+/* Gaussian parameters, before activation (Sec. 3 "standard 3DGS
+ * parameterization"): scale = exp(log_scale), rotation = normalised quat
+ * (w, x, y, z), opacity = sigmoid(opacity_logit), colour = SH degree 3. */
+typedef struct gs_scene {
+    int64_t n;
+    const float* mean;          /* [3][n] */
+    const float* log_scale;     /* [3][n] */
+    const float* quat;          /* [4][n] */
+    const float* opacity_logit; /* [n] */
+    const float* sh;            /* [16][3][n] (coefficient, channel, Gaussian) */
+    const uint8_t* lod;         /* [n] level labels, or NULL */
+} gs_scene;
+
+/* Projection of one camera's input list (entry j = Gaussian active_idx[j]).
+ * `rec` is required: the packed per-Gaussian render record, 12 floats,
+ * 16-byte aligned: (mx, my, conic_a, conic_b), (conic_c, opacity, r, g),
+ * (b, depth, 0, 0).  The component-major copies (mean2d .. rgb) are optional
+ * (NULL = not written).  Culled entries get radius 0, tiles_touched 0,
+ * depth 0, clamp bits 0 and zeros in the optional arrays; their `rec` is not
+ * written. */
+typedef struct gs_projected {
+    float* rec;               /* [n][12] required */
+    float* depth;             /* [n] required */
+    int32_t* radius;          /* [n] required */
+    uint32_t* tiles_touched;  /* [n] required */
+    uint8_t* clamp_bits;      /* [n] required; bit c: colour channel c clamped at 0 */
+    float* mean2d;            /* [2][n] optional */
+    float* conic;             /* [3][n] optional */
+    float* opacity;           /* [n] optional */
+    float* rgb;               /* [3][n] optional */
+} gs_projected;
+
+/* Parameter gradients, same layouts as gs_scene; accumulated (+=). */
+typedef struct gs_grads {
+    float* mean;
+    float* log_scale;
+    float* quat;
+    float* opacity_logit;
+    float* sh;
+} gs_grads;
+
+enum { GS_LOD_NONE = 0, GS_LOD_LEVEL = 1, GS_LOD_RADIUS = 2 };
+
+typedef struct gs_lod_params {
+    int32_t mode;          /* GS_LOD_NONE | GS_LOD_LEVEL | GS_LOD_RADIUS */
+    float d0;              /* level mode: reference camera-to-scene distance */
+    float f;               /* level mode: ratio between levels (2) */
+    int32_t l_max;         /* level mode: unlocked ceiling L_max(t) */
+    float fallback_ratio;  /* skip the gate when it keeps >= this share (0.95) */
+    float radius_min_px;   /* radius mode: keep r >= this (0.5) */
+    float radius_sigma_k;  /* radius mode: r = k fx max_j s_j / |mu - c| (1) */
+} gs_lod_params;
+
+enum {
+    GS_OP_LOD_MASK = 0,
+    GS_OP_BIN_SORT = 1,
+    GS_OP_RENDER_BWD = 2,
+    GS_OP_IMPORTANCE = 3,
+    GS_OP_SCORE_KEEP = 4,
+    GS_OP_L1_LOSS = 5
+};
+
+/* Bytes of workspace `op` needs for n Gaussians (per camera), n_pairs pair
+ * capacity, n_tiles tiles over all cameras and n_cams cameras.  Arguments an
+ * op does not use are ignored. */
+size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t n_tiles, int n_cams);
+
+const char* gs_last_error(void);
+
+/* Number of 16x16 tiles of a width x height image. */
+int64_t gs_num_tiles(int32_t width, int32_t height);
+
+/*
+ * View-level active set (Sec. 3.3, Eqs. 1-3).  Gate per Gaussian i:
+ *  GS_LOD_LEVEL:  L_v = clamp(floor(log_f(d0 / d) + 0.5), 0, l_max) with
+ *                 d = |mean_i - camera centre| (d < 1e-6 gives l_max);
+ *                 keep lod_i <= L_v (Eqs. 1-2).  Needs scene->lod.
+ *  GS_LOD_RADIUS: keep k * fx * max_j exp(log_scale_ij) / d >= radius_min_px.
+ *  GS_LOD_NONE:   keep all.
+ * If the gate keeps at least fallback_ratio * n Gaussians it is skipped (the
+ * paper's fall-back to the full shard when the ratio is close to one).
+ * Active set (Eq. 3) = gate AND keep_bits (NULL = all kept; e.g. the
+ * complement of a view's Cull row, or a score mask), written to
+ * active_idx[0 .. n_active) in ascending order; *n_active_dev = count.
+ * active_idx holds n entries.  Workspace: GS_OP_LOD_MASK.
+ */
+int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
+                const uint32_t* keep_bits, int32_t* active_idx, int64_t* n_active_dev,
+                void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Projection (Appendix A: Gaussians projected to screen-space ellipses) of
+ * the input list into n_cams cameras at once, reading the scene once.
+ * Entry j < n_in is Gaussian active_idx[j] (active_idx NULL: Gaussian j).
+ * If n_in_dev is non-NULL the list holds min(*n_in_dev, n_in) entries and the
+ * remaining entries are written as culled (no host synchronisation needed).
+ * Per entry and camera: scale activation, Sigma = R S S^T R^T, camera
+ * transform, near cull, EWA Jacobian (off-axis clamp 1.3x the half field of
+ * view), screen covariance + 0.3 I, conic, radius ceil(3 sqrt(lambda_max)),
+ * 16x16 tile rectangle, SH degree-3 colour + 0.5 clamped at 0, depth.
+ * out[c] receives camera c.  n_cams <= GS_MAX_CAMS.
+ */
+int gs_project(const gs_scene* scene, const int32_t* active_idx, int64_t n_in,
+               const int64_t* n_in_dev, const gs_camera* cams, int n_cams,
+               const gs_projected* out, hipStream_t stream);
+
+/*
+ * Tile binning and depth sort (Appendix A: the depth-ordered Gaussians of each
+ * pixel's tile).  Cameras are concatenated: camera c owns global tiles
+ * [tile_offset_c, tile_offset_c + gs_num_tiles(c)).  For every entry j with
+ * radius > 0 (in order of camera, then j) and each tile of its rectangle in
+ * row-major order, a pair (key = global_tile << 32 | float bits of depth,
+ * value = j) is emitted; pairs are sorted stably by key (LSD radix sort on
+ * 32 + ceil(log2 total_tiles) bits), so each tile's list is ordered by
+ * (depth, j).  tile_ranges [2][total_tiles]: row 0 start, row 1 end.
+ * *n_pairs_dev = number of pairs K.  If K > capacity nothing is sorted and
+ * every tile range is empty; the caller re-runs with capacity >= K.  A
+ * negative count reports an internal failure of the sort (a bounded wait
+ * between workgroups timed out); the lists are then invalid.
+ * keys/vals hold `capacity` entries (capacity <= GS_MAX_PAIRS).
+ * Workspace: GS_OP_BIN_SORT with n_pairs = capacity.
+ */
+int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int n_cams, int64_t n_in,
+                uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* tile_ranges,
+                int64_t* n_pairs_dev, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Front-to-back compositing (Appendix A, compositing equation) of every tile.
+ * Per pixel: T = 1; for the tile's list in order: alpha = min(0.99, o G);
+ * skip if alpha < 1/255; if T (1 - alpha) < 1e-4 stop without compositing;
+ * C += c alpha T; T *= 1 - alpha.  Finally C += T bg.
+ * out_rgb[c] [3][H_c][W_c], out_T[c] [H_c][W_c] final transmittance,
+ * out_last[c] [H_c][W_c] = 1 + list position of the last composited
+ * Gaussian (0 if none).  bg: host float[3].
+ */
+int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, int n_cams,
+                  const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
+                  float* const* out_rgb, float* const* out_T, uint32_t* const* out_last,
+                  hipStream_t stream);
+
+/*
+ * Backward of gs_render_fwd and gs_project: given dL/dC (grad_rgb[c],
+ * [3][H][W]) accumulates dL/dparameters into grads (+=) at the Gaussians
+ * named by active_idx.  Per tile the list is walked back to front from each
+ * pixel's `last`, the transmittance before each Gaussian is recomputed from
+ * the final T (T_k = T_{k+1} / (1 - alpha_k)), and
+ *   dC/dalpha_k = T_k (c_k - S_k) - T_final bg / (1 - alpha_k)
+ * with S_k the colour composited behind k normalised by T_{k+1}.  Per
+ * (Gaussian, tile) the 9 screen-space partials are reduced across the
+ * wavefront and added with one atomic each; a second kernel maps them to
+ * mean, log_scale, quat, opacity_logit and SH (all derivatives exact, zero
+ * through culls, clamps and skip/stop decisions).
+ * If grads2d is non-NULL it receives the screen-space partials of camera 0
+ * ([9][n_in]: d mean2d (2), d conic (3), d opacity (1), d rgb (3)).
+ * Workspace: GS_OP_RENDER_BWD (n = n_in, n_cams).
+ */
+int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in,
+                  const int64_t* n_in_dev, const gs_projected* proj, const gs_camera* cams,
+                  int n_cams, const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
+                  float* const* out_T, uint32_t* const* out_last, float* const* grad_rgb,
+                  gs_grads* grads, float* grads2d, void* ws, size_t ws_bytes,
+                  hipStream_t stream);
+
+/*
+ * One view of the importance-scoring sweep (Sec. 3.2 "Importance score",
+ * Fig. 3) over a single camera's projection of the whole shard (n entries):
+ * the colour-less instrumented blend records w_i = sum_p alpha T and
+ * a_i = number of pixels at which i is composited (w, a: [n], overwritten);
+ * then c^rad = [radius_i > 0], c^vis = membership in the shortest prefix of
+ * (w descending, i ascending) whose mass reaches mass_frac * sum(w),
+ * Cull = 1 - c^vis written as bitmap row cull_row [ceil(n/32)],
+ * score_i += w_i / (a_i + eps) where a_i > 0, c_rad_i += c^rad,
+ * c_vis_i += c^vis.  Workspace: GS_OP_IMPORTANCE.
+ */
+int gs_importance(const gs_projected* proj, const gs_camera* cam, int64_t n,
+                  const uint32_t* vals, const uint32_t* tile_ranges, float mass_frac, float eps,
+                  float* w, uint32_t* a, float* score, uint32_t* c_rad, uint32_t* c_vis,
+                  uint32_t* cull_row, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Score mask: keep_bits [ceil(n/32)] with the n_drop lowest scores (order:
+ * score ascending, index ascending) cleared and all others set.  Scores must
+ * be non-negative.  Workspace: GS_OP_SCORE_KEEP.
+ */
+int gs_score_keep_bits(const float* score, int64_t n, int64_t n_drop, uint32_t* keep_bits,
+                       void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * L1 photometric term (Eq. 4 with lambda = 0): *loss_dev = mean |C - target|
+ * over n_vals values, grad = sign(C - target) / n_vals (sign(0) = 0).
+ * Deterministic two-stage reduction.  Workspace: GS_OP_L1_LOSS.
+ */
+int gs_l1_loss(const float* rgb, const float* target, int64_t n_vals, float* loss_dev,
+               float* grad, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adam with bias correction (Kingma & Ba), one fused launch over n_groups
+ * parameter groups (host arrays of device pointers and counts):
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr_k * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * n_groups <= 8, step >= 1.
+ */
+int gs_adam_step(float* const* params, const float* const* grads, float* const* m,
+                 float* const* v, const int64_t* counts, int n_groups, const float* lr,
+                 float b1, float b2, float eps, int step, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSMI_H */

@@ -196,13 +196,15 @@ def l1_loss(img, target):
 # End-to-end forward + backward
 # --------------------------------------------------------------------------
 def forward_backward(scene_arrays: dict, cam, target=None, bg=(0.0, 0.0, 0.0),
-                     projected_override: Projected | None = None):
+                     projected_override: Projected | None = None, grad_img=None):
     """Project, bin, composite; with a target also the L1 loss and the
     gradients of every parameter (mean, log_scale, quat, opacity_logit, sh).
 
     `projected_override` (tests only) replaces the projected record fed to
-    binning and compositing, e.g. by its float32 rounding."""
-    want = target is not None
+    binning and compositing, e.g. by its float32 rounding.  `grad_img`
+    (tests only) replaces dL/dC, so that two implementations can be compared
+    on the same upstream gradient."""
+    want = target is not None or grad_img is not None
     leaves, out, pr = project(scene_arrays, cam, requires_grad=want)
     prx = projected_override if projected_override is not None else pr
     W, H = cam.width, cam.height
@@ -211,7 +213,10 @@ def forward_backward(scene_arrays: dict, cam, target=None, bg=(0.0, 0.0, 0.0),
     res = dict(projected=pr, out=out, K=K, keys=keys, vals=vals, ranges=ranges, **fwd)
     if not want:
         return res
-    loss, g = l1_loss(fwd["rgb"], target)
+    if grad_img is not None:
+        loss, g = float("nan"), np.asarray(grad_img, dtype=np.float64)
+    else:
+        loss, g = l1_loss(fwd["rgb"], target)
     d2 = render_bwd(prx, vals, ranges, W, H, g, bg)
     vis = out["visible"]
     grads_out = [torch.from_numpy(d2["mean2d"].T.copy()), torch.from_numpy(d2["conic"].T.copy()),

@@ -1,0 +1,467 @@
+// Tile binning: scan of per-entry tile counts fused with key emission, an
+// LSD onesweep radix sort of the 64-bit (tile | depth) keys, and tile-range
+// detection.  All counts stay on the device (no host synchronisation).
+#include "common.h"
+
+namespace gsmi {
+
+// ---------------------------------------------------------------------------
+// Emission
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanIters = 16;
+constexpr int kScanItems = kScanThreads * kScanIters;  // entries per block
+
+struct EmitIn {
+    const float* rec[GS_MAX_CAMS];
+    const float* depth[GS_MAX_CAMS];
+    const int32_t* radius[GS_MAX_CAMS];
+    const uint32_t* tiles[GS_MAX_CAMS];
+    uint32_t tile_off[GS_MAX_CAMS];
+    int32_t TX[GS_MAX_CAMS];
+    int32_t TY[GS_MAX_CAMS];
+    int n_cams;
+    int64_t n_in;  // entries per camera
+};
+
+__device__ __forceinline__ uint32_t tiles_of(const EmitIn& E, int64_t e) {
+    const int c = int(e / E.n_in);
+    const int64_t j = e - int64_t(c) * E.n_in;
+    return E.tiles[c][j];
+}
+
+// Inclusive prefix sum over the wavefront (Hillis-Steele with DPP-free
+// cross-lane reads via __shfl_up; 6 steps).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (lane_id() >= uint32_t(o)) v += t;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads), returns
+// the exclusive prefix and writes the block total to *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds4, uint32_t* total) {
+    const uint32_t inc = wave_incl_scan(v);
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 63) lds4[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t s = lds4[k];
+        if (k < w) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(EmitIn E, int64_t n_total, uint32_t* __restrict__ block_sums) {
+    __shared__ uint32_t lds4[4];
+    const int64_t base = int64_t(blockIdx.x) * kScanItems;
+    uint32_t acc = 0;
+#pragma unroll 4
+    for (int it = 0; it < kScanIters; ++it) {
+        const int64_t e = base + int64_t(it) * kScanThreads + threadIdx.x;
+        if (e < n_total) acc += tiles_of(E, e);
+    }
+    uint32_t tot;
+    block_excl_scan(acc, lds4, &tot);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+// One workgroup: exclusive scan of the block sums, total pair count.
+__global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ block_sums, int64_t n_blocks,
+                                                     int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                     uint32_t* __restrict__ n_sorted) {
+    __shared__ uint32_t lds4[4];
+    __shared__ uint64_t carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < n_blocks; b0 += 256) {
+        const int64_t b = b0 + threadIdx.x;
+        const uint32_t v = b < n_blocks ? block_sums[b] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, lds4, &tot);
+        const uint64_t carry = carry_s;
+        if (b < n_blocks) block_sums[b] = uint32_t(carry + ex);  // fits: K < 2^32 checked below
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t K = int64_t(carry_s);
+        *n_pairs = K;
+        *n_sorted = (K <= capacity) ? uint32_t(K) : 0u;
+    }
+}
+
+__device__ __forceinline__ int64_t fdiv16(int64_t a) { return a >= 0 ? a / 16 : -((-a + 15) / 16); }
+
+__global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const uint32_t* __restrict__ block_offs,
+                                              const uint32_t* __restrict__ n_sorted,
+                                              uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    __shared__ uint32_t lds4[4];
+    if (*n_sorted == 0) return;  // nothing fits (or nothing to emit)
+    const int64_t base = int64_t(blockIdx.x) * kScanItems;
+    uint32_t run = block_offs[blockIdx.x];
+    for (int it = 0; it < kScanIters; ++it) {
+        const int64_t e = base + int64_t(it) * kScanThreads + threadIdx.x;
+        const bool ok = e < n_total;
+        int c = 0;
+        int64_t j = 0;
+        uint32_t cnt = 0;
+        if (ok) {
+            c = int(e / E.n_in);
+            j = e - int64_t(c) * E.n_in;
+            cnt = E.tiles[c][j];
+        }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(cnt, lds4, &tot);
+        if (cnt > 0) {
+            const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
+            const int64_t r = E.radius[c][j];
+            const int64_t xi = int64_t(floorf(fminf(fmaxf(q0.x, -1073741824.f), 1073741824.f)));
+            const int64_t yi = int64_t(floorf(fminf(fmaxf(q0.y, -1073741824.f), 1073741824.f)));
+            const int64_t TX = E.TX[c], TY = E.TY[c];
+            const int64_t x0 = min<int64_t>(max<int64_t>(fdiv16(xi - r), 0), TX);
+            const int64_t x1 = min<int64_t>(max<int64_t>(fdiv16(xi + r) + 1, 0), TX);
+            const int64_t y0 = min<int64_t>(max<int64_t>(fdiv16(yi - r), 0), TY);
+            const int64_t y1 = min<int64_t>(max<int64_t>(fdiv16(yi + r) + 1, 0), TY);
+            const uint32_t dbits = __float_as_uint(E.depth[c][j]);
+            uint32_t o = run + ex;
+            const uint32_t end = o + cnt;  // cnt == (x1-x0)*(y1-y0) by construction
+            for (int64_t ty = y0; ty < y1 && o < end; ++ty)
+                for (int64_t tx = x0; tx < x1 && o < end; ++tx, ++o) {
+                    const uint64_t tile = uint64_t(E.tile_off[c]) + uint64_t(ty * TX + tx);
+                    keys[o] = (tile << 32) | uint64_t(dbits);
+                    vals[o] = uint32_t(j);
+                }
+        }
+        run += tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Onesweep LSD radix sort, 8-bit digits
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 256;
+constexpr int kSortPerThread = 15;
+constexpr int kPart = kSortThreads * kSortPerThread;  // 3840 keys per partition
+constexpr int kWaves = kSortThreads / 64;
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1u;
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+// Global digit histograms of every pass in one read of the keys; also
+// clears the look-back status of the first pass.
+__global__ __launch_bounds__(256) void k_sort_hist(const uint64_t* __restrict__ keys,
+                                                   const uint32_t* __restrict__ n_sorted, int passes,
+                                                   uint32_t* __restrict__ hist, uint32_t* __restrict__ status0) {
+    __shared__ uint32_t h[8][256];
+    for (int k = threadIdx.x; k < 8 * 256; k += 256) (&h[0][0])[k] = 0;
+    __syncthreads();
+    const uint32_t n = *n_sorted;
+    const uint32_t n_parts = (n + kPart - 1) / kPart;
+    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const uint64_t key = keys[i];
+        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(key >> (8 * p)) & 255], 1u);
+    }
+    __syncthreads();
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t v = h[p][threadIdx.x];
+        if (v) atomicAdd(&hist[p * 256 + threadIdx.x], v);
+    }
+}
+
+struct SortLds {
+    uint64_t keys[kPart];
+    uint32_t vals[kPart];
+    uint32_t wcnt[kWaves][256];
+    uint32_t bin_start[256];
+    uint32_t gbase[256];
+    uint32_t dig_off[256];
+    uint32_t scan4[4];
+    uint32_t part;
+};
+
+__global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ keys_in,
+                                                   const uint32_t* __restrict__ vals_in,
+                                                   uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                   const uint32_t* __restrict__ n_sorted,
+                                                   const uint32_t* __restrict__ hist_pass,
+                                                   uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
+                                                   uint32_t* __restrict__ counter, uint32_t* __restrict__ err,
+                                                   int shift) {
+    __shared__ SortLds L;
+    const uint32_t n = *n_sorted;
+    const uint32_t n_parts = (n + kPart - 1) / kPart;
+    const int tid = threadIdx.x;
+    const int w = tid / 64;
+    const uint32_t lane = lane_id();
+
+    // Global exclusive offsets of each digit (scan of this pass's histogram).
+    {
+        const uint32_t v = hist_pass[tid];
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, L.scan4, &tot);
+        L.dig_off[tid] = ex;
+    }
+    for (;;) {
+        if (tid == 0) L.part = atomicAdd(counter, 1u);
+        for (int k = tid; k < kWaves * 256; k += 256) (&L.wcnt[0][0])[k] = 0;
+        __syncthreads();
+        const uint32_t part = L.part;
+        if (part >= n_parts) break;
+        if (status_next) status_next[part * 256 + tid] = 0;  // next pass starts clean
+
+        // 1. load (wave-striped) and rank within the wavefront, stably
+        const uint32_t wbase = part * kPart + uint32_t(w) * (kSortPerThread * 64);
+        uint64_t k_[kSortPerThread];
+        uint32_t v_[kSortPerThread];
+        uint32_t rank_[kSortPerThread];
+#pragma unroll
+        for (int it = 0; it < kSortPerThread; ++it) {
+            const uint32_t idx = wbase + uint32_t(it) * 64 + lane;
+            const bool valid = idx < n;
+            k_[it] = valid ? keys_in[idx] : ~0ull;
+            v_[it] = valid ? vals_in[idx] : 0u;
+            const uint32_t d = uint32_t(k_[it] >> shift) & 255u;
+            uint64_t peers = ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint32_t before = popc64(peers & lanemask_lt());
+            const uint32_t base = L.wcnt[w][d];
+            rank_[it] = base + before;
+            // the lowest lane of each group bumps the wavefront's bin count
+            if (valid && before == 0) L.wcnt[w][d] = base + popc64(peers);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+
+        // 2. per-bin totals, wavefront offsets, and the partition's bin starts
+        uint32_t total = 0;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) {
+            const uint32_t c = L.wcnt[ww][tid];
+            L.wcnt[ww][tid] = total;
+            total += c;
+        }
+        {
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan(total, L.scan4, &tot);
+            L.bin_start[tid] = ex;
+        }
+
+        // 3. decoupled look-back for bin tid
+        {
+            uint32_t* st = status + size_t(part) * 256 + tid;
+            uint32_t excl = 0;
+            if (part == 0) {
+                st_agent(st, kFlagInc | total);
+            } else {
+                st_agent(st, kFlagAgg | total);
+                int64_t p = int64_t(part) - 1;
+                uint32_t spins = 0;
+                while (p >= 0) {
+                    const uint32_t s = ld_agent(status + size_t(p) * 256 + tid);
+                    const uint32_t flag = s & ~kValMask;
+                    if (flag == 0u) {
+                        if (++spins > kSpinLimit) {
+                            atomicOr(err, 1u);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    excl += s & kValMask;
+                    if (flag == kFlagInc) break;
+                    --p;
+                }
+                st_agent(st, kFlagInc | ((excl + total) & kValMask));
+            }
+            L.gbase[tid] = L.dig_off[tid] + excl - L.bin_start[tid];
+        }
+        __syncthreads();
+
+        // 4. stage in LDS in (digit, input order) order
+#pragma unroll
+        for (int it = 0; it < kSortPerThread; ++it) {
+            const uint32_t idx = wbase + uint32_t(it) * 64 + lane;
+            if (idx < n) {
+                const uint32_t d = uint32_t(k_[it] >> shift) & 255u;
+                const uint32_t lp = L.bin_start[d] + L.wcnt[w][d] + rank_[it];
+                L.keys[lp] = k_[it];
+                L.vals[lp] = v_[it];
+            }
+        }
+        __syncthreads();
+
+        // 5. coalesced write-out
+        const uint32_t cnt = min<uint32_t>(kPart, n - part * kPart);
+        for (uint32_t i = tid; i < cnt; i += 256) {
+            const uint64_t key = L.keys[i];
+            const uint32_t d = uint32_t(key >> shift) & 255u;
+            const uint32_t g = L.gbase[d] + i;
+            if (g < n) {  // always true unless a look-back wait timed out
+                keys_out[g] = key;
+                vals_out[g] = L.vals[i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// tile_ranges[t] = first index of tile t, tile_ranges[T + t] = one past last.
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys,
+                                                     const uint32_t* __restrict__ n_sorted, uint32_t n_tiles,
+                                                     uint32_t* __restrict__ ranges) {
+    const uint32_t n = *n_sorted;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const uint32_t t = uint32_t(keys[i] >> 32);
+        // neighbours within the wavefront come from the lane next door
+        const uint32_t tprev_lane = __shfl_up(t, 1, 64);
+        const uint32_t tnext_lane = __shfl_down(t, 1, 64);
+        const uint32_t l = lane_id();
+        const uint32_t tprev = (i == 0) ? 0xffffffffu : (l > 0 ? tprev_lane : uint32_t(keys[i - 1] >> 32));
+        const uint32_t tnext = (i + 1 >= n) ? 0xffffffffu : (l < 63 && i + 1 < n ? tnext_lane : uint32_t(keys[i + 1] >> 32));
+        if (t >= n_tiles) continue;
+        if (t != tprev) ranges[t] = i;
+        if (t != tnext) ranges[n_tiles + t] = i + 1;
+    }
+}
+
+struct SortWs {
+    uint32_t* block_sums;
+    uint32_t* n_sorted;
+    uint32_t* hist;
+    uint32_t* counters;
+    uint32_t* err;
+    uint32_t* status[2];
+    uint64_t* keys_alt;
+    uint32_t* vals_alt;
+    size_t bytes;
+};
+
+static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity) {
+    Carve cv(ws);
+    SortWs s;
+    const int64_t nb = (n_total + kScanItems - 1) / kScanItems + 1;
+    const int64_t np = (capacity + kPart - 1) / kPart + 1;
+    s.block_sums = cv.take<uint32_t>(size_t(nb));
+    s.n_sorted = cv.take<uint32_t>(4);
+    s.hist = cv.take<uint32_t>(8 * 256);
+    s.counters = cv.take<uint32_t>(8);
+    s.err = cv.take<uint32_t>(4);
+    s.status[0] = cv.take<uint32_t>(size_t(np) * 256);
+    s.status[1] = cv.take<uint32_t>(size_t(np) * 256);
+    s.keys_alt = cv.take<uint64_t>(size_t(capacity > 0 ? capacity : 1));
+    s.vals_alt = cv.take<uint32_t>(size_t(capacity > 0 ? capacity : 1));
+    s.bytes = cv.used();
+    return s;
+}
+
+// A timed-out look-back wait (never expected) is reported as a negative count.
+__global__ void k_sort_report(const uint32_t* __restrict__ err, int64_t* __restrict__ n_pairs) {
+    if (threadIdx.x == 0 && *err) *n_pairs = -1;
+}
+
+__global__ void k_sort_init(uint32_t* hist, uint32_t* counters, uint32_t* err) {
+    for (int k = threadIdx.x; k < 8 * 256; k += blockDim.x) hist[k] = 0;
+    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *err = 0;
+}
+
+}  // namespace gsmi
+
+using namespace gsmi;
+
+size_t ws_bin_sort(int64_t n_total, int64_t capacity, int64_t /*n_tiles*/) {
+    return carve_sort(nullptr, n_total, capacity).bytes;
+}
+
+extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int n_cams, int64_t n_in,
+                           uint64_t* keys, uint32_t* vals, int64_t capacity, uint32_t* tile_ranges,
+                           int64_t* n_pairs_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
+    int64_t total_tiles = 0;
+    int rc = validate_cams(cams, n_cams, GS_MAX_CAMS, &total_tiles);
+    if (rc) return rc;
+    if (!proj || n_in < 0 || n_in >= (int64_t(1) << 31))
+        return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: bad projection or n_in");
+    if (capacity < 0 || capacity >= GS_MAX_PAIRS)
+        return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: capacity must be in [0, 2^30)");
+    if (!tile_ranges || !n_pairs_dev || (capacity > 0 && (!keys || !vals)))
+        return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: null output");
+    const int64_t n_total = n_in * n_cams;
+    if (n_total >= (int64_t(1) << 32)) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many entries");
+    SortWs S = carve_sort(ws, n_total, capacity);
+    if (!ws || ws_bytes < S.bytes || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_bin_sort: workspace needs %zu bytes (256-aligned)", S.bytes);
+    EmitIn E;
+    memset(&E, 0, sizeof(E));
+    uint32_t off = 0;
+    for (int c = 0; c < n_cams; ++c) {
+        const gs_projected& p = proj[c];
+        if (n_in > 0 && (!p.rec || !p.depth || !p.radius || !p.tiles_touched))
+            return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: camera %d: null projection array", c);
+        E.rec[c] = p.rec; E.depth[c] = p.depth; E.radius[c] = p.radius; E.tiles[c] = p.tiles_touched;
+        E.tile_off[c] = off;
+        E.TX[c] = int32_t(tiles_x(cams[c].width));
+        E.TY[c] = int32_t(tiles_y(cams[c].height));
+        off += uint32_t(gs_num_tiles(cams[c].width, cams[c].height));
+    }
+    E.n_cams = n_cams;
+    E.n_in = n_in > 0 ? n_in : 1;
+
+    // key bits: 32 depth bits + enough for the global tile id
+    int tile_bits = 0;
+    while ((int64_t(1) << tile_bits) < total_tiles) ++tile_bits;
+    const int passes = (32 + tile_bits + 7) / 8;
+    if (passes > 8) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
+
+    hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, S.hist, S.counters, S.err);
+    if ((rc = fill_u32(tile_ranges, 0u, size_t(2 * total_tiles), stream))) return rc;
+    const int64_t nb = (n_total + kScanItems - 1) / kScanItems;
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, stream, S.block_sums, nb, n_pairs_dev, capacity,
+                       S.n_sorted);
+    if ((rc = check_launch("gs_bin_sort scan"))) return rc;
+    if (capacity == 0) return GS_OK;
+    // Emission target: the ping-pong buffer that ends in keys/vals after `passes` passes.
+    uint64_t* kb[2] = {keys, S.keys_alt};
+    uint32_t* vb[2] = {vals, S.vals_alt};
+    int cur = (passes % 2 == 0) ? 0 : 1;
+    if (nb > 0)
+        hipLaunchKernelGGL(k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
+                           S.n_sorted, kb[cur], vb[cur]);
+    const int64_t max_parts = (capacity + kPart - 1) / kPart;
+    int hist_blocks = int(std::min<int64_t>(1024, (capacity + 4095) / 4096));
+    if (hist_blocks < 1) hist_blocks = 1;
+    hipLaunchKernelGGL(k_sort_hist, dim3(hist_blocks), dim3(256), 0, stream, kb[cur], S.n_sorted, passes, S.hist,
+                       S.status[0]);
+    int grid = int(std::min<int64_t>(max_parts, 256 * 3));
+    if (grid < 1) grid = 1;
+    for (int p = 0; p < passes; ++p) {
+        const int nxt = cur ^ 1;
+        hipLaunchKernelGGL(k_sort_pass, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur], kb[nxt], vb[nxt],
+                           S.n_sorted, S.hist + p * 256, S.status[p & 1],
+                           (p + 1 < passes) ? S.status[(p + 1) & 1] : nullptr, S.counters + p, S.err, 8 * p);
+        cur = nxt;
+    }
+    hipLaunchKernelGGL(k_sort_report, dim3(1), dim3(64), 0, stream, S.err, n_pairs_dev);
+    if ((rc = check_launch("gs_bin_sort sort"))) return rc;
+    hipLaunchKernelGGL(k_tile_ranges, dim3(unsigned(std::min<int64_t>(4096, (capacity + 255) / 256))), dim3(256), 0,
+                       stream, keys, S.n_sorted, uint32_t(total_tiles), tile_ranges);
+    return check_launch("gs_bin_sort ranges");
+}

@@ -1,0 +1,205 @@
+// Error reporting, workspace sizing, fill kernel, L1 loss and fused Adam.
+#include <cmath>
+#include <cstdarg>
+
+#include "common.h"
+
+namespace gsmi {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return GS_OK;
+}
+
+int validate_cams(const gs_camera* cams, int n_cams, int max_cams, int64_t* total_tiles) {
+    if (!cams || n_cams < 1 || n_cams > max_cams)
+        return fail(GS_ERR_INVALID_ARG, "n_cams must be in [1, %d]", max_cams);
+    int64_t tot = 0;
+    for (int c = 0; c < n_cams; ++c) {
+        const gs_camera& k = cams[c];
+        if (k.width <= 0 || k.height <= 0 || k.width > 16384 || k.height > 16384)
+            return fail(GS_ERR_INVALID_ARG, "camera %d: bad image size %dx%d", c, k.width, k.height);
+        if (!(k.fx > 0.f) || !(k.fy > 0.f))
+            return fail(GS_ERR_INVALID_ARG, "camera %d: focal lengths must be positive", c);
+        if (!(k.znear > 0.f)) return fail(GS_ERR_INVALID_ARG, "camera %d: znear must be positive", c);
+        tot += tiles_x(k.width) * tiles_y(k.height);
+    }
+    if (tot >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "too many tiles");
+    if (total_tiles) *total_tiles = tot;
+    return GS_OK;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ dst, uint32_t value, size_t count) {
+    size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    size_t stride = size_t(gridDim.x) * blockDim.x;
+    for (; i < count; i += stride) dst[i] = value;
+}
+
+int fill_u32(void* dst, uint32_t value, size_t count, hipStream_t s) {
+    if (count == 0) return GS_OK;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(blocks)), dim3(256), 0, s,
+                       static_cast<uint32_t*>(dst), value, count);
+    return check_launch("fill");
+}
+
+// ---------------------------------------------------------------------------
+// L1 loss: per-block partial sums in double, then one block sums them in a
+// fixed order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int kL1Blocks = 1024;
+
+__global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ rgb,
+                                                    const float* __restrict__ target, int64_t n,
+                                                    float* __restrict__ grad, double* __restrict__ part) {
+    __shared__ double red[256];
+    const float inv = 1.0f / float(n);
+    double acc = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        float d = rgb[i] - target[i];
+        acc += double(fabsf(d));
+        float s = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+        grad[i] = s * inv;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_l1_final(const double* __restrict__ part, int nparts, int64_t n,
+                                                  float* __restrict__ loss) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = float(red[0] / double(n));
+}
+
+// ---------------------------------------------------------------------------
+// Fused Adam over up to 8 groups
+// ---------------------------------------------------------------------------
+struct AdamGroups {
+    float* p[8];
+    const float* g[8];
+    float* m[8];
+    float* v[8];
+    int64_t start[9];  // prefix of counts (flattened element space)
+    float lr_bc[8];    // lr / (1 - b1^t)
+    int n;
+};
+
+__global__ __launch_bounds__(256) void k_adam(AdamGroups G, float b1, float b2, float eps,
+                                              float inv_sqrt_bc2, int64_t total) {
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+        int k = 0;
+        while (k + 1 < G.n && e >= G.start[k + 1]) ++k;
+        int64_t i = e - G.start[k];
+        float g = G.g[k][i];
+        float m = fmaf(b1, G.m[k][i], (1.f - b1) * g);
+        float v = fmaf(b2, G.v[k][i], (1.f - b2) * g * g);
+        G.m[k][i] = m;
+        G.v[k][i] = v;
+        float denom = sqrtf(v) * inv_sqrt_bc2 + eps;
+        G.p[k][i] -= G.lr_bc[k] * m / denom;
+    }
+}
+
+}  // namespace gsmi
+
+using namespace gsmi;
+
+extern "C" const char* gs_last_error(void) { return g_err; }
+
+extern "C" int64_t gs_num_tiles(int32_t width, int32_t height) {
+    if (width <= 0 || height <= 0) return 0;
+    return tiles_x(width) * tiles_y(height);
+}
+
+size_t ws_lod_mask(int64_t n);
+size_t ws_bin_sort(int64_t n_total, int64_t capacity, int64_t n_tiles);
+size_t ws_render_bwd(int64_t n, int n_cams);
+size_t ws_importance(int64_t n);
+size_t ws_score_keep(int64_t n);
+
+extern "C" size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t n_tiles, int n_cams) {
+    if (n < 0) n = 0;
+    if (n_cams < 1) n_cams = 1;
+    switch (op) {
+        case GS_OP_LOD_MASK: return ws_lod_mask(n);
+        case GS_OP_BIN_SORT: return ws_bin_sort(n * n_cams, n_pairs, n_tiles);
+        case GS_OP_RENDER_BWD: return ws_render_bwd(n, n_cams);
+        case GS_OP_IMPORTANCE: return ws_importance(n);
+        case GS_OP_SCORE_KEEP: return ws_score_keep(n);
+        case GS_OP_L1_LOSS: return size_t(kL1Blocks) * sizeof(double);
+        default: return 0;
+    }
+}
+
+extern "C" int gs_l1_loss(const float* rgb, const float* target, int64_t n_vals, float* loss_dev,
+                          float* grad, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n_vals <= 0 || !rgb || !target || !loss_dev || !grad)
+        return fail(GS_ERR_INVALID_ARG, "gs_l1_loss: null pointer or empty input");
+    if (!ws || ws_bytes < size_t(kL1Blocks) * sizeof(double) || !aligned(ws, 8))
+        return fail(GS_ERR_WORKSPACE, "gs_l1_loss: workspace too small");
+    int blocks = int((n_vals + 255) / 256);
+    if (blocks > kL1Blocks) blocks = kL1Blocks;
+    double* part = static_cast<double*>(ws);
+    hipLaunchKernelGGL(k_l1_partial, dim3(blocks), dim3(256), 0, stream, rgb, target, n_vals, grad, part);
+    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, stream, part, blocks, n_vals, loss_dev);
+    return check_launch("gs_l1_loss");
+}
+
+extern "C" int gs_adam_step(float* const* params, const float* const* grads, float* const* m,
+                            float* const* v, const int64_t* counts, int n_groups, const float* lr,
+                            float b1, float b2, float eps, int step, hipStream_t stream) {
+    if (n_groups < 1 || n_groups > 8 || !params || !grads || !m || !v || !counts || !lr || step < 1)
+        return fail(GS_ERR_INVALID_ARG, "gs_adam_step: bad arguments");
+    AdamGroups G;
+    memset(&G, 0, sizeof(G));
+    G.n = n_groups;
+    G.start[0] = 0;
+    const double bc1 = 1.0 - std::pow(double(b1), step);
+    const double bc2 = 1.0 - std::pow(double(b2), step);
+    for (int k = 0; k < n_groups; ++k) {
+        if (counts[k] < 0 || (counts[k] > 0 && (!params[k] || !grads[k] || !m[k] || !v[k])))
+            return fail(GS_ERR_INVALID_ARG, "gs_adam_step: group %d", k);
+        G.p[k] = params[k]; G.g[k] = grads[k]; G.m[k] = m[k]; G.v[k] = v[k];
+        G.start[k + 1] = G.start[k] + counts[k];
+        G.lr_bc[k] = float(double(lr[k]) / bc1);
+    }
+    const int64_t total = G.start[n_groups];
+    if (total == 0) return GS_OK;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_adam, dim3(unsigned(blocks)), dim3(256), 0, stream, G, b1, b2, eps,
+                       float(1.0 / std::sqrt(bc2)), total);
+    return check_launch("gs_adam_step");
+}

@@ -1,0 +1,497 @@
+// Per-Gaussian projection (EWA splatting + SH degree-3 colour) and its
+// backward.  One thread per input entry; parameters are read as coalesced
+// component-major (SoA) loads, the scene once for all cameras of a batch.
+#include "common.h"
+
+namespace gsmi {
+
+struct SceneP {
+    const float* mean;
+    const float* log_scale;
+    const float* quat;
+    const float* opacity_logit;
+    const float* sh;
+    int64_t n;
+};
+
+struct CamSet {
+    DevCam cam[GS_MAX_CAMS];
+    int n;
+};
+
+struct ProjOut {
+    float* rec[GS_MAX_CAMS];
+    float* depth[GS_MAX_CAMS];
+    int32_t* radius[GS_MAX_CAMS];
+    uint32_t* tiles[GS_MAX_CAMS];
+    uint8_t* clamp[GS_MAX_CAMS];
+    float* mean2d[GS_MAX_CAMS];
+    float* conic[GS_MAX_CAMS];
+    float* opacity[GS_MAX_CAMS];
+    float* rgb[GS_MAX_CAMS];
+};
+
+// Real SH of degree 3 (Condon-Shortley phase, index l*l + l + m) at a unit
+// direction, as the closed-form polynomials of x, y, z.
+constexpr float kC0 = 0.28209479177387814f;
+constexpr float kC1 = 0.4886025119029199f;
+constexpr float kC20 = 1.0925484305920792f, kC21 = -1.0925484305920792f, kC22 = 0.31539156525252005f,
+                kC23 = -1.0925484305920792f, kC24 = 0.5462742152960396f;
+constexpr float kC30 = -0.5900435899266435f, kC31 = 2.890611442640554f, kC32 = -0.4570457994644658f,
+                kC33 = 0.3731763325901154f, kC34 = -0.4570457994644658f, kC35 = 1.445305721320277f,
+                kC36 = -0.5900435899266435f;
+
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float Y[16]) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = kC0;
+    Y[1] = -kC1 * y;
+    Y[2] = kC1 * z;
+    Y[3] = -kC1 * x;
+    Y[4] = kC20 * x * y;
+    Y[5] = kC21 * y * z;
+    Y[6] = kC22 * (2.f * zz - xx - yy);
+    Y[7] = kC23 * x * z;
+    Y[8] = kC24 * (xx - yy);
+    Y[9] = kC30 * y * (3.f * xx - yy);
+    Y[10] = kC31 * x * y * z;
+    Y[11] = kC32 * y * (4.f * zz - xx - yy);
+    Y[12] = kC33 * z * (2.f * zz - 3.f * xx - 3.f * yy);
+    Y[13] = kC34 * x * (4.f * zz - xx - yy);
+    Y[14] = kC35 * z * (xx - yy);
+    Y[15] = kC36 * x * (xx - 3.f * yy);
+}
+
+// Gradient of sum_k w[k] Y_k(x, y, z) with respect to (x, y, z), treating the
+// polynomials above as functions of three free variables.
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, const float w[16], float g[3]) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    gy += w[1] * -kC1;
+    gz += w[2] * kC1;
+    gx += w[3] * -kC1;
+    gx += w[4] * kC20 * y;                gy += w[4] * kC20 * x;
+    gy += w[5] * kC21 * z;                gz += w[5] * kC21 * y;
+    gx += w[6] * kC22 * -2.f * x;         gy += w[6] * kC22 * -2.f * y;   gz += w[6] * kC22 * 4.f * z;
+    gx += w[7] * kC23 * z;                gz += w[7] * kC23 * x;
+    gx += w[8] * kC24 * 2.f * x;          gy += w[8] * kC24 * -2.f * y;
+    gx += w[9] * kC30 * 6.f * x * y;      gy += w[9] * kC30 * (3.f * xx - 3.f * yy);
+    gx += w[10] * kC31 * y * z;           gy += w[10] * kC31 * x * z;     gz += w[10] * kC31 * x * y;
+    gx += w[11] * kC32 * -2.f * x * y;    gy += w[11] * kC32 * (4.f * zz - xx - 3.f * yy);
+    gz += w[11] * kC32 * 8.f * y * z;
+    gx += w[12] * kC33 * -6.f * x * z;    gy += w[12] * kC33 * -6.f * y * z;
+    gz += w[12] * kC33 * (6.f * zz - 3.f * xx - 3.f * yy);
+    gx += w[13] * kC34 * (4.f * zz - 3.f * xx - yy);
+    gy += w[13] * kC34 * -2.f * x * y;    gz += w[13] * kC34 * 8.f * x * z;
+    gx += w[14] * kC35 * 2.f * x * z;     gy += w[14] * kC35 * -2.f * y * z; gz += w[14] * kC35 * (xx - yy);
+    gx += w[15] * kC36 * (3.f * xx - 3.f * yy);
+    gy += w[15] * kC36 * -6.f * x * y;
+    g[0] = gx; g[1] = gy; g[2] = gz;
+}
+
+__device__ __forceinline__ void quat_rot(float w, float x, float y, float z, float R[9]) {
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// Shared forward geometry of one Gaussian in one camera.
+struct Geo {
+    float tx, ty, tz, rz, txtz, tytz, ux, uy;
+    float T0[3], T1[3];  // T = J W
+    float U0[3], U1[3];  // U = T Sigma
+    float a, b, c, det;
+};
+
+__device__ __forceinline__ void geo_camera(const DevCam& C, const float mu[3], Geo& g) {
+    g.tx = fmaf(C.R[0], mu[0], fmaf(C.R[1], mu[1], fmaf(C.R[2], mu[2], C.t[0])));
+    g.ty = fmaf(C.R[3], mu[0], fmaf(C.R[4], mu[1], fmaf(C.R[5], mu[2], C.t[1])));
+    g.tz = fmaf(C.R[6], mu[0], fmaf(C.R[7], mu[1], fmaf(C.R[8], mu[2], C.t[2])));
+}
+
+__device__ __forceinline__ void geo_cov(const DevCam& C, const float S[6], Geo& g) {
+    // S = (s00, s01, s02, s11, s12, s22)
+    g.rz = 1.f / g.tz;
+    g.txtz = g.tx * g.rz;
+    g.tytz = g.ty * g.rz;
+    g.ux = fminf(fmaxf(g.txtz, -C.limx), C.limx);
+    g.uy = fminf(fmaxf(g.tytz, -C.limy), C.limy);
+    const float J00 = C.fx * g.rz, J02 = -C.fx * g.ux * g.rz;
+    const float J11 = C.fy * g.rz, J12 = -C.fy * g.uy * g.rz;
+    for (int k = 0; k < 3; ++k) {
+        g.T0[k] = fmaf(J00, C.R[k], J02 * C.R[6 + k]);
+        g.T1[k] = fmaf(J11, C.R[3 + k], J12 * C.R[6 + k]);
+    }
+    const float s00 = S[0], s01 = S[1], s02 = S[2], s11 = S[3], s12 = S[4], s22 = S[5];
+    g.U0[0] = g.T0[0] * s00 + g.T0[1] * s01 + g.T0[2] * s02;
+    g.U0[1] = g.T0[0] * s01 + g.T0[1] * s11 + g.T0[2] * s12;
+    g.U0[2] = g.T0[0] * s02 + g.T0[1] * s12 + g.T0[2] * s22;
+    g.U1[0] = g.T1[0] * s00 + g.T1[1] * s01 + g.T1[2] * s02;
+    g.U1[1] = g.T1[0] * s01 + g.T1[1] * s11 + g.T1[2] * s12;
+    g.U1[2] = g.T1[0] * s02 + g.T1[1] * s12 + g.T1[2] * s22;
+    g.a = g.U0[0] * g.T0[0] + g.U0[1] * g.T0[1] + g.U0[2] * g.T0[2] + kDilation;
+    g.b = g.U0[0] * g.T1[0] + g.U0[1] * g.T1[1] + g.U0[2] * g.T1[2];
+    g.c = g.U1[0] * g.T1[0] + g.U1[1] * g.T1[1] + g.U1[2] * g.T1[2] + kDilation;
+    g.det = g.a * g.c - g.b * g.b;
+}
+
+__device__ __forceinline__ void covariance(const float ls[3], const float q[4], float s[3], float qn[4],
+                                           float R[9], float M[9], float S[6], float& qlen) {
+    s[0] = __expf(ls[0]); s[1] = __expf(ls[1]); s[2] = __expf(ls[2]);
+    qlen = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const float inv = 1.f / qlen;
+    for (int k = 0; k < 4; ++k) qn[k] = q[k] * inv;
+    quat_rot(qn[0], qn[1], qn[2], qn[3], R);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[r * 3 + c] = R[r * 3 + c] * s[c];
+    S[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+    S[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+    S[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+    S[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+    S[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+    S[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+}
+
+__device__ __forceinline__ int64_t floordiv16(int64_t a) { return a >= 0 ? a / 16 : -((-a + 15) / 16); }
+
+__device__ __forceinline__ void culled_out(const ProjOut& O, int c, int64_t j, int64_t n) {
+    O.depth[c][j] = 0.f;
+    O.radius[c][j] = 0;
+    O.tiles[c][j] = 0u;
+    O.clamp[c][j] = 0;
+    if (O.mean2d[c]) { O.mean2d[c][j] = 0.f; O.mean2d[c][n + j] = 0.f; }
+    if (O.conic[c]) { O.conic[c][j] = 0.f; O.conic[c][n + j] = 0.f; O.conic[c][2 * n + j] = 0.f; }
+    if (O.opacity[c]) O.opacity[c][j] = 0.f;
+    if (O.rgb[c]) { O.rgb[c][j] = 0.f; O.rgb[c][n + j] = 0.f; O.rgb[c][2 * n + j] = 0.f; }
+}
+
+__global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
+                                                 const int64_t* __restrict__ n_in_dev, CamSet C, ProjOut O) {
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= n_in) return;
+    int64_t cnt = n_in;
+    if (n_in_dev) cnt = min(cnt, *n_in_dev);
+    int64_t i = j;
+    if (active) i = j < cnt ? int64_t(active[j]) : -1;
+    if (j >= cnt || i < 0 || i >= P.n) {
+        for (int c = 0; c < C.n; ++c) culled_out(O, c, j, n_in);
+        return;
+    }
+    const int64_t N = P.n;
+    float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
+    bool any = false;
+    for (int c = 0; c < C.n; ++c) {
+        const DevCam& K = C.cam[c];
+        const float tz = fmaf(K.R[6], mu[0], fmaf(K.R[7], mu[1], fmaf(K.R[8], mu[2], K.t[2])));
+        any |= tz > K.znear;
+    }
+    if (!any) {
+        for (int c = 0; c < C.n; ++c) culled_out(O, c, j, n_in);
+        return;
+    }
+    const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
+    const float q[4] = {P.quat[i], P.quat[N + i], P.quat[2 * N + i], P.quat[3 * N + i]};
+    float s[3], qn[4], R[9], M[9], S[6], qlen;
+    covariance(ls, q, s, qn, R, M, S, qlen);
+    const float opa = 1.f / (1.f + __expf(-P.opacity_logit[i]));
+    bool have_sh = false;
+    float sh[48];
+    for (int c = 0; c < C.n; ++c) {
+        const DevCam& K = C.cam[c];
+        Geo G;
+        geo_camera(K, mu, G);
+        if (!(G.tz > K.znear)) { culled_out(O, c, j, n_in); continue; }
+        geo_cov(K, S, G);
+        if (!(G.det > 0.f)) { culled_out(O, c, j, n_in); continue; }
+        const float idet = 1.f / G.det;
+        const float ca = G.c * idet, cb = -G.b * idet, cc = G.a * idet;
+        const float mx = fmaf(K.fx, G.txtz, K.cx), my = fmaf(K.fy, G.tytz, K.cy);
+        const float mid = 0.5f * (G.a + G.c);
+        const float lam = mid + sqrtf(fmaxf(0.f, mid * mid - G.det));
+        const float rf = fminf(ceilf(3.f * sqrtf(lam)), 1073741824.f);
+        const int64_t r = int64_t(rf);
+        const int64_t xi = int64_t(floorf(fminf(fmaxf(mx, -1073741824.f), 1073741824.f)));
+        const int64_t yi = int64_t(floorf(fminf(fmaxf(my, -1073741824.f), 1073741824.f)));
+        const int64_t x0 = min<int64_t>(max<int64_t>(floordiv16(xi - r), 0), K.TX);
+        const int64_t x1 = min<int64_t>(max<int64_t>(floordiv16(xi + r) + 1, 0), K.TX);
+        const int64_t y0 = min<int64_t>(max<int64_t>(floordiv16(yi - r), 0), K.TY);
+        const int64_t y1 = min<int64_t>(max<int64_t>(floordiv16(yi + r) + 1, 0), K.TY);
+        const int64_t touched = (x1 - x0) * (y1 - y0);
+        if (touched <= 0 || !(rf > 0.f)) { culled_out(O, c, j, n_in); continue; }
+        if (!have_sh) {
+#pragma unroll
+            for (int k = 0; k < 48; ++k) sh[k] = P.sh[int64_t(k) * N + i];
+            have_sh = true;
+        }
+        float vx = mu[0] - K.campos[0], vy = mu[1] - K.campos[1], vz = mu[2] - K.campos[2];
+        const float il = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
+        float Y[16];
+        sh_basis(vx * il, vy * il, vz * il, Y);
+        float rgb[3];
+        uint8_t cbits = 0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc = fmaf(sh[k * 3 + ch], Y[k], acc);
+            acc += 0.5f;
+            if (acc < 0.f) { cbits |= uint8_t(1u << ch); acc = 0.f; }
+            rgb[ch] = acc;
+        }
+        float4* rp = reinterpret_cast<float4*>(O.rec[c] + j * kRec);
+        rp[0] = make_float4(mx, my, ca, cb);
+        rp[1] = make_float4(cc, opa, rgb[0], rgb[1]);
+        rp[2] = make_float4(rgb[2], G.tz, 0.f, 0.f);
+        O.depth[c][j] = G.tz;
+        O.radius[c][j] = int32_t(r);
+        O.tiles[c][j] = uint32_t(touched);
+        O.clamp[c][j] = cbits;
+        if (O.mean2d[c]) { O.mean2d[c][j] = mx; O.mean2d[c][n_in + j] = my; }
+        if (O.conic[c]) { O.conic[c][j] = ca; O.conic[c][n_in + j] = cb; O.conic[c][2 * n_in + j] = cc; }
+        if (O.opacity[c]) O.opacity[c][j] = opa;
+        if (O.rgb[c]) { O.rgb[c][j] = rgb[0]; O.rgb[c][n_in + j] = rgb[1]; O.rgb[c][2 * n_in + j] = rgb[2]; }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: screen-space partials d2 = (d mean2d x, y, d conic a, b, c,
+// d opacity, d rgb r, g, b) of every camera -> parameter gradients.
+// ---------------------------------------------------------------------------
+struct BwdIn {
+    const float* d2[GS_MAX_CAMS];       // [9][n_in]
+    const int32_t* radius[GS_MAX_CAMS];
+    const uint8_t* clamp[GS_MAX_CAMS];
+};
+
+struct GradOut {
+    float* mean;
+    float* log_scale;
+    float* quat;
+    float* opacity_logit;
+    float* sh;
+};
+
+__global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
+                                                     const int64_t* __restrict__ n_in_dev, CamSet C, BwdIn B,
+                                                     GradOut GO) {
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= n_in) return;
+    int64_t cnt = n_in;
+    if (n_in_dev) cnt = min(cnt, *n_in_dev);
+    if (j >= cnt) return;
+    bool any = false;
+    for (int c = 0; c < C.n; ++c) any |= B.radius[c][j] > 0;
+    if (!any) return;
+    const int64_t i = active ? int64_t(active[j]) : j;
+    if (i < 0 || i >= P.n) return;
+    const int64_t N = P.n;
+    const float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
+    const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
+    const float q[4] = {P.quat[i], P.quat[N + i], P.quat[2 * N + i], P.quat[3 * N + i]};
+    float s[3], qn[4], R[9], M[9], S[6], qlen;
+    covariance(ls, q, s, qn, R, M, S, qlen);
+    const float opa = 1.f / (1.f + __expf(-P.opacity_logit[i]));
+    float sh[48];
+#pragma unroll
+    for (int k = 0; k < 48; ++k) sh[k] = P.sh[int64_t(k) * N + i];
+
+    float dmu[3] = {0.f, 0.f, 0.f};
+    float dS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric: 00 01 02 11 12 22
+    float dlogit = 0.f;
+    float dsh[48];
+#pragma unroll
+    for (int k = 0; k < 48; ++k) dsh[k] = 0.f;
+
+    for (int c = 0; c < C.n; ++c) {
+        if (B.radius[c][j] <= 0) continue;
+        const DevCam& K = C.cam[c];
+        const float* d2 = B.d2[c];
+        const float dmx = d2[j], dmy = d2[n_in + j];
+        const float dca = d2[2 * n_in + j], dcb = d2[3 * n_in + j], dcc = d2[4 * n_in + j];
+        const float dop = d2[5 * n_in + j];
+        float drgb[3] = {d2[6 * n_in + j], d2[7 * n_in + j], d2[8 * n_in + j]};
+        const uint8_t cb = B.clamp[c][j];
+        Geo G;
+        geo_camera(K, mu, G);
+        geo_cov(K, S, G);
+        // opacity
+        dlogit += dop * opa * (1.f - opa);
+        // conic = (c, -b, a) / det  ->  d(a, b, c) of the screen covariance
+        const float A = G.a, Bv = G.b, Cv = G.c;
+        const float id2 = 1.f / (G.det * G.det);
+        const float dA = (-Cv * Cv * dca + Bv * Cv * dcb - Bv * Bv * dcc) * id2;
+        const float dB = (2.f * Bv * Cv * dca - (A * Cv + Bv * Bv) * dcb + 2.f * A * Bv * dcc) * id2;
+        const float dC = (-Bv * Bv * dca + A * Bv * dcb - A * A * dcc) * id2;
+        // Sigma2D = T Sigma T^T with symmetric upstream Gs = [[dA, dB/2], [dB/2, dC]]
+        float dT0[3], dT1[3];
+        for (int k = 0; k < 3; ++k) {
+            dT0[k] = 2.f * dA * G.U0[k] + dB * G.U1[k];
+            dT1[k] = dB * G.U0[k] + 2.f * dC * G.U1[k];
+        }
+        const float hB = 0.5f * dB;
+        // dSigma = T^T Gs T
+        {
+            const float* t0 = G.T0;
+            const float* t1 = G.T1;
+            auto ent = [&](int k, int l) {
+                return dA * t0[k] * t0[l] + hB * (t0[k] * t1[l] + t1[k] * t0[l]) + dC * t1[k] * t1[l];
+            };
+            dS[0] += ent(0, 0); dS[1] += ent(0, 1); dS[2] += ent(0, 2);
+            dS[3] += ent(1, 1); dS[4] += ent(1, 2); dS[5] += ent(2, 2);
+        }
+        // T = J W: dJ = dT W^T on the non-zero entries of J
+        const float dJ00 = dT0[0] * K.R[0] + dT0[1] * K.R[1] + dT0[2] * K.R[2];
+        const float dJ02 = dT0[0] * K.R[6] + dT0[1] * K.R[7] + dT0[2] * K.R[8];
+        const float dJ11 = dT1[0] * K.R[3] + dT1[1] * K.R[4] + dT1[2] * K.R[5];
+        const float dJ12 = dT1[0] * K.R[6] + dT1[1] * K.R[7] + dT1[2] * K.R[8];
+        const float rz = G.rz, rz2 = rz * rz, rz3 = rz2 * rz;
+        const float txc = G.ux * G.tz, tyc = G.uy * G.tz;
+        float dtx = 0.f, dty = 0.f;
+        float dtz = -K.fx * rz2 * dJ00 - K.fy * rz2 * dJ11 + 2.f * K.fx * txc * rz3 * dJ02 +
+                    2.f * K.fy * tyc * rz3 * dJ12;
+        const float gtxc = -K.fx * rz2 * dJ02, gtyc = -K.fy * rz2 * dJ12;
+        if (G.txtz >= -K.limx && G.txtz <= K.limx) dtx += gtxc; else dtz += G.ux * gtxc;
+        if (G.tytz >= -K.limy && G.tytz <= K.limy) dty += gtyc; else dtz += G.uy * gtyc;
+        // mean2d = (fx tx / tz + cx, fy ty / tz + cy)
+        dtx += dmx * K.fx * rz;
+        dty += dmy * K.fy * rz;
+        dtz -= (dmx * K.fx * G.tx + dmy * K.fy * G.ty) * rz2;
+        // t = W mu + t_cw
+        dmu[0] += K.R[0] * dtx + K.R[3] * dty + K.R[6] * dtz;
+        dmu[1] += K.R[1] * dtx + K.R[4] * dty + K.R[7] * dtz;
+        dmu[2] += K.R[2] * dtx + K.R[5] * dty + K.R[8] * dtz;
+        // colour
+        const float vx = mu[0] - K.campos[0], vy = mu[1] - K.campos[1], vz = mu[2] - K.campos[2];
+        const float len = sqrtf(vx * vx + vy * vy + vz * vz);
+        const float il = 1.f / len;
+        const float x = vx * il, y = vy * il, z = vz * il;
+        float Y[16];
+        sh_basis(x, y, z, Y);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+            if (cb & (1u << ch)) drgb[ch] = 0.f;
+        float wsum[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            dsh[k * 3 + 0] += drgb[0] * Y[k];
+            dsh[k * 3 + 1] += drgb[1] * Y[k];
+            dsh[k * 3 + 2] += drgb[2] * Y[k];
+            wsum[k] = drgb[0] * sh[k * 3 + 0] + drgb[1] * sh[k * 3 + 1] + drgb[2] * sh[k * 3 + 2];
+        }
+        float gd[3];
+        sh_basis_grad(x, y, z, wsum, gd);
+        const float dot = gd[0] * x + gd[1] * y + gd[2] * z;
+        dmu[0] += (gd[0] - dot * x) * il;
+        dmu[1] += (gd[1] - dot * y) * il;
+        dmu[2] += (gd[2] - dot * z) * il;
+    }
+    // Sigma = M M^T: dM = 2 dSigma_sym M
+    const float D[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+    float dM[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            dM[r * 3 + c] = 2.f * (D[r * 3 + 0] * M[0 * 3 + c] + D[r * 3 + 1] * M[1 * 3 + c] + D[r * 3 + 2] * M[2 * 3 + c]);
+    // M = R diag(s)
+    float dls[3], dR[9];
+    for (int c = 0; c < 3; ++c) {
+        const float ds = dM[c] * R[c] + dM[3 + c] * R[3 + c] + dM[6 + c] * R[6 + c];
+        dls[c] = ds * s[c];
+    }
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) dR[r * 3 + c] = dM[r * 3 + c] * s[c];
+    const float w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+    float dq[4];
+    dq[0] = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                   2.f * x * dR[8]);
+    dq[2] = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                   2.f * y * dR[8]);
+    dq[3] = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] + x * dR[6] +
+                   y * dR[7]);
+    const float qd = dq[0] * qn[0] + dq[1] * qn[1] + dq[2] * qn[2] + dq[3] * qn[3];
+    const float iq = 1.f / qlen;
+    for (int k = 0; k < 4; ++k) GO.quat[int64_t(k) * N + i] += (dq[k] - qd * qn[k]) * iq;
+    for (int k = 0; k < 3; ++k) {
+        GO.mean[int64_t(k) * N + i] += dmu[k];
+        GO.log_scale[int64_t(k) * N + i] += dls[k];
+    }
+    GO.opacity_logit[i] += dlogit;
+#pragma unroll
+    for (int k = 0; k < 48; ++k) GO.sh[int64_t(k) * N + i] += dsh[k];
+}
+
+int fill_camset(const gs_camera* cams, int n_cams, CamSet& C) {
+    int64_t tt = 0;
+    int rc = validate_cams(cams, n_cams, GS_MAX_CAMS, &tt);
+    if (rc) return rc;
+    memset(&C, 0, sizeof(C));
+    C.n = n_cams;
+    uint32_t off = 0;
+    for (int c = 0; c < n_cams; ++c) {
+        C.cam[c] = make_devcam(cams[c], off);
+        off += uint32_t(gs_num_tiles(cams[c].width, cams[c].height));
+    }
+    return GS_OK;
+}
+
+static int scene_ok(const gs_scene* s) {
+    if (!s || s->n < 0 || s->n >= (int64_t(1) << 31))
+        return fail(GS_ERR_INVALID_ARG, "scene: null or n out of range");
+    if (s->n > 0 && (!s->mean || !s->log_scale || !s->quat || !s->opacity_logit || !s->sh))
+        return fail(GS_ERR_INVALID_ARG, "scene: null parameter array");
+    return GS_OK;
+}
+
+int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
+                       const gs_camera* cams, int n_cams, const float* const* d2, const gs_projected* proj,
+                       const gs_grads* grads, hipStream_t stream) {
+    CamSet C;
+    int rc = fill_camset(cams, n_cams, C);
+    if (rc) return rc;
+    SceneP P{scene->mean, scene->log_scale, scene->quat, scene->opacity_logit, scene->sh, scene->n};
+    BwdIn B;
+    memset(&B, 0, sizeof(B));
+    for (int c = 0; c < n_cams; ++c) {
+        B.d2[c] = d2[c];
+        B.radius[c] = proj[c].radius;
+        B.clamp[c] = proj[c].clamp_bits;
+    }
+    GradOut G{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh};
+    if (n_in == 0) return GS_OK;
+    hipLaunchKernelGGL(k_project_bwd, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx,
+                       n_in, n_in_dev, C, B, G);
+    return check_launch("project backward");
+}
+
+int check_scene(const gs_scene* s) { return scene_ok(s); }
+
+}  // namespace gsmi
+
+using namespace gsmi;
+
+extern "C" int gs_project(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
+                          const gs_camera* cams, int n_cams, const gs_projected* out, hipStream_t stream) {
+    int rc = scene_ok(scene);
+    if (rc) return rc;
+    if (n_in < 0 || n_in >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_project: n_in out of range");
+    if (!active_idx && n_in > scene->n) return fail(GS_ERR_INVALID_ARG, "gs_project: n_in > n without active_idx");
+    if (!out) return fail(GS_ERR_INVALID_ARG, "gs_project: null output");
+    CamSet C;
+    rc = fill_camset(cams, n_cams, C);
+    if (rc) return rc;
+    ProjOut O;
+    memset(&O, 0, sizeof(O));
+    for (int c = 0; c < n_cams; ++c) {
+        const gs_projected& p = out[c];
+        if (n_in > 0 && (!p.rec || !p.depth || !p.radius || !p.tiles_touched || !p.clamp_bits))
+            return fail(GS_ERR_INVALID_ARG, "gs_project: camera %d: null required output", c);
+        if (!aligned(p.rec, 16)) return fail(GS_ERR_INVALID_ARG, "gs_project: rec must be 16-byte aligned");
+        O.rec[c] = p.rec; O.depth[c] = p.depth; O.radius[c] = p.radius; O.tiles[c] = p.tiles_touched;
+        O.clamp[c] = p.clamp_bits; O.mean2d[c] = p.mean2d; O.conic[c] = p.conic; O.opacity[c] = p.opacity;
+        O.rgb[c] = p.rgb;
+    }
+    if (n_in == 0) return GS_OK;
+    SceneP P{scene->mean, scene->log_scale, scene->quat, scene->opacity_logit, scene->sh, scene->n};
+    hipLaunchKernelGGL(k_project, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx, n_in,
+                       n_in_dev, C, O);
+    return check_launch("gs_project");
+}

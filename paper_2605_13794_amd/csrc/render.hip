@@ -1,0 +1,460 @@
+// Front-to-back compositing of 16x16 tiles, its backward, and the
+// colour-less instrumented blend of the importance sweep.
+//
+// One wavefront (64 lanes) owns one tile; lane l covers column l % 16 and
+// rows l / 16 + {0, 4, 8, 12}, so each record staged in LDS is read once per
+// lane and evaluated for four pixels that share dx.  Records are gathered
+// from the packed per-Gaussian render record in batches of 64.
+#include "common.h"
+
+namespace gsmi {
+
+struct RenderCams {
+    const float* rec[GS_MAX_CAMS];
+    uint32_t tile_off[GS_MAX_CAMS + 1];
+    int32_t TX[GS_MAX_CAMS];
+    int32_t W[GS_MAX_CAMS];
+    int32_t H[GS_MAX_CAMS];
+    int n_cams;
+};
+
+struct TileCtx {
+    int c;
+    int px, py0;
+    float fxp;
+    float fyp[4];
+    bool valid[4];
+    uint32_t start, end;
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const RenderCams& A, const uint32_t* ranges, uint32_t n_tiles) {
+    TileCtx t;
+    const uint32_t tile = blockIdx.x;
+    int c = 0;
+    while (c + 1 < A.n_cams && tile >= A.tile_off[c + 1]) ++c;
+    t.c = c;
+    const uint32_t lt = tile - A.tile_off[c];
+    const int TX = A.TX[c];
+    const int tx = int(lt % uint32_t(TX)), ty = int(lt / uint32_t(TX));
+    const int lane = threadIdx.x;
+    t.px = tx * GS_TILE + (lane & 15);
+    t.py0 = ty * GS_TILE + (lane >> 4);
+    t.fxp = float(t.px) + 0.5f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        t.fyp[r] = float(t.py0 + 4 * r) + 0.5f;
+        t.valid[r] = t.px < A.W[c] && (t.py0 + 4 * r) < A.H[c];
+    }
+    t.start = ranges[tile];
+    t.end = ranges[n_tiles + tile];
+    return t;
+}
+
+// Staged record: (mx, my, na, nb), (nc, o, r, g), (b), with the conic scaled
+// so that the log2-domain exponent is na dx^2 + nb dx dy + nc dy^2.
+__device__ __forceinline__ void stage_record(const float* rec, uint32_t j, float4& A, float4& B, float& C) {
+    const float4* p = reinterpret_cast<const float4*>(rec) + size_t(j) * 3;
+    const float4 q0 = p[0];
+    const float4 q1 = p[1];
+    const float q2 = p[2].x;
+    A = make_float4(q0.x, q0.y, -0.5f * kLog2e * q0.z, -kLog2e * q0.w);
+    B = make_float4(-0.5f * kLog2e * q1.x, q1.y, q1.z, q1.w);
+    C = q2;
+}
+
+// alpha of a staged record at one pixel; identical in forward and backward.
+__device__ __forceinline__ float eval_alpha(float ebase, float eb, float nc, float o, float dy, float& G,
+                                            bool& pass) {
+    const float e2 = gauss_e2(ebase, eb, nc, dy);
+    G = fast_exp2(e2);
+    const float alpha = fminf(kAlphaMax, o * G);
+    pass = (e2 <= 0.f) && (alpha >= kAlphaMin);
+    return alpha;
+}
+
+struct FwdOut {
+    float* rgb[GS_MAX_CAMS];
+    float* T[GS_MAX_CAMS];
+    uint32_t* last[GS_MAX_CAMS];
+    float bg[3];
+};
+
+__global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ ranges, uint32_t n_tiles, FwdOut O) {
+    __shared__ float4 sA[64];
+    __shared__ float4 sB[64];
+    __shared__ float sC[64];
+    const TileCtx t = tile_ctx(A, ranges, n_tiles);
+    const float* rec = A.rec[t.c];
+    float T[4], C0[4], C1[4], C2[4];
+    uint32_t last[4];
+    bool done[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        T[r] = 1.f; C0[r] = C1[r] = C2[r] = 0.f; last[r] = 0; done[r] = !t.valid[r];
+    }
+    const int lane = threadIdx.x;
+    for (uint32_t b0 = t.start; b0 < t.end; b0 += 64) {
+        if (__all(done[0] && done[1] && done[2] && done[3])) break;
+        const uint32_t nb = min(64u, t.end - b0);
+        __syncthreads();
+        if (uint32_t(lane) < nb) {
+            float4 a, b;
+            float cc;
+            stage_record(rec, vals[b0 + lane], a, b, cc);
+            sA[lane] = a; sB[lane] = b; sC[lane] = cc;
+        }
+        __syncthreads();
+        for (uint32_t i = 0; i < nb; ++i) {
+            const float4 a = sA[i];
+            const float4 b = sB[i];
+            const float cb = sC[i];
+            const float dx = a.x - t.fxp;
+            const float ebase = a.z * dx * dx;
+            const float eb = a.w * dx;
+            const uint32_t pos = b0 - t.start + i + 1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float G;
+                bool pass;
+                const float alpha = eval_alpha(ebase, eb, b.x, b.y, a.y - t.fyp[r], G, pass);
+                const float Tn = T[r] * (1.f - alpha);
+                const bool ok = pass && !done[r];
+                const bool stop = ok && (Tn < kTMin);
+                const bool comp = ok && !stop;
+                const float wgt = comp ? alpha * T[r] : 0.f;
+                C0[r] = fmaf(wgt, b.z, C0[r]);
+                C1[r] = fmaf(wgt, b.w, C1[r]);
+                C2[r] = fmaf(wgt, cb, C2[r]);
+                T[r] = comp ? Tn : T[r];
+                last[r] = comp ? pos : last[r];
+                done[r] = done[r] || stop;
+            }
+            if (__all(done[0] && done[1] && done[2] && done[3])) break;
+        }
+    }
+    const int W = A.W[t.c], H = A.H[t.c];
+    const size_t plane = size_t(W) * H;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (!t.valid[r]) continue;
+        const size_t p = size_t(t.py0 + 4 * r) * W + t.px;
+        O.rgb[t.c][p] = fmaf(T[r], O.bg[0], C0[r]);
+        O.rgb[t.c][plane + p] = fmaf(T[r], O.bg[1], C1[r]);
+        O.rgb[t.c][2 * plane + p] = fmaf(T[r], O.bg[2], C2[r]);
+        O.T[t.c][p] = T[r];
+        O.last[t.c][p] = last[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward of the compositing
+// ---------------------------------------------------------------------------
+struct BwdImg {
+    const float* T[GS_MAX_CAMS];
+    const uint32_t* last[GS_MAX_CAMS];
+    const float* grad[GS_MAX_CAMS];
+    float* d2[GS_MAX_CAMS];  // [9][n_in]
+    int64_t n_in;
+    float bg[3];
+};
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, uint32_t(__shfl_xor(int(v), o, 64)));
+    return v;
+}
+
+__global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ ranges, uint32_t n_tiles, BwdImg I) {
+    __shared__ float4 sA[64];
+    __shared__ float4 sB[64];
+    __shared__ float4 sR[64];  // (raw conic a, b, c, b channel)
+    __shared__ uint32_t sJ[64];
+    const TileCtx t = tile_ctx(A, ranges, n_tiles);
+    const float* rec = A.rec[t.c];
+    const int W = A.W[t.c];
+    const size_t plane = size_t(W) * A.H[t.c];
+    float T[4], acc0[4], acc1[4], acc2[4], g0[4], g1[4], g2[4], gbg[4];
+    uint32_t lst[4];
+    uint32_t lmax = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const size_t p = size_t(t.py0 + 4 * r) * W + t.px;
+        const bool v = t.valid[r];
+        T[r] = v ? I.T[t.c][p] : 1.f;
+        lst[r] = v ? I.last[t.c][p] : 0u;
+        g0[r] = v ? I.grad[t.c][p] : 0.f;
+        g1[r] = v ? I.grad[t.c][plane + p] : 0.f;
+        g2[r] = v ? I.grad[t.c][2 * plane + p] : 0.f;
+        gbg[r] = T[r] * (g0[r] * I.bg[0] + g1[r] * I.bg[1] + g2[r] * I.bg[2]);
+        acc0[r] = acc1[r] = acc2[r] = 0.f;
+        lmax = max(lmax, lst[r]);
+    }
+    lmax = wave_max_u32(lmax);
+    const int lane = threadIdx.x;
+    const int64_t n_in = I.n_in;
+    float* d2 = I.d2[t.c];
+    const uint32_t stop_at = t.start + min(lmax, t.end - t.start);
+    for (uint32_t b_end = stop_at; b_end > t.start;) {
+        const uint32_t nb = min(64u, b_end - t.start);
+        const uint32_t b0 = b_end - nb;
+        __syncthreads();
+        if (uint32_t(lane) < nb) {
+            const uint32_t j = vals[b0 + lane];
+            float4 a, b;
+            float cc;
+            stage_record(rec, j, a, b, cc);
+            const float4 q0 = reinterpret_cast<const float4*>(rec)[size_t(j) * 3];
+            const float qc = reinterpret_cast<const float4*>(rec)[size_t(j) * 3 + 1].x;
+            sA[lane] = a; sB[lane] = b;
+            sR[lane] = make_float4(q0.z, q0.w, qc, cc);
+            sJ[lane] = j;
+        }
+        __syncthreads();
+        for (int i = int(nb) - 1; i >= 0; --i) {
+            const float4 a = sA[i];
+            const float4 b = sB[i];
+            const float4 rw = sR[i];
+            const uint32_t pos = b0 - t.start + uint32_t(i);  // 0-based list position
+            const float dx = a.x - t.fxp;
+            const float ebase = a.z * dx * dx;
+            const float eb = a.w * dx;
+            const float o = b.y;
+            float s_mx = 0.f, s_my = 0.f, s_ca = 0.f, s_cb = 0.f, s_cc = 0.f, s_op = 0.f;
+            float s_r = 0.f, s_g = 0.f, s_b = 0.f;
+            bool any = false;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float dy = a.y - t.fyp[r];
+                float G;
+                bool pass;
+                const float alpha = eval_alpha(ebase, eb, b.x, o, dy, G, pass);
+                const bool ok = pass && (pos < lst[r]);
+                any |= ok;
+                const float om = 1.f - alpha;
+                const float rom = fast_rcp(om);
+                const float Tk = ok ? T[r] * rom : T[r];
+                const float dLda = g0[r] * (Tk * (b.z - acc0[r])) + g1[r] * (Tk * (b.w - acc1[r])) +
+                                   g2[r] * (Tk * (rw.w - acc2[r])) - gbg[r] * rom;
+                const float aT = alpha * Tk;
+                if (ok) {
+                    acc0[r] = fmaf(alpha, b.z, om * acc0[r]);
+                    acc1[r] = fmaf(alpha, b.w, om * acc1[r]);
+                    acc2[r] = fmaf(alpha, rw.w, om * acc2[r]);
+                    T[r] = Tk;
+                    s_r = fmaf(g0[r], aT, s_r);
+                    s_g = fmaf(g1[r], aT, s_g);
+                    s_b = fmaf(g2[r], aT, s_b);
+                    if (o * G <= kAlphaMax) {
+                        s_op = fmaf(dLda, G, s_op);
+                        const float dP = dLda * o * G;
+                        s_mx -= dP * (rw.x * dx + rw.y * dy);
+                        s_my -= dP * (rw.y * dx + rw.z * dy);
+                        s_ca -= 0.5f * dP * dx * dx;
+                        s_cb -= dP * dx * dy;
+                        s_cc -= 0.5f * dP * dy * dy;
+                    }
+                }
+            }
+            if (__any(any)) {
+                s_mx = wave_sum_to_last(s_mx);
+                s_my = wave_sum_to_last(s_my);
+                s_ca = wave_sum_to_last(s_ca);
+                s_cb = wave_sum_to_last(s_cb);
+                s_cc = wave_sum_to_last(s_cc);
+                s_op = wave_sum_to_last(s_op);
+                s_r = wave_sum_to_last(s_r);
+                s_g = wave_sum_to_last(s_g);
+                s_b = wave_sum_to_last(s_b);
+                if (lane == 63) {
+                    const int64_t j = sJ[i];
+                    atomicAdd(d2 + j, s_mx);
+                    atomicAdd(d2 + n_in + j, s_my);
+                    atomicAdd(d2 + 2 * n_in + j, s_ca);
+                    atomicAdd(d2 + 3 * n_in + j, s_cb);
+                    atomicAdd(d2 + 4 * n_in + j, s_cc);
+                    atomicAdd(d2 + 5 * n_in + j, s_op);
+                    atomicAdd(d2 + 6 * n_in + j, s_r);
+                    atomicAdd(d2 + 7 * n_in + j, s_g);
+                    atomicAdd(d2 + 8 * n_in + j, s_b);
+                }
+            }
+        }
+        b_end = b0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Importance: colour-less blend, w_j += alpha T and a_j += 1 per composited
+// (pixel, Gaussian), reduced per (Gaussian, tile) across the wavefront.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uint32_t* __restrict__ vals,
+                                                         const uint32_t* __restrict__ ranges, uint32_t n_tiles,
+                                                         float* __restrict__ w, uint32_t* __restrict__ a_cnt) {
+    __shared__ float4 sA[64];
+    __shared__ float2 sB[64];
+    __shared__ uint32_t sJ[64];
+    const TileCtx t = tile_ctx(A, ranges, n_tiles);
+    const float* rec = A.rec[t.c];
+    float T[4];
+    bool done[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { T[r] = 1.f; done[r] = !t.valid[r]; }
+    const int lane = threadIdx.x;
+    for (uint32_t b0 = t.start; b0 < t.end; b0 += 64) {
+        if (__all(done[0] && done[1] && done[2] && done[3])) break;
+        const uint32_t nb = min(64u, t.end - b0);
+        __syncthreads();
+        if (uint32_t(lane) < nb) {
+            const uint32_t j = vals[b0 + lane];
+            float4 a, b;
+            float cc;
+            stage_record(rec, j, a, b, cc);
+            sA[lane] = a;
+            sB[lane] = make_float2(b.x, b.y);
+            sJ[lane] = j;
+        }
+        __syncthreads();
+        for (uint32_t i = 0; i < nb; ++i) {
+            const float4 a = sA[i];
+            const float2 b = sB[i];
+            const float dx = a.x - t.fxp;
+            const float ebase = a.z * dx * dx;
+            const float eb = a.w * dx;
+            float sw = 0.f;
+            uint32_t sn = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float G;
+                bool pass;
+                const float alpha = eval_alpha(ebase, eb, b.x, b.y, a.y - t.fyp[r], G, pass);
+                const float Tn = T[r] * (1.f - alpha);
+                const bool ok = pass && !done[r];
+                const bool stop = ok && (Tn < kTMin);
+                const bool comp = ok && !stop;
+                sw += comp ? alpha * T[r] : 0.f;
+                sn += comp ? 1u : 0u;
+                T[r] = comp ? Tn : T[r];
+                done[r] = done[r] || stop;
+            }
+            if (__any(sn > 0)) {
+                sw = wave_sum_to_last(sw);
+                sn = wave_sum_to_last_u32(sn);
+                if (lane == 63) {
+                    atomicAdd(w + sJ[i], sw);
+                    atomicAdd(a_cnt + sJ[i], sn);
+                }
+            }
+            if (__all(done[0] && done[1] && done[2] && done[3])) break;
+        }
+    }
+}
+
+int fill_render_cams(const gs_projected* proj, const gs_camera* cams, int n_cams, RenderCams& A,
+                     int64_t* total_tiles) {
+    int rc = validate_cams(cams, n_cams, GS_MAX_CAMS, total_tiles);
+    if (rc) return rc;
+    memset(&A, 0, sizeof(A));
+    A.n_cams = n_cams;
+    uint32_t off = 0;
+    for (int c = 0; c < n_cams; ++c) {
+        if (!proj[c].rec || !aligned(proj[c].rec, 16))
+            return fail(GS_ERR_INVALID_ARG, "camera %d: null or misaligned render record", c);
+        A.rec[c] = proj[c].rec;
+        A.tile_off[c] = off;
+        A.TX[c] = int32_t(tiles_x(cams[c].width));
+        A.W[c] = cams[c].width;
+        A.H[c] = cams[c].height;
+        off += uint32_t(gs_num_tiles(cams[c].width, cams[c].height));
+    }
+    A.tile_off[n_cams] = off;
+    return GS_OK;
+}
+
+int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, const uint32_t* vals,
+                            const uint32_t* ranges, float* w, uint32_t* a, hipStream_t stream) {
+    RenderCams A;
+    int64_t tt = 0;
+    int rc = fill_render_cams(proj, cam, 1, A, &tt);
+    if (rc) return rc;
+    if (tt == 0) return GS_OK;
+    hipLaunchKernelGGL(k_importance_blend, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, ranges, uint32_t(tt), w,
+                       a);
+    return check_launch("importance blend");
+}
+
+int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
+                       const gs_camera* cams, int n_cams, const float* const* d2, const gs_projected* proj,
+                       const gs_grads* grads, hipStream_t stream);
+int check_scene(const gs_scene* s);
+
+}  // namespace gsmi
+
+using namespace gsmi;
+
+size_t ws_render_bwd(int64_t n, int n_cams) {
+    Carve cv(nullptr);
+    cv.take<float>(size_t(9) * size_t(n > 0 ? n : 1) * size_t(n_cams));
+    return cv.used();
+}
+
+extern "C" int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, int n_cams, const uint32_t* vals,
+                             const uint32_t* tile_ranges, const float* bg, float* const* out_rgb,
+                             float* const* out_T, uint32_t* const* out_last, hipStream_t stream) {
+    if (!proj || !tile_ranges || !bg || !out_rgb || !out_T || !out_last)
+        return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: null argument");
+    RenderCams A;
+    int64_t tt = 0;
+    int rc = fill_render_cams(proj, cams, n_cams, A, &tt);
+    if (rc) return rc;
+    FwdOut O;
+    memset(&O, 0, sizeof(O));
+    for (int c = 0; c < n_cams; ++c) {
+        if (!out_rgb[c] || !out_T[c] || !out_last[c]) return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: null image");
+        O.rgb[c] = out_rgb[c]; O.T[c] = out_T[c]; O.last[c] = out_last[c];
+    }
+    O.bg[0] = bg[0]; O.bg[1] = bg[1]; O.bg[2] = bg[2];
+    if (tt == 0) return GS_OK;
+    hipLaunchKernelGGL(k_render_fwd, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges, uint32_t(tt), O);
+    return check_launch("gs_render_fwd");
+}
+
+extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
+                             const gs_projected* proj, const gs_camera* cams, int n_cams, const uint32_t* vals,
+                             const uint32_t* tile_ranges, const float* bg, float* const* out_T,
+                             uint32_t* const* out_last, float* const* grad_rgb, gs_grads* grads, float* grads2d,
+                             void* ws, size_t ws_bytes, hipStream_t stream) {
+    int rc = check_scene(scene);
+    if (rc) return rc;
+    if (!proj || !tile_ranges || !bg || !out_T || !out_last || !grad_rgb || !grads)
+        return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: null argument");
+    if (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity_logit || !grads->sh)
+        return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: null gradient array");
+    if (n_in < 0 || n_in >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: n_in out of range");
+    if (!active_idx && n_in > scene->n) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: n_in > n without active_idx");
+    RenderCams A;
+    int64_t tt = 0;
+    rc = fill_render_cams(proj, cams, n_cams, A, &tt);
+    if (rc) return rc;
+    const size_t need = ws_render_bwd(n_in, n_cams);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_render_bwd: workspace needs %zu bytes (256-aligned)", need);
+    BwdImg I;
+    memset(&I, 0, sizeof(I));
+    const float* d2c[GS_MAX_CAMS];
+    float* base = static_cast<float*>(ws);
+    for (int c = 0; c < n_cams; ++c) {
+        if (!out_T[c] || !out_last[c] || !grad_rgb[c]) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: null image");
+        I.T[c] = out_T[c]; I.last[c] = out_last[c]; I.grad[c] = grad_rgb[c];
+        I.d2[c] = (c == 0 && grads2d) ? grads2d : base + size_t(9) * size_t(n_in) * c;
+        d2c[c] = I.d2[c];
+        if ((rc = fill_u32(I.d2[c], 0u, size_t(9) * size_t(n_in), stream))) return rc;
+    }
+    I.n_in = n_in;
+    I.bg[0] = bg[0]; I.bg[1] = bg[1]; I.bg[2] = bg[2];
+    if (tt > 0 && n_in > 0)
+        hipLaunchKernelGGL(k_render_bwd, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges, uint32_t(tt), I);
+    if ((rc = check_launch("gs_render_bwd blend"))) return rc;
+    return launch_project_bwd(scene, active_idx, n_in, n_in_dev, cams, n_cams, d2c, proj, grads, stream);
+}

@@ -1,0 +1,534 @@
+// View-level gate + active-set compaction, importance aggregation with the
+// per-view top-mass cut, and the score mask.  Order statistics use an
+// MSD radix select over float bits (4 passes of 8 bits, histograms in LDS);
+// ties at the threshold are resolved by index with a block-count scan.
+#include "common.h"
+
+namespace gsmi {
+
+constexpr int kBlk = 256;  // elements per block, one per thread
+
+// Exclusive scan of per-block counts in place (one workgroup); writes the
+// total to *total if non-null.
+__global__ __launch_bounds__(256) void k_scan_counts(uint32_t* __restrict__ cnt, int64_t nb,
+                                                     uint64_t* __restrict__ total) {
+    __shared__ uint32_t w4[4];
+    __shared__ uint64_t carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        const int64_t b = b0 + threadIdx.x;
+        const uint32_t v = b < nb ? cnt[b] : 0u;
+        // wave inclusive scan
+        uint32_t inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane_id() >= uint32_t(o)) inc += t;
+        }
+        const int w = threadIdx.x / 64;
+        if (lane_id() == 63) w4[w] = inc;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int k = 0; k < 4; ++k) {
+            if (k < w) before += w4[k];
+            tot += w4[k];
+        }
+        const uint64_t carry = carry_s;
+        if (b < nb) cnt[b] = uint32_t(carry + before + inc - v);
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) *total = carry_s;
+}
+
+// Block-local exclusive rank of `pred` over the block's 256 elements, plus the
+// block's count.
+__device__ __forceinline__ uint32_t block_rank(bool pred, uint32_t* w4, uint32_t* count) {
+    const uint64_t m = ballot(pred);
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0) w4[w] = popc64(m);
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int k = 0; k < 4; ++k) {
+        if (k < w) before += w4[k];
+        tot += w4[k];
+    }
+    __syncthreads();
+    *count = tot;
+    return before + popc64(m & lanemask_lt());
+}
+
+// Writes the wavefront's 64 predicate bits as two 32-bit words.
+__device__ __forceinline__ void store_bits(uint32_t* words, int64_t n, int64_t elem0_of_wave, uint64_t m) {
+    const int64_t w0 = elem0_of_wave / 32;
+    const int64_t nw = (n + 31) / 32;
+    if (lane_id() == 0 && w0 < nw) words[w0] = uint32_t(m);
+    if (lane_id() == 1 && w0 + 1 < nw) words[w0 + 1] = uint32_t(m >> 32);
+}
+
+__device__ __forceinline__ bool bit_of(const uint32_t* words, int64_t i) {
+    return (words[i >> 5] >> (i & 31)) & 1u;
+}
+
+// ---------------------------------------------------------------------------
+// LOD gate and active set
+// ---------------------------------------------------------------------------
+struct GateArgs {
+    const float* mean;
+    const float* log_scale;
+    const uint8_t* lod;
+    const uint32_t* keep;
+    int64_t n;
+    int mode;
+    float campos[3];
+    float d0, inv_log2f, fx_k, rmin, fallback;
+    int l_max;
+};
+
+__global__ __launch_bounds__(256) void k_gate(GateArgs G, uint32_t* __restrict__ gate_words,
+                                              uint32_t* __restrict__ c_gate, uint32_t* __restrict__ c_act,
+                                              uint32_t* __restrict__ c_keep) {
+    __shared__ uint32_t w4[4];
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    const bool in = i < G.n;
+    bool gate = in;
+    if (in && G.mode != GS_LOD_NONE) {
+        const float dx = G.mean[i] - G.campos[0];
+        const float dy = G.mean[G.n + i] - G.campos[1];
+        const float dz = G.mean[2 * G.n + i] - G.campos[2];
+        const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+        if (G.mode == GS_LOD_LEVEL) {
+            int lv;
+            if (d < 1e-6f) {
+                lv = G.l_max;
+            } else {
+                const float x = floorf(log2f(G.d0 / d) * G.inv_log2f + 0.5f);
+                lv = int(fminf(fmaxf(x, 0.f), float(G.l_max)));
+            }
+            gate = int(G.lod[i]) <= lv;
+        } else {
+            const float smax = fmaxf(fmaxf(G.log_scale[i], G.log_scale[G.n + i]), G.log_scale[2 * G.n + i]);
+            gate = G.fx_k * __expf(smax) >= G.rmin * d;
+        }
+    }
+    const bool keep = in && (G.keep ? bit_of(G.keep, i) : true);
+    const uint64_t mg = ballot(gate);
+    store_bits(gate_words, G.n, int64_t(blockIdx.x) * kBlk + (threadIdx.x / 64) * 64, mg);
+    uint32_t ng, na, nk;
+    block_rank(gate, w4, &ng);
+    block_rank(gate && keep, w4, &na);
+    block_rank(keep, w4, &nk);
+    if (threadIdx.x == 0) {
+        c_gate[blockIdx.x] = ng;
+        c_act[blockIdx.x] = na;
+        c_keep[blockIdx.x] = nk;
+    }
+}
+
+// Fallback decision and block offsets of the active set (one workgroup).
+__global__ __launch_bounds__(256) void k_gate_decide(uint32_t* __restrict__ c_gate, uint32_t* __restrict__ c_act,
+                                                     uint32_t* __restrict__ c_keep, int64_t nb, int64_t n,
+                                                     float fallback, uint32_t* __restrict__ flag) {
+    __shared__ uint64_t red[256];
+    uint64_t s = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) s += c_gate[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const bool fb = n > 0 && double(red[0]) >= double(fallback) * double(n);
+    if (threadIdx.x == 0) *flag = fb ? 1u : 0u;
+    if (fb)
+        for (int64_t b = threadIdx.x; b < nb; b += 256) c_act[b] = c_keep[b];
+}
+
+__global__ __launch_bounds__(256) void k_compact(GateArgs G, const uint32_t* __restrict__ gate_words,
+                                                 const uint32_t* __restrict__ offs, const uint32_t* __restrict__ flag,
+                                                 int32_t* __restrict__ out) {
+    __shared__ uint32_t w4[4];
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    const bool in = i < G.n;
+    const bool fb = *flag != 0u;
+    const bool gate = in && (fb || bit_of(gate_words, i));
+    const bool keep = in && (G.keep ? bit_of(G.keep, i) : true);
+    const bool act = gate && keep;
+    uint32_t tot;
+    const uint32_t r = block_rank(act, w4, &tot);
+    if (act) out[offs[blockIdx.x] + r] = int32_t(i);
+}
+
+__global__ void k_store_count(const uint64_t* __restrict__ total, int64_t* __restrict__ dst) {
+    if (threadIdx.x == 0) *dst = int64_t(*total);
+}
+
+// ---------------------------------------------------------------------------
+// Radix select
+// ---------------------------------------------------------------------------
+struct SelState {
+    uint32_t prefix;       // selected high bits so far
+    uint32_t done_bits;    // number of bits fixed
+    uint32_t need_eq;      // ties at the threshold to take (by ascending index)
+    uint32_t cnt_eq;       // elements equal to the threshold
+    uint32_t active;       // 0: nothing selected, 1: threshold valid
+    uint32_t take_all_eq;  // 1 if every tie is taken
+    uint32_t pad[2];
+    double target;         // mass mode: frac * W
+    double mass_above;     // mass mode: sum of values above the prefix range
+    uint64_t k_rem;        // count mode: rank still to place inside the prefix range
+};
+
+// mode 0: mass (w > 0, descending), mode 1: count (ascending).
+__global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ v, int64_t n, int shift,
+                                                  const SelState* __restrict__ st, uint32_t* __restrict__ hcnt,
+                                                  double* __restrict__ hmass, double* __restrict__ total, int mode) {
+    __shared__ uint32_t lc[256];
+    __shared__ double lm[256];
+    lc[threadIdx.x] = 0;
+    lm[threadIdx.x] = 0.0;
+    __syncthreads();
+    const uint32_t pre = st->prefix;
+    const uint32_t hi_mask = shift >= 24 ? 0u : (0xffffffffu << (shift + 8));
+    double tsum = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        const float x = v[i];
+        if (mode == 0 && !(x > 0.f)) continue;
+        if (mode == 0 && shift == 24) tsum += double(x);
+        const uint32_t b = __float_as_uint(x);
+        if ((b & hi_mask) != (pre & hi_mask)) continue;
+        const uint32_t d = (b >> shift) & 255u;
+        atomicAdd(&lc[d], 1u);
+        if (mode == 0) atomicAdd(&lm[d], double(x));
+    }
+    __syncthreads();
+    if (lc[threadIdx.x]) {
+        atomicAdd(&hcnt[threadIdx.x], lc[threadIdx.x]);
+        if (mode == 0) atomicAdd(&hmass[threadIdx.x], lm[threadIdx.x]);
+    }
+    if (mode == 0 && shift == 24) {
+        // block sum of tsum
+        __shared__ double red[256];
+        red[threadIdx.x] = tsum;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(total, red[0]);
+    }
+}
+
+// One thread: choose the digit bin, update the state, clear the histogram.
+__global__ void k_sel_pick(SelState* __restrict__ st, uint32_t* __restrict__ hcnt, double* __restrict__ hmass,
+                           const double* __restrict__ total, int shift, int mode, float frac) {
+    if (threadIdx.x != 0) return;
+    SelState s = *st;
+    if (shift == 24) {
+        if (mode == 0) {
+            s.target = double(frac) * (*total);
+            s.mass_above = 0.0;
+            s.active = (*total > 0.0) ? 1u : 0u;
+        }
+    }
+    if (s.active) {
+        int chosen = -1;
+        if (mode == 0) {
+            double acc = s.mass_above;
+            int lowest = -1;
+            for (int b = 255; b >= 0; --b) {
+                if (hcnt[b] == 0) continue;
+                lowest = b;
+                if (acc + hmass[b] >= s.target) { chosen = b; break; }
+                acc += hmass[b];
+            }
+            if (chosen < 0) {  // rounding left the total just short: take the smallest bin
+                chosen = lowest;
+                acc = s.mass_above;
+                for (int b = 255; b > chosen; --b) acc += hmass[b];
+            }
+            if (chosen < 0) {
+                s.active = 0;
+            } else {
+                s.mass_above = acc;
+            }
+        } else {
+            uint64_t acc = 0;
+            for (int b = 0; b < 256; ++b) {
+                if (acc + hcnt[b] >= s.k_rem) { chosen = b; break; }
+                acc += hcnt[b];
+            }
+            if (chosen < 0) s.active = 0;
+            else s.k_rem -= acc;
+        }
+        if (chosen >= 0) {
+            s.prefix |= uint32_t(chosen) << shift;
+            s.done_bits += 8;
+            if (shift == 0) {
+                s.cnt_eq = hcnt[chosen];
+                if (mode == 0) {
+                    const double tau = double(__uint_as_float(s.prefix));
+                    double need = ceil((s.target - s.mass_above) / tau);
+                    if (need < 1.0) need = 1.0;
+                    if (need > double(s.cnt_eq)) need = double(s.cnt_eq);
+                    s.need_eq = uint32_t(need);
+                } else {
+                    s.need_eq = uint32_t(s.k_rem);
+                }
+                s.take_all_eq = s.need_eq >= s.cnt_eq ? 1u : 0u;
+            }
+        }
+    }
+    for (int b = 0; b < 256; ++b) { hcnt[b] = 0; hmass[b] = 0.0; }
+    *st = s;
+}
+
+__global__ void k_sel_init(SelState* __restrict__ st, uint32_t* __restrict__ hcnt, double* __restrict__ hmass,
+                           double* __restrict__ total, int mode, uint64_t k) {
+    if (threadIdx.x == 0) {
+        SelState s;
+        memset(&s, 0, sizeof(s));
+        s.active = mode == 1 ? (k > 0 ? 1u : 0u) : 0u;
+        s.k_rem = k;
+        *st = s;
+        *total = 0.0;
+    }
+    hcnt[threadIdx.x] = 0;
+    hmass[threadIdx.x] = 0.0;
+}
+
+// Per-block count of elements equal to the threshold (only when ranks matter).
+__global__ __launch_bounds__(256) void k_eq_count(const float* __restrict__ v, int64_t n,
+                                                  const SelState* __restrict__ st, uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t w4[4];
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    const bool need = st->active && !st->take_all_eq;
+    const bool eq = need && i < n && __float_as_uint(v[i]) == st->prefix;
+    uint32_t tot;
+    block_rank(eq, w4, &tot);
+    if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+}
+
+__device__ __forceinline__ bool selected(float x, uint32_t rank_eq, const SelState& s, int mode) {
+    if (!s.active) return false;
+    const uint32_t b = __float_as_uint(x);
+    if (mode == 0) {
+        if (!(x > 0.f)) return false;
+        if (b > s.prefix) return true;  // positive floats order as their bits
+    } else {
+        if (b < s.prefix) return true;
+    }
+    if (b != s.prefix) return false;
+    return s.take_all_eq || rank_eq < s.need_eq;
+}
+
+// ---------------------------------------------------------------------------
+// Importance fold
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_importance_fold(const float* __restrict__ w, const uint32_t* __restrict__ a,
+                                                         const int32_t* __restrict__ radius, int64_t n,
+                                                         const SelState* __restrict__ stp,
+                                                         const uint32_t* __restrict__ eq_off, float eps,
+                                                         float* __restrict__ score, uint32_t* __restrict__ c_rad,
+                                                         uint32_t* __restrict__ c_vis, uint32_t* __restrict__ cull) {
+    __shared__ uint32_t w4[4];
+    const SelState s = *stp;
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    const bool in = i < n;
+    const float wi = in ? w[i] : 0.f;
+    const bool eq = in && s.active && !s.take_all_eq && __float_as_uint(wi) == s.prefix;
+    uint32_t tot;
+    const uint32_t r = block_rank(eq, w4, &tot);
+    const uint32_t rank_eq = eq ? eq_off[blockIdx.x] + r : 0u;
+    const bool vis = in && selected(wi, rank_eq, s, 0);
+    const uint64_t m = ballot(in && !vis);
+    store_bits(cull, n, int64_t(blockIdx.x) * kBlk + (threadIdx.x / 64) * 64, m);
+    if (!in) return;
+    const uint32_t ai = a[i];
+    if (ai > 0) score[i] += wi / (float(ai) + eps);
+    if (radius[i] > 0) c_rad[i] += 1u;
+    if (vis) c_vis[i] += 1u;
+}
+
+__global__ __launch_bounds__(256) void k_keep_bits(const float* __restrict__ score, int64_t n,
+                                                   const SelState* __restrict__ stp, const uint32_t* __restrict__ eq_off,
+                                                   uint32_t* __restrict__ keep) {
+    __shared__ uint32_t w4[4];
+    const SelState s = *stp;
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    const bool in = i < n;
+    const float x = in ? score[i] : 0.f;
+    const bool eq = in && s.active && !s.take_all_eq && __float_as_uint(x) == s.prefix;
+    uint32_t tot;
+    const uint32_t r = block_rank(eq, w4, &tot);
+    const uint32_t rank_eq = eq ? eq_off[blockIdx.x] + r : 0u;
+    const bool drop = in && selected(x, rank_eq, s, 1);
+    const uint64_t m = ballot(in && !drop);
+    store_bits(keep, n, int64_t(blockIdx.x) * kBlk + (threadIdx.x / 64) * 64, m);
+}
+
+struct SelWs {
+    SelState* st;
+    uint32_t* hcnt;
+    double* hmass;
+    double* total;
+    uint32_t* eq_cnt;
+    uint64_t* tot64;
+    size_t bytes;
+};
+
+static SelWs carve_sel(Carve& cv, int64_t n) {
+    SelWs s;
+    const int64_t nb = (n + kBlk - 1) / kBlk + 1;
+    s.st = cv.take<SelState>(1);
+    s.hcnt = cv.take<uint32_t>(256);
+    s.hmass = cv.take<double>(256);
+    s.total = cv.take<double>(1);
+    s.eq_cnt = cv.take<uint32_t>(size_t(nb));
+    s.tot64 = cv.take<uint64_t>(1);
+    s.bytes = 0;
+    return s;
+}
+
+static int run_select(const float* v, int64_t n, int mode, float frac, uint64_t k, const SelWs& W, hipStream_t s) {
+    const int64_t nb = (n + kBlk - 1) / kBlk;
+    const int hb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096)));
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, W.st, W.hcnt, W.hmass, W.total, mode, k);
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_sel_hist, dim3(hb), dim3(256), 0, s, v, n, shift, W.st, W.hcnt, W.hmass, W.total, mode);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, s, W.st, W.hcnt, W.hmass, W.total, shift, mode, frac);
+    }
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_eq_count, dim3(unsigned(nb)), dim3(256), 0, s, v, n, W.st, W.eq_cnt);
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, s, W.eq_cnt, nb, W.tot64);
+    }
+    return check_launch("radix select");
+}
+
+}  // namespace gsmi
+
+using namespace gsmi;
+
+size_t ws_lod_mask(int64_t n) {
+    Carve cv(nullptr);
+    const int64_t nb = (n + kBlk - 1) / kBlk + 1;
+    cv.take<uint32_t>(size_t((n + 31) / 32 + 2));
+    cv.take<uint32_t>(size_t(nb));
+    cv.take<uint32_t>(size_t(nb));
+    cv.take<uint32_t>(size_t(nb));
+    cv.take<uint32_t>(4);
+    cv.take<uint64_t>(1);
+    return cv.used();
+}
+
+size_t ws_importance(int64_t n) {
+    Carve cv(nullptr);
+    carve_sel(cv, n);
+    return cv.used();
+}
+
+size_t ws_score_keep(int64_t n) { return ws_importance(n); }
+
+namespace gsmi {
+int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, const uint32_t* vals,
+                            const uint32_t* ranges, float* w, uint32_t* a, hipStream_t stream);
+}
+
+extern "C" int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
+                           const uint32_t* keep_bits, int32_t* active_idx, int64_t* n_active_dev, void* ws,
+                           size_t ws_bytes, hipStream_t stream) {
+    if (!scene || !cam || !params || !active_idx || !n_active_dev)
+        return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: null argument");
+    if (scene->n < 0 || scene->n >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: bad n");
+    const int64_t n = scene->n;
+    if (params->mode != GS_LOD_NONE && params->mode != GS_LOD_LEVEL && params->mode != GS_LOD_RADIUS)
+        return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: unknown mode %d", params->mode);
+    if (n > 0 && params->mode != GS_LOD_NONE && !scene->mean)
+        return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: null means");
+    if (n > 0 && params->mode == GS_LOD_LEVEL && (!scene->lod || !(params->d0 > 0.f) || !(params->f > 1.f)))
+        return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: level mode needs lod labels, d0 > 0 and f > 1");
+    if (n > 0 && params->mode == GS_LOD_RADIUS && !scene->log_scale)
+        return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: radius mode needs log-scales");
+    const size_t need = ws_lod_mask(n);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_lod_mask: workspace needs %zu bytes (256-aligned)", need);
+    DevCam dc = make_devcam(*cam, 0);
+    GateArgs G;
+    memset(&G, 0, sizeof(G));
+    G.mean = scene->mean; G.log_scale = scene->log_scale; G.lod = scene->lod; G.keep = keep_bits; G.n = n;
+    G.mode = params->mode;
+    for (int k = 0; k < 3; ++k) G.campos[k] = dc.campos[k];
+    G.d0 = params->d0;
+    G.inv_log2f = params->mode == GS_LOD_LEVEL ? float(1.0 / std::log2(double(params->f))) : 1.f;
+    G.fx_k = cam->fx * params->radius_sigma_k;
+    G.rmin = params->radius_min_px;
+    G.fallback = params->fallback_ratio;
+    G.l_max = params->l_max;
+    Carve cv(ws);
+    const int64_t nb = (n + kBlk - 1) / kBlk;
+    uint32_t* words = cv.take<uint32_t>(size_t((n + 31) / 32 + 2));
+    uint32_t* c_gate = cv.take<uint32_t>(size_t(nb + 1));
+    uint32_t* c_act = cv.take<uint32_t>(size_t(nb + 1));
+    uint32_t* c_keep = cv.take<uint32_t>(size_t(nb + 1));
+    uint32_t* flag = cv.take<uint32_t>(4);
+    uint64_t* tot = cv.take<uint64_t>(1);
+    if (n == 0) {
+        int rc = fill_u32(tot, 0u, 2, stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_store_count, dim3(1), dim3(64), 0, stream, tot, n_active_dev);
+        return check_launch("gs_lod_mask");
+    }
+    hipLaunchKernelGGL(k_gate, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_gate, c_act, c_keep);
+    hipLaunchKernelGGL(k_gate_decide, dim3(1), dim3(256), 0, stream, c_gate, c_act, c_keep, nb, n,
+                       params->fallback_ratio, flag);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, c_act, nb, tot);
+    hipLaunchKernelGGL(k_compact, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_act, flag, active_idx);
+    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(64), 0, stream, tot, n_active_dev);
+    return check_launch("gs_lod_mask");
+}
+
+extern "C" int gs_importance(const gs_projected* proj, const gs_camera* cam, int64_t n, const uint32_t* vals,
+                             const uint32_t* tile_ranges, float mass_frac, float eps, float* w, uint32_t* a,
+                             float* score, uint32_t* c_rad, uint32_t* c_vis, uint32_t* cull_row, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+    if (!proj || !cam || !tile_ranges || !w || !a || !score || !c_rad || !c_vis || !cull_row)
+        return fail(GS_ERR_INVALID_ARG, "gs_importance: null argument");
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_importance: bad n");
+    if (!(mass_frac > 0.f) || mass_frac > 1.f) return fail(GS_ERR_INVALID_ARG, "gs_importance: mass_frac in (0, 1]");
+    if (!proj->radius) return fail(GS_ERR_INVALID_ARG, "gs_importance: null radius");
+    const size_t need = ws_importance(n);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_importance: workspace needs %zu bytes (256-aligned)", need);
+    if (n == 0) return GS_OK;
+    int rc;
+    if ((rc = fill_u32(w, 0u, size_t(n), stream))) return rc;
+    if ((rc = fill_u32(a, 0u, size_t(n), stream))) return rc;
+    if ((rc = launch_importance_blend(proj, cam, vals, tile_ranges, w, a, stream))) return rc;
+    Carve cv(ws);
+    SelWs S = carve_sel(cv, n);
+    if ((rc = run_select(w, n, 0, mass_frac, 0, S, stream))) return rc;
+    const int64_t nb = (n + kBlk - 1) / kBlk;
+    hipLaunchKernelGGL(k_importance_fold, dim3(unsigned(nb)), dim3(256), 0, stream, w, a, proj->radius, n, S.st,
+                       S.eq_cnt, eps, score, c_rad, c_vis, cull_row);
+    return check_launch("gs_importance");
+}
+
+extern "C" int gs_score_keep_bits(const float* score, int64_t n, int64_t n_drop, uint32_t* keep_bits, void* ws,
+                                  size_t ws_bytes, hipStream_t stream) {
+    if (!score || !keep_bits) return fail(GS_ERR_INVALID_ARG, "gs_score_keep_bits: null argument");
+    if (n < 0 || n >= (int64_t(1) << 31) || n_drop < 0 || n_drop > n)
+        return fail(GS_ERR_INVALID_ARG, "gs_score_keep_bits: need 0 <= n_drop <= n < 2^31");
+    const size_t need = ws_score_keep(n);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_score_keep_bits: workspace needs %zu bytes (256-aligned)", need);
+    if (n == 0) return GS_OK;
+    Carve cv(ws);
+    SelWs S = carve_sel(cv, n);
+    int rc;
+    if ((rc = run_select(score, n, 1, 0.f, uint64_t(n_drop), S, stream))) return rc;
+    const int64_t nb = (n + kBlk - 1) / kBlk;
+    hipLaunchKernelGGL(k_keep_bits, dim3(unsigned(nb)), dim3(256), 0, stream, score, n, S.st, S.eq_cnt, keep_bits);
+    return check_launch("gs_score_keep_bits");
+}

@@ -1,0 +1,256 @@
+"""ctypes binding of libgsmi.so: one Python function per C entry point, with
+the same name, doing argument marshalling only (torch tensors supply device
+pointers and the HIP stream).  Every step of the work runs in the library's
+HIP kernels; there is no fallback path, and loading fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsmi.so")
+
+GS_OK = 0
+GS_ERR_INVALID_ARG = -1
+GS_ERR_CAPACITY = -2
+GS_ERR_WORKSPACE = -3
+GS_ERR_HIP = -4
+
+GS_LOD_NONE, GS_LOD_LEVEL, GS_LOD_RADIUS = 0, 1, 2
+GS_OP_LOD_MASK, GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_IMPORTANCE, GS_OP_SCORE_KEEP, GS_OP_L1_LOSS = range(6)
+GS_MAX_CAMS = 8
+GS_MAX_PAIRS = 1 << 30
+REC_FLOATS = 12
+
+EXPORTED = ("gs_workspace_size", "gs_last_error", "gs_num_tiles", "gs_lod_mask", "gs_project", "gs_bin_sort",
+            "gs_render_fwd", "gs_render_bwd", "gs_importance", "gs_score_keep_bits", "gs_l1_loss",
+            "gs_adam_step")
+
+c_int, c_i32, c_i64, c_f, c_p, c_sz = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                                       ctypes.c_void_p, ctypes.c_size_t)
+
+
+class GsCamera(ctypes.Structure):
+    _fields_ = [("width", c_i32), ("height", c_i32), ("fx", c_f), ("fy", c_f), ("cx", c_f), ("cy", c_f),
+                ("R", c_f * 9), ("t", c_f * 3), ("znear", c_f)]
+
+
+class GsScene(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("mean", c_p), ("log_scale", c_p), ("quat", c_p), ("opacity_logit", c_p),
+                ("sh", c_p), ("lod", c_p)]
+
+
+class GsProjected(ctypes.Structure):
+    _fields_ = [("rec", c_p), ("depth", c_p), ("radius", c_p), ("tiles_touched", c_p), ("clamp_bits", c_p),
+                ("mean2d", c_p), ("conic", c_p), ("opacity", c_p), ("rgb", c_p)]
+
+
+class GsGrads(ctypes.Structure):
+    _fields_ = [("mean", c_p), ("log_scale", c_p), ("quat", c_p), ("opacity_logit", c_p), ("sh", c_p)]
+
+
+class GsLodParams(ctypes.Structure):
+    _fields_ = [("mode", c_i32), ("d0", c_f), ("f", c_f), ("l_max", c_i32), ("fallback_ratio", c_f),
+                ("radius_min_px", c_f), ("radius_sigma_k", c_f)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_13794_amd.build` "
+                               "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = c_p
+        L.gs_workspace_size.restype = c_sz
+        L.gs_workspace_size.argtypes = [c_int, c_i64, c_i64, c_i64, c_int]
+        L.gs_last_error.restype = ctypes.c_char_p
+        L.gs_last_error.argtypes = []
+        L.gs_num_tiles.restype = c_i64
+        L.gs_num_tiles.argtypes = [c_i32, c_i32]
+        L.gs_lod_mask.argtypes = [P, P, P, P, P, P, P, c_sz, P]
+        L.gs_project.argtypes = [P, P, c_i64, P, P, c_int, P, P]
+        L.gs_bin_sort.argtypes = [P, P, c_int, c_i64, P, P, c_i64, P, P, P, c_sz, P]
+        L.gs_render_fwd.argtypes = [P, P, c_int, P, P, P, P, P, P, P]
+        L.gs_render_bwd.argtypes = [P, P, c_i64, P, P, P, c_int, P, P, P, P, P, P, P, P, P, c_sz, P]
+        L.gs_importance.argtypes = [P, P, c_i64, P, P, c_f, c_f, P, P, P, P, P, P, P, c_sz, P]
+        L.gs_score_keep_bits.argtypes = [P, c_i64, c_i64, P, P, c_sz, P]
+        L.gs_l1_loss.argtypes = [P, P, c_i64, P, P, P, c_sz, P]
+        L.gs_adam_step.argtypes = [P, P, P, P, P, c_int, P, c_f, c_f, c_f, c_int, P]
+        for name in EXPORTED:
+            if name not in ("gs_workspace_size", "gs_last_error", "gs_num_tiles"):
+                getattr(L, name).restype = c_int
+        _lib = L
+    return _lib
+
+
+class GsmiError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+def _check(rc: int, fn: str):
+    if rc != GS_OK:
+        raise GsmiError(rc, fn, lib().gs_last_error().decode(errors="replace"))
+
+
+def ptr(t) -> int | None:
+    """Device pointer of a tensor (None for None)."""
+    if t is None:
+        return None
+    assert isinstance(t, torch.Tensor)
+    return t.data_ptr()
+
+
+def stream_handle(stream=None) -> int | None:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ref(x):
+    return ctypes.byref(x) if x is not None else None
+
+
+def camera(cam) -> GsCamera:
+    """gs_camera from an object with width, height, fx, fy, cx, cy, R, t, znear."""
+    c = GsCamera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = [float(v) for v in __import__("numpy").asarray(cam.R, dtype="float64").reshape(-1)]
+    t = [float(v) for v in __import__("numpy").asarray(cam.t, dtype="float64").reshape(-1)]
+    c.R[:] = R
+    c.t[:] = t
+    c.znear = float(getattr(cam, "znear", 0.2))
+    return c
+
+
+def camera_array(cams):
+    arr = (GsCamera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = camera(c)
+    return arr
+
+
+def scene(mean, log_scale, quat, opacity_logit, sh, lod=None) -> GsScene:
+    s = GsScene()
+    s.n = int(mean.shape[-1])
+    s.mean, s.log_scale, s.quat = ptr(mean), ptr(log_scale), ptr(quat)
+    s.opacity_logit, s.sh, s.lod = ptr(opacity_logit), ptr(sh), ptr(lod)
+    return s
+
+
+def projected(rec, depth, radius, tiles_touched, clamp_bits, mean2d=None, conic=None, opacity=None,
+              rgb=None) -> GsProjected:
+    p = GsProjected()
+    p.rec, p.depth, p.radius, p.tiles_touched, p.clamp_bits = (ptr(rec), ptr(depth), ptr(radius),
+                                                               ptr(tiles_touched), ptr(clamp_bits))
+    p.mean2d, p.conic, p.opacity, p.rgb = ptr(mean2d), ptr(conic), ptr(opacity), ptr(rgb)
+    return p
+
+
+def grads(mean, log_scale, quat, opacity_logit, sh) -> GsGrads:
+    g = GsGrads()
+    g.mean, g.log_scale, g.quat, g.opacity_logit, g.sh = (ptr(mean), ptr(log_scale), ptr(quat),
+                                                          ptr(opacity_logit), ptr(sh))
+    return g
+
+
+def lod_params(mode=GS_LOD_NONE, d0=1.0, f=2.0, l_max=0, fallback_ratio=0.95, radius_min_px=0.5,
+               radius_sigma_k=1.0) -> GsLodParams:
+    p = GsLodParams()
+    p.mode, p.d0, p.f, p.l_max = int(mode), float(d0), float(f), int(l_max)
+    p.fallback_ratio, p.radius_min_px, p.radius_sigma_k = float(fallback_ratio), float(radius_min_px), float(
+        radius_sigma_k)
+    return p
+
+
+def _ptr_array(tensors, ctype=c_p):
+    arr = (ctype * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = ptr(t)
+    return arr
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+def gs_workspace_size(op, n=0, n_pairs=0, n_tiles=0, n_cams=1) -> int:
+    return int(lib().gs_workspace_size(op, n, n_pairs, n_tiles, n_cams))
+
+
+def gs_num_tiles(width, height) -> int:
+    return int(lib().gs_num_tiles(width, height))
+
+
+def gs_last_error() -> str:
+    return lib().gs_last_error().decode(errors="replace")
+
+
+def gs_lod_mask(scn: GsScene, cam: GsCamera, params: GsLodParams, keep_bits, active_idx, n_active_dev, ws,
+                stream=None):
+    _check(lib().gs_lod_mask(ctypes.byref(scn), ctypes.byref(cam), ctypes.byref(params), ptr(keep_bits),
+                             ptr(active_idx), ptr(n_active_dev), ptr(ws), ws.numel() if ws is not None else 0,
+                             stream_handle(stream)), "gs_lod_mask")
+
+
+def gs_project(scn: GsScene, active_idx, n_in, n_in_dev, cams, outs, stream=None):
+    outs_arr = (GsProjected * len(outs))(*outs)
+    _check(lib().gs_project(ctypes.byref(scn), ptr(active_idx), int(n_in), ptr(n_in_dev), cams, len(cams),
+                            outs_arr, stream_handle(stream)), "gs_project")
+
+
+def gs_bin_sort(projs, cams, n_in, keys, vals, capacity, tile_ranges, n_pairs_dev, ws, stream=None):
+    parr = (GsProjected * len(projs))(*projs)
+    _check(lib().gs_bin_sort(parr, cams, len(cams), int(n_in), ptr(keys), ptr(vals), int(capacity),
+                             ptr(tile_ranges), ptr(n_pairs_dev), ptr(ws), ws.numel(), stream_handle(stream)),
+           "gs_bin_sort")
+
+
+def gs_render_fwd(projs, cams, vals, tile_ranges, bg, out_rgb, out_T, out_last, stream=None):
+    parr = (GsProjected * len(projs))(*projs)
+    bgv = (c_f * 3)(*[float(x) for x in bg])
+    _check(lib().gs_render_fwd(parr, cams, len(cams), ptr(vals), ptr(tile_ranges), bgv, _ptr_array(out_rgb),
+                               _ptr_array(out_T), _ptr_array(out_last), stream_handle(stream)), "gs_render_fwd")
+
+
+def gs_render_bwd(scn: GsScene, active_idx, n_in, n_in_dev, projs, cams, vals, tile_ranges, bg, out_T, out_last,
+                  grad_rgb, grd: GsGrads, grads2d, ws, stream=None):
+    parr = (GsProjected * len(projs))(*projs)
+    bgv = (c_f * 3)(*[float(x) for x in bg])
+    _check(lib().gs_render_bwd(ctypes.byref(scn), ptr(active_idx), int(n_in), ptr(n_in_dev), parr, cams, len(cams),
+                               ptr(vals), ptr(tile_ranges), bgv, _ptr_array(out_T), _ptr_array(out_last),
+                               _ptr_array(grad_rgb), ctypes.byref(grd), ptr(grads2d), ptr(ws), ws.numel(),
+                               stream_handle(stream)), "gs_render_bwd")
+
+
+def gs_importance(proj: GsProjected, cam: GsCamera, n, vals, tile_ranges, mass_frac, eps, w, a, score, c_rad, c_vis,
+                  cull_row, ws, stream=None):
+    _check(lib().gs_importance(ctypes.byref(proj), ctypes.byref(cam), int(n), ptr(vals), ptr(tile_ranges),
+                               float(mass_frac), float(eps), ptr(w), ptr(a), ptr(score), ptr(c_rad), ptr(c_vis),
+                               ptr(cull_row), ptr(ws), ws.numel(), stream_handle(stream)), "gs_importance")
+
+
+def gs_score_keep_bits(score, n, n_drop, keep_bits, ws, stream=None):
+    _check(lib().gs_score_keep_bits(ptr(score), int(n), int(n_drop), ptr(keep_bits), ptr(ws), ws.numel(),
+                                    stream_handle(stream)), "gs_score_keep_bits")
+
+
+def gs_l1_loss(rgb, target, n_vals, loss_dev, grad, ws, stream=None):
+    _check(lib().gs_l1_loss(ptr(rgb), ptr(target), int(n_vals), ptr(loss_dev), ptr(grad), ptr(ws), ws.numel(),
+                            stream_handle(stream)), "gs_l1_loss")
+
+
+def gs_adam_step(params, grads_, m, v, lrs, b1, b2, eps, step, stream=None):
+    n = len(params)
+    counts = (c_i64 * n)(*[int(p.numel()) for p in params])
+    lr = (c_f * n)(*[float(x) for x in lrs])
+    _check(lib().gs_adam_step(_ptr_array(params), _ptr_array(grads_), _ptr_array(m), _ptr_array(v), counts, n, lr,
+                              float(b1), float(b2), float(eps), int(step), stream_handle(stream)), "gs_adam_step")

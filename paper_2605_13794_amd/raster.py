@@ -1,0 +1,226 @@
+"""Device buffers and the forward/backward pipeline of the rasterizer over the
+C ABI, plus the torch.autograd.Function that exposes it to training code.
+
+PyTorch only allocates device memory and provides the stream; every step
+(gate, projection, binning, sort, compositing, loss, backward, Adam) is a
+library call.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import gsmi as G
+from . import scenes as S
+
+F32, I32, U8 = torch.float32, torch.int32, torch.uint8
+
+
+class Workspace:
+    """Grow-only device scratch buffer (256-byte aligned)."""
+
+    def __init__(self, device):
+        self.device = device
+        self.buf = torch.empty(0, dtype=U8, device=device)
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        nbytes = max(int(nbytes), 256)
+        if self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes + 4096, dtype=U8, device=self.device)
+            if self.buf.data_ptr() % 256:
+                raise RuntimeError("workspace allocation is not 256-byte aligned")
+        return self.buf
+
+
+class DeviceScene:
+    """Scene parameters resident in device memory (SoA, float32)."""
+
+    def __init__(self, scene: S.Scene, device="cuda", requires_grad=False):
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+        self.mean = t(scene.mean)
+        self.log_scale = t(scene.log_scale)
+        self.quat = t(scene.quat)
+        self.opacity_logit = t(scene.opacity_logit)
+        self.sh = t(scene.sh)
+        self.lod = t(scene.lod)
+        self.n = scene.n
+        if requires_grad:
+            for p in self.params():
+                p.requires_grad_(True)
+
+    def params(self):
+        return [self.mean, self.log_scale, self.quat, self.opacity_logit, self.sh]
+
+    def struct(self, params=None) -> G.GsScene:
+        p = params if params is not None else self.params()
+        return G.scene(*[x.detach() for x in p], lod=self.lod)
+
+
+class ProjBuffers:
+    """Per-camera outputs of gs_project for up to n entries."""
+
+    def __init__(self, n: int, device, soa: bool = False):
+        n = max(int(n), 1)
+        self.n = n
+        self.rec = torch.empty(n * G.REC_FLOATS, dtype=F32, device=device)
+        self.depth = torch.empty(n, dtype=F32, device=device)
+        self.radius = torch.empty(n, dtype=I32, device=device)
+        self.tiles = torch.empty(n, dtype=I32, device=device)
+        self.clamp = torch.empty(n, dtype=U8, device=device)
+        self.soa = soa
+        if soa:
+            self.mean2d = torch.empty(2, n, dtype=F32, device=device)
+            self.conic = torch.empty(3, n, dtype=F32, device=device)
+            self.opacity = torch.empty(n, dtype=F32, device=device)
+            self.rgb = torch.empty(3, n, dtype=F32, device=device)
+
+    def struct(self) -> G.GsProjected:
+        if self.soa:
+            return G.projected(self.rec, self.depth, self.radius, self.tiles, self.clamp, self.mean2d, self.conic,
+                               self.opacity, self.rgb)
+        return G.projected(self.rec, self.depth, self.radius, self.tiles, self.clamp)
+
+
+@dataclasses.dataclass
+class FrameOutputs:
+    rgb: list
+    T: list
+    last: list
+
+
+class Frame:
+    """All buffers of one rasterization pass over a batch of cameras."""
+
+    def __init__(self, cams, n_max: int, device="cuda", capacity: int | None = None, soa: bool = False):
+        assert 1 <= len(cams) <= G.GS_MAX_CAMS
+        self.device = torch.device(device)
+        self.cams = list(cams)
+        self.cam_arr = G.camera_array(self.cams)
+        self.n_max = int(n_max)
+        self.proj = [ProjBuffers(n_max, self.device, soa) for _ in cams]
+        self.total_tiles = sum(G.gs_num_tiles(c.width, c.height) for c in cams)
+        self.ranges = torch.empty(2 * self.total_tiles, dtype=I32, device=self.device)
+        self.n_pairs = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.capacity = 0
+        self.keys = self.vals = None
+        self.ws_sort = Workspace(self.device)
+        self.ws_bwd = Workspace(self.device)
+        self.ws_loss = Workspace(self.device)
+        self.rgb = [torch.empty(3, c.height, c.width, dtype=F32, device=self.device) for c in cams]
+        self.T = [torch.empty(c.height, c.width, dtype=F32, device=self.device) for c in cams]
+        self.last = [torch.empty(c.height, c.width, dtype=I32, device=self.device) for c in cams]
+        self.grad_rgb = [torch.empty_like(x) for x in self.rgb]
+        self.loss = torch.zeros(len(cams), dtype=F32, device=self.device)
+        self.ensure_capacity(capacity if capacity is not None else max(1024, 4 * self.n_max * len(cams)))
+        self.n_in = self.n_max
+        self.active = None
+        self.n_in_dev = None
+
+    def ensure_capacity(self, cap: int):
+        cap = int(min(max(cap, 1), G.GS_MAX_PAIRS - 1))
+        if cap <= self.capacity:
+            return
+        self.capacity = cap
+        self.keys = torch.empty(cap, dtype=torch.int64, device=self.device)
+        self.vals = torch.empty(cap, dtype=I32, device=self.device)
+
+    def proj_structs(self):
+        return [p.struct() for p in self.proj]
+
+    # -- forward -----------------------------------------------------------
+    def project(self, scn: G.GsScene, active=None, n_in=None, n_in_dev=None, stream=None):
+        self.n_in = self.n_max if n_in is None else int(n_in)
+        self.active, self.n_in_dev = active, n_in_dev
+        G.gs_project(scn, active, self.n_in, n_in_dev, self.cam_arr, self.proj_structs(), stream)
+
+    def bin_sort(self, check: bool = True, stream=None):
+        ws = self.ws_sort.get(G.gs_workspace_size(G.GS_OP_BIN_SORT, self.n_in, self.capacity, self.total_tiles,
+                                                  len(self.cams)))
+        G.gs_bin_sort(self.proj_structs(), self.cam_arr, self.n_in, self.keys, self.vals, self.capacity,
+                      self.ranges, self.n_pairs, ws, stream)
+        if check:
+            K = int(self.n_pairs.item())
+            if K > self.capacity:
+                self.ensure_capacity(int(K * 1.25) + 1024)
+                return self.bin_sort(check=True, stream=stream)
+            return K
+        return None
+
+    def render_fwd(self, bg=(0.0, 0.0, 0.0), stream=None):
+        self.bg = tuple(float(x) for x in bg)
+        G.gs_render_fwd(self.proj_structs(), self.cam_arr, self.vals, self.ranges, self.bg, self.rgb, self.T,
+                        self.last, stream)
+        return FrameOutputs(self.rgb, self.T, self.last)
+
+    def forward(self, scn, active=None, n_in=None, n_in_dev=None, bg=(0.0, 0.0, 0.0), check=True, stream=None):
+        self.project(scn, active, n_in, n_in_dev, stream)
+        K = self.bin_sort(check=check, stream=stream)
+        out = self.render_fwd(bg, stream)
+        return out, K
+
+    # -- loss and backward ----------------------------------------------------
+    def l1_loss(self, targets, stream=None):
+        for c, (img, tgt) in enumerate(zip(self.rgb, targets)):
+            ws = self.ws_loss.get(G.gs_workspace_size(G.GS_OP_L1_LOSS))
+            G.gs_l1_loss(img, tgt, img.numel(), self.loss[c:c + 1], self.grad_rgb[c], ws, stream)
+        return self.loss
+
+    def backward(self, scn, grd: G.GsGrads, grad_rgb=None, grads2d=None, stream=None):
+        g = grad_rgb if grad_rgb is not None else self.grad_rgb
+        ws = self.ws_bwd.get(G.gs_workspace_size(G.GS_OP_RENDER_BWD, self.n_in, 0, 0, len(self.cams)))
+        G.gs_render_bwd(scn, self.active, self.n_in, self.n_in_dev, self.proj_structs(), self.cam_arr, self.vals,
+                        self.ranges, self.bg, self.T, self.last, g, grd, grads2d, ws, stream)
+
+
+class RasterizeFn(torch.autograd.Function):
+    """Differentiable rasterization of a batch of cameras.
+
+    forward(frame, scene, mean, log_scale, quat, opacity_logit, sh) -> images
+    [B, 3, H, W] (all cameras of the frame must share one resolution).  The
+    backward calls gs_render_bwd, which recomputes every pixel's
+    transmittance chain from the final T instead of storing it.
+    """
+
+    @staticmethod
+    def forward(ctx, frame: Frame, dscene: DeviceScene, mean, log_scale, quat, opacity_logit, sh, active=None,
+                n_in_dev=None):
+        params = [mean, log_scale, quat, opacity_logit, sh]
+        scn = G.scene(*[p.detach() for p in params], lod=dscene.lod)
+        n_in = None if active is None else int(active.numel())
+        out, _ = frame.forward(scn, active, n_in, n_in_dev)
+        ctx.frame, ctx.scn, ctx.params = frame, scn, [p.detach() for p in params]
+        return torch.stack([x.clone() for x in out.rgb])
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        frame = ctx.frame
+        gr = [torch.zeros_like(p) for p in ctx.params]
+        grad_rgb = [grad_out[c].contiguous() for c in range(len(frame.cams))]
+        frame.backward(ctx.scn, G.grads(*gr), grad_rgb=grad_rgb)
+        return (None, None, *gr, None, None)
+
+
+def rasterize(frame: Frame, dscene: DeviceScene, active=None, n_in_dev=None):
+    return RasterizeFn.apply(frame, dscene, *dscene.params(), active, n_in_dev)
+
+
+class Adam:
+    """Adam over the scene's parameter tensors through gs_adam_step."""
+
+    def __init__(self, params, lrs, b1=0.9, b2=0.999, eps=1e-15):
+        self.params = list(params)
+        self.lrs = list(lrs)
+        self.m = [torch.zeros_like(p) for p in self.params]
+        self.v = [torch.zeros_like(p) for p in self.params]
+        self.b1, self.b2, self.eps = b1, b2, eps
+        self.t = 0
+
+    def step(self, grads, stream=None):
+        self.t += 1
+        G.gs_adam_step([p.detach() for p in self.params], grads, self.m, self.v, self.lrs, self.b1, self.b2,
+                       self.eps, self.t, stream)
+
+
+DEFAULT_LRS = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)  # mean, log_scale, quat, opacity_logit, sh
