@@ -134,6 +134,15 @@ size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t n_tiles, in
 
 const char* gs_last_error(void);
 
+/* Diagnostics: while `name` is set, every launch of that kernel (one of
+ * "project", "project_bwd", "emit", "scan_reduce", "sort_hist", "sort_pass",
+ * "tile_ranges", "render_fwd", "render_bwd", "importance_blend",
+ * "importance_fold", "sel_hist", "gate", "compact", "adam") records `start`
+ * and `stop` (caller-owned HIP events) immediately around the kernel on the
+ * stream it is launched on; each launch overwrites the previous record.
+ * name = NULL or "" turns it off.  Per calling thread. */
+int gs_profile_kernel(const char* name, hipEvent_t start, hipEvent_t stop);
+
 /* Number of 16x16 tiles of a width x height image. */
 int64_t gs_num_tiles(int32_t width, int32_t height);
 
@@ -262,14 +271,16 @@ int gs_l1_loss(const float* rgb, const float* target, int64_t n_vals, float* los
 
 /*
  * Adam with bias correction (Kingma & Ba), one fused launch over n_groups
- * parameter groups (host arrays of device pointers and counts):
+ * parameter groups (host arrays of device pointers and counts); the paper's
+ * per-rank optimizer state (Sec. 3.1) implies it:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * p -= lr_k * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
- * n_groups <= 8, step >= 1.
+ * With clear_grads != 0 each gradient is reset to 0 after it is read, ready
+ * for the next accumulating gs_render_bwd.  n_groups <= 8, step >= 1.
  */
-int gs_adam_step(float* const* params, const float* const* grads, float* const* m,
+int gs_adam_step(float* const* params, float* const* grads, float* const* m,
                  float* const* v, const int64_t* counts, int n_groups, const float* lr,
-                 float b1, float b2, float eps, int step, hipStream_t stream);
+                 float b1, float b2, float eps, int step, int clear_grads, hipStream_t stream);
 
 #ifdef __cplusplus
 }

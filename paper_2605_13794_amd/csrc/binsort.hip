@@ -433,7 +433,7 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     if ((rc = fill_u32(tile_ranges, 0u, size_t(2 * total_tiles), stream))) return rc;
     const int64_t nb = (n_total + kScanItems - 1) / kScanItems;
     if (nb > 0)
-        hipLaunchKernelGGL(k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums);
+        launch("scan_reduce", k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, stream, S.block_sums, nb, n_pairs_dev, capacity,
                        S.n_sorted);
     if ((rc = check_launch("gs_bin_sort scan"))) return rc;
@@ -443,25 +443,25 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     uint32_t* vb[2] = {vals, S.vals_alt};
     int cur = (passes % 2 == 0) ? 0 : 1;
     if (nb > 0)
-        hipLaunchKernelGGL(k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
+        launch("emit", k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
                            S.n_sorted, kb[cur], vb[cur]);
     const int64_t max_parts = (capacity + kPart - 1) / kPart;
     int hist_blocks = int(std::min<int64_t>(1024, (capacity + 4095) / 4096));
     if (hist_blocks < 1) hist_blocks = 1;
-    hipLaunchKernelGGL(k_sort_hist, dim3(hist_blocks), dim3(256), 0, stream, kb[cur], S.n_sorted, passes, S.hist,
+    launch("sort_hist", k_sort_hist, dim3(hist_blocks), dim3(256), 0, stream, kb[cur], S.n_sorted, passes, S.hist,
                        S.status[0]);
     int grid = int(std::min<int64_t>(max_parts, 256 * 3));
     if (grid < 1) grid = 1;
     for (int p = 0; p < passes; ++p) {
         const int nxt = cur ^ 1;
-        hipLaunchKernelGGL(k_sort_pass, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur], kb[nxt], vb[nxt],
+        launch("sort_pass", k_sort_pass, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur], kb[nxt], vb[nxt],
                            S.n_sorted, S.hist + p * 256, S.status[p & 1],
                            (p + 1 < passes) ? S.status[(p + 1) & 1] : nullptr, S.counters + p, S.err, 8 * p);
         cur = nxt;
     }
     hipLaunchKernelGGL(k_sort_report, dim3(1), dim3(64), 0, stream, S.err, n_pairs_dev);
     if ((rc = check_launch("gs_bin_sort sort"))) return rc;
-    hipLaunchKernelGGL(k_tile_ranges, dim3(unsigned(std::min<int64_t>(4096, (capacity + 255) / 256))), dim3(256), 0,
+    launch("tile_ranges", k_tile_ranges, dim3(unsigned(std::min<int64_t>(4096, (capacity + 255) / 256))), dim3(256), 0,
                        stream, keys, S.n_sorted, uint32_t(total_tiles), tile_ranges);
     return check_launch("gs_bin_sort ranges");
 }

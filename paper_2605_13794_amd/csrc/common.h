@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -145,5 +146,18 @@ __device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
 
 // Small fill kernel launcher (graph-capture friendly, unlike memset nodes).
 int fill_u32(void* dst, uint32_t value, size_t count, hipStream_t s);
+
+// Optional timing of one named kernel with caller events (gs_profile_kernel).
+bool profile_match(const char* name, hipEvent_t* start, hipEvent_t* stop);
+
+template <typename Kernel, typename... Args>
+inline void launch(const char* name, Kernel kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t s,
+                   Args... args) {
+    hipEvent_t e0, e1;
+    if (profile_match(name, &e0, &e1))
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+}
 
 }  // namespace gsmi

@@ -23,6 +23,16 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+static thread_local char g_prof_name[64] = "";
+static thread_local hipEvent_t g_prof_start = nullptr, g_prof_stop = nullptr;
+
+bool profile_match(const char* name, hipEvent_t* start, hipEvent_t* stop) {
+    if (!g_prof_name[0] || strcmp(name, g_prof_name) != 0) return false;
+    *start = g_prof_start;
+    *stop = g_prof_stop;
+    return true;
+}
+
 int check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(GS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
@@ -108,7 +118,7 @@ __global__ __launch_bounds__(256) void k_l1_final(const double* __restrict__ par
 // ---------------------------------------------------------------------------
 struct AdamGroups {
     float* p[8];
-    const float* g[8];
+    float* g[8];
     float* m[8];
     float* v[8];
     int64_t start[9];  // prefix of counts (flattened element space)
@@ -117,12 +127,13 @@ struct AdamGroups {
 };
 
 __global__ __launch_bounds__(256) void k_adam(AdamGroups G, float b1, float b2, float eps,
-                                              float inv_sqrt_bc2, int64_t total) {
+                                              float inv_sqrt_bc2, int64_t total, int clear) {
     for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
         int k = 0;
         while (k + 1 < G.n && e >= G.start[k + 1]) ++k;
         int64_t i = e - G.start[k];
         float g = G.g[k][i];
+        if (clear) G.g[k][i] = 0.f;
         float m = fmaf(b1, G.m[k][i], (1.f - b1) * g);
         float v = fmaf(b2, G.v[k][i], (1.f - b2) * g * g);
         G.m[k][i] = m;
@@ -137,6 +148,19 @@ __global__ __launch_bounds__(256) void k_adam(AdamGroups G, float b1, float b2, 
 using namespace gsmi;
 
 extern "C" const char* gs_last_error(void) { return g_err; }
+
+extern "C" int gs_profile_kernel(const char* name, hipEvent_t start, hipEvent_t stop) {
+    if (!name || !name[0]) {
+        g_prof_name[0] = 0;
+        return GS_OK;
+    }
+    if (!start || !stop || strlen(name) >= sizeof(g_prof_name))
+        return fail(GS_ERR_INVALID_ARG, "gs_profile_kernel: bad name or events");
+    strcpy(g_prof_name, name);
+    g_prof_start = start;
+    g_prof_stop = stop;
+    return GS_OK;
+}
 
 extern "C" int64_t gs_num_tiles(int32_t width, int32_t height) {
     if (width <= 0 || height <= 0) return 0;
@@ -177,9 +201,9 @@ extern "C" int gs_l1_loss(const float* rgb, const float* target, int64_t n_vals,
     return check_launch("gs_l1_loss");
 }
 
-extern "C" int gs_adam_step(float* const* params, const float* const* grads, float* const* m,
+extern "C" int gs_adam_step(float* const* params, float* const* grads, float* const* m,
                             float* const* v, const int64_t* counts, int n_groups, const float* lr,
-                            float b1, float b2, float eps, int step, hipStream_t stream) {
+                            float b1, float b2, float eps, int step, int clear_grads, hipStream_t stream) {
     if (n_groups < 1 || n_groups > 8 || !params || !grads || !m || !v || !counts || !lr || step < 1)
         return fail(GS_ERR_INVALID_ARG, "gs_adam_step: bad arguments");
     AdamGroups G;
@@ -199,7 +223,7 @@ extern "C" int gs_adam_step(float* const* params, const float* const* grads, flo
     if (total == 0) return GS_OK;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_adam, dim3(unsigned(blocks)), dim3(256), 0, stream, G, b1, b2, eps,
-                       float(1.0 / std::sqrt(bc2)), total);
+    launch("adam", k_adam, dim3(unsigned(blocks)), dim3(256), 0, stream, G, b1, b2, eps,
+                       float(1.0 / std::sqrt(bc2)), total, clear_grads ? 1 : 0);
     return check_launch("gs_adam_step");
 }

@@ -457,7 +457,7 @@ int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t
     }
     GradOut G{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh};
     if (n_in == 0) return GS_OK;
-    hipLaunchKernelGGL(k_project_bwd, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx,
+    launch("project_bwd", k_project_bwd, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx,
                        n_in, n_in_dev, C, B, G);
     return check_launch("project backward");
 }
@@ -491,7 +491,7 @@ extern "C" int gs_project(const gs_scene* scene, const int32_t* active_idx, int6
     }
     if (n_in == 0) return GS_OK;
     SceneP P{scene->mean, scene->log_scale, scene->quat, scene->opacity_logit, scene->sh, scene->n};
-    hipLaunchKernelGGL(k_project, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx, n_in,
+    launch("project", k_project, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx, n_in,
                        n_in_dev, C, O);
     return check_launch("gs_project");
 }

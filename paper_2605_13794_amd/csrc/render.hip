@@ -379,7 +379,7 @@ int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, cons
     int rc = fill_render_cams(proj, cam, 1, A, &tt);
     if (rc) return rc;
     if (tt == 0) return GS_OK;
-    hipLaunchKernelGGL(k_importance_blend, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, ranges, uint32_t(tt), w,
+    launch("importance_blend", k_importance_blend, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, ranges, uint32_t(tt), w,
                        a);
     return check_launch("importance blend");
 }
@@ -416,7 +416,7 @@ extern "C" int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, in
     }
     O.bg[0] = bg[0]; O.bg[1] = bg[1]; O.bg[2] = bg[2];
     if (tt == 0) return GS_OK;
-    hipLaunchKernelGGL(k_render_fwd, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges, uint32_t(tt), O);
+    launch("render_fwd", k_render_fwd, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges, uint32_t(tt), O);
     return check_launch("gs_render_fwd");
 }
 
@@ -454,7 +454,7 @@ extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, i
     I.n_in = n_in;
     I.bg[0] = bg[0]; I.bg[1] = bg[1]; I.bg[2] = bg[2];
     if (tt > 0 && n_in > 0)
-        hipLaunchKernelGGL(k_render_bwd, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges, uint32_t(tt), I);
+        launch("render_bwd", k_render_bwd, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges, uint32_t(tt), I);
     if ((rc = check_launch("gs_render_bwd blend"))) return rc;
     return launch_project_bwd(scene, active_idx, n_in, n_in_dev, cams, n_cams, d2c, proj, grads, stream);
 }

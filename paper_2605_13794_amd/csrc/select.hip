@@ -397,7 +397,7 @@ static int run_select(const float* v, int64_t n, int mode, float frac, uint64_t 
     const int hb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096)));
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, W.st, W.hcnt, W.hmass, W.total, mode, k);
     for (int shift = 24; shift >= 0; shift -= 8) {
-        hipLaunchKernelGGL(k_sel_hist, dim3(hb), dim3(256), 0, s, v, n, shift, W.st, W.hcnt, W.hmass, W.total, mode);
+        launch("sel_hist", k_sel_hist, dim3(hb), dim3(256), 0, s, v, n, shift, W.st, W.hcnt, W.hmass, W.total, mode);
         hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, s, W.st, W.hcnt, W.hmass, W.total, shift, mode, frac);
     }
     if (nb > 0) {
@@ -480,11 +480,11 @@ extern "C" int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs
         hipLaunchKernelGGL(k_store_count, dim3(1), dim3(64), 0, stream, tot, n_active_dev);
         return check_launch("gs_lod_mask");
     }
-    hipLaunchKernelGGL(k_gate, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_gate, c_act, c_keep);
+    launch("gate", k_gate, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_gate, c_act, c_keep);
     hipLaunchKernelGGL(k_gate_decide, dim3(1), dim3(256), 0, stream, c_gate, c_act, c_keep, nb, n,
                        params->fallback_ratio, flag);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, c_act, nb, tot);
-    hipLaunchKernelGGL(k_compact, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_act, flag, active_idx);
+    launch("compact", k_compact, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_act, flag, active_idx);
     hipLaunchKernelGGL(k_store_count, dim3(1), dim3(64), 0, stream, tot, n_active_dev);
     return check_launch("gs_lod_mask");
 }
@@ -510,7 +510,7 @@ extern "C" int gs_importance(const gs_projected* proj, const gs_camera* cam, int
     SelWs S = carve_sel(cv, n);
     if ((rc = run_select(w, n, 0, mass_frac, 0, S, stream))) return rc;
     const int64_t nb = (n + kBlk - 1) / kBlk;
-    hipLaunchKernelGGL(k_importance_fold, dim3(unsigned(nb)), dim3(256), 0, stream, w, a, proj->radius, n, S.st,
+    launch("importance_fold", k_importance_fold, dim3(unsigned(nb)), dim3(256), 0, stream, w, a, proj->radius, n, S.st,
                        S.eq_cnt, eps, score, c_rad, c_vis, cull_row);
     return check_launch("gs_importance");
 }

@@ -28,7 +28,7 @@ REC_FLOATS = 12
 
 EXPORTED = ("gs_workspace_size", "gs_last_error", "gs_num_tiles", "gs_lod_mask", "gs_project", "gs_bin_sort",
             "gs_render_fwd", "gs_render_bwd", "gs_importance", "gs_score_keep_bits", "gs_l1_loss",
-            "gs_adam_step")
+            "gs_adam_step", "gs_profile_kernel")
 
 c_int, c_i32, c_i64, c_f, c_p, c_sz = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                        ctypes.c_void_p, ctypes.c_size_t)
@@ -83,7 +83,8 @@ def lib() -> ctypes.CDLL:
         L.gs_importance.argtypes = [P, P, c_i64, P, P, c_f, c_f, P, P, P, P, P, P, P, c_sz, P]
         L.gs_score_keep_bits.argtypes = [P, c_i64, c_i64, P, P, c_sz, P]
         L.gs_l1_loss.argtypes = [P, P, c_i64, P, P, P, c_sz, P]
-        L.gs_adam_step.argtypes = [P, P, P, P, P, c_int, P, c_f, c_f, c_f, c_int, P]
+        L.gs_adam_step.argtypes = [P, P, P, P, P, c_int, P, c_f, c_f, c_f, c_int, c_int, P]
+        L.gs_profile_kernel.argtypes = [ctypes.c_char_p, P, P]
         for name in EXPORTED:
             if name not in ("gs_workspace_size", "gs_last_error", "gs_num_tiles"):
                 getattr(L, name).restype = c_int
@@ -248,9 +249,60 @@ def gs_l1_loss(rgb, target, n_vals, loss_dev, grad, ws, stream=None):
                             stream_handle(stream)), "gs_l1_loss")
 
 
-def gs_adam_step(params, grads_, m, v, lrs, b1, b2, eps, step, stream=None):
+def gs_adam_step(params, grads_, m, v, lrs, b1, b2, eps, step, clear_grads=False, stream=None):
     n = len(params)
     counts = (c_i64 * n)(*[int(p.numel()) for p in params])
     lr = (c_f * n)(*[float(x) for x in lrs])
     _check(lib().gs_adam_step(_ptr_array(params), _ptr_array(grads_), _ptr_array(m), _ptr_array(v), counts, n, lr,
-                              float(b1), float(b2), float(eps), int(step), stream_handle(stream)), "gs_adam_step")
+                              float(b1), float(b2), float(eps), int(step), int(bool(clear_grads)),
+                              stream_handle(stream)), "gs_adam_step")
+
+
+def gs_profile_kernel(name, start=None, stop=None):
+    """Times the launches of kernel `name` with HIP events (see HipEvent)."""
+    _check(lib().gs_profile_kernel(name.encode() if name else None, start, stop), "gs_profile_kernel")
+
+
+class HipEvent:
+    """A raw HIP event (handle usable by gs_profile_kernel)."""
+    _hip = None
+
+    @classmethod
+    def hip(cls):
+        if cls._hip is None:
+            torch.cuda.init()
+            h = None
+            for name in ("libamdhip64.so", "libamdhip64.so.7", "libamdhip64.so.6"):
+                try:
+                    h = ctypes.CDLL(name)
+                    break
+                except OSError:
+                    continue
+            if h is None:
+                raise RuntimeError("libamdhip64 not found")
+            h.hipEventCreate.argtypes = [ctypes.POINTER(c_p)]
+            h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), c_p, c_p]
+            h.hipEventSynchronize.argtypes = [c_p]
+            h.hipEventDestroy.argtypes = [c_p]
+            cls._hip = h
+        return cls._hip
+
+    def __init__(self):
+        self.handle = c_p()
+        if self.hip().hipEventCreate(ctypes.byref(self.handle)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+
+    def elapsed_ms(self, end: "HipEvent") -> float:
+        h = self.hip()
+        h.hipEventSynchronize(end.handle)
+        ms = ctypes.c_float()
+        if h.hipEventElapsedTime(ctypes.byref(ms), self.handle, end.handle) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def __del__(self):
+        try:
+            if self.handle:
+                self.hip().hipEventDestroy(self.handle)
+        except Exception:
+            pass

@@ -217,10 +217,10 @@ class Adam:
         self.b1, self.b2, self.eps = b1, b2, eps
         self.t = 0
 
-    def step(self, grads, stream=None):
+    def step(self, grads, clear_grads=False, stream=None):
         self.t += 1
         G.gs_adam_step([p.detach() for p in self.params], grads, self.m, self.v, self.lrs, self.b1, self.b2,
-                       self.eps, self.t, stream)
+                       self.eps, self.t, clear_grads, stream)
 
 
 DEFAULT_LRS = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)  # mean, log_scale, quat, opacity_logit, sh
