@@ -55,6 +55,13 @@ def parse():
     ap.add_argument("--kernel", default="render_bwd", help="kernel timed for the roofline entry")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the plain/gated side measurements")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="measured seconds of the serving trace (0 disables serving)")
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-n", type=int, default=8 << 20, help="Gaussians of the served scene")
+    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg3", "cfg4"],
+                    help="cfg2: 1M city, one 1080p view (default line); cfg3: 8M city, 64-view importance "
+                         "sweep and gated vs ungated views; cfg4: 5M city, batch of 4 1080p views with Adam")
     return ap.parse_args()
 
 
@@ -208,6 +215,150 @@ class Bench:
         return 10.0 * math.log10(1.0 / mse) if mse > 0 else float("inf")
 
 
+def run_cfg3(args):
+    """8M city: importance over 64 orbit views, score mask (drop 40%), then per
+    view the 0.5 px radius gate; gated vs ungated forward and forward+backward
+    time and PSNR on a subset of views."""
+    import numpy as np
+    import torch
+
+    from paper_2605_13794_amd import gsmi as G
+    from paper_2605_13794_amd import scenes as S
+    from paper_2605_13794_amd.raster import DeviceScene, Frame, Workspace
+    n = args.n if args.n != (1 << 20) else (8 << 20)
+    sc = S.city_scene(n, seed=5)
+    ds = DeviceScene(sc, "cuda:0")
+    del sc
+    dev = torch.device("cuda:0")
+    cams = S.orbit_cameras(64, 500.0, 300.0, args.width, args.height)
+    fr = Frame([cams[0]], n, dev)
+    w = torch.empty(n, device=dev)
+    a = torch.empty(n, dtype=torch.int32, device=dev)
+    score = torch.zeros(n, device=dev)
+    c_rad = torch.zeros(n, dtype=torch.int32, device=dev)
+    c_vis = torch.zeros(n, dtype=torch.int32, device=dev)
+    cull = torch.zeros(64, (n + 31) // 32, dtype=torch.int32, device=dev)
+    ws_imp = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_IMPORTANCE, n))
+    # size the pair buffer on the first view
+    fr.project(ds.struct())
+    K0 = fr.bin_sort(check=True)
+    fr.ensure_capacity(int(K0 * 1.5) + 4096)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ks = []
+    for v, cam in enumerate(cams):
+        fr.cams = [cam]
+        fr.cam_arr = G.camera_array([cam])
+        fr.project(ds.struct())
+        fr.bin_sort(check=False)
+        G.gs_importance(fr.proj[0].struct(), G.camera(cam), n, fr.vals, fr.ranges, 0.99, 1e-6, w, a, score, c_rad,
+                        c_vis, cull[v], ws_imp)
+        Ks.append(fr.n_pairs.clone())
+    torch.cuda.synchronize()
+    sweep_ms = 1e3 * (time.perf_counter() - t0) / 64
+    Kmax = max(int(k.item()) for k in Ks)
+    if Kmax > fr.capacity:
+        raise RuntimeError("pair capacity exceeded during the sweep; rerun")
+    keep = torch.zeros((n + 31) // 32, dtype=torch.int32, device=dev)
+    G.gs_score_keep_bits(score, n, int(math.ceil(0.4 * n)), keep, Workspace(dev).get(
+        G.gs_workspace_size(G.GS_OP_SCORE_KEEP, n)))
+    active = torch.empty(n, dtype=torch.int32, device=dev)
+    n_act = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws_lod = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_LOD_MASK, n))
+    lodp = G.lod_params(G.GS_LOD_RADIUS, fallback_ratio=0.95, radius_min_px=0.5)
+    fracs, rows = [], []
+    grads = [torch.zeros_like(p) for p in ds.params()]
+    gs = G.grads(*grads)
+    target = torch.from_numpy(S.target_image(args.width, args.height, seed=1)).to(dev)
+    for v, cam in enumerate(cams):
+        G.gs_lod_mask(ds.struct(), G.camera(cam), lodp, keep, active, n_act, ws_lod)
+        fracs.append(n_act)
+    fracs = [int(x.item()) / n for x in fracs]
+    for v in range(0, 64, 8):
+        cam = cams[v]
+        res = {}
+        for mode in ("plain", "gated"):
+            f = Frame([cam], n, dev, capacity=int(Kmax * 1.2) + 4096)
+            def fwd():
+                if mode == "gated":
+                    G.gs_lod_mask(ds.struct(), G.camera(cam), lodp, keep, active, n_act, ws_lod)
+                    f.forward(ds.struct(), active, n, n_act, check=False)
+                else:
+                    f.forward(ds.struct(), check=False)
+            def fb():
+                fwd()
+                f.l1_loss([target])
+                f.backward(ds.struct(), gs)
+            for fn, key in ((fwd, "fwd_ms"), (fb, "fwd_bwd_ms")):
+                fn()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    fn()
+                torch.cuda.synchronize()
+                res[(mode, key)] = 1e3 * (time.perf_counter() - t0) / 5
+            res[(mode, "img")] = f.rgb[0].clone()
+        mse = float(((res[("gated", "img")] - res[("plain", "img")]) ** 2).mean().item())
+        rows.append({"view": v, "active_fraction": fracs[v],
+                     "plain_fwd_ms": res[("plain", "fwd_ms")], "gated_fwd_ms": res[("gated", "fwd_ms")],
+                     "plain_fwd_bwd_ms": res[("plain", "fwd_bwd_ms")],
+                     "gated_fwd_bwd_ms": res[("gated", "fwd_bwd_ms")],
+                     "psnr_db": 10 * math.log10(1 / mse) if mse > 0 else float("inf")})
+    out = {"metric": METRIC, "config": {"workload": f"aerial city {n} Gaussians, 64 orbit views 1080p: importance "
+                                                    f"sweep, drop 40% by score, 0.5 px radius gate"},
+           "importance_ms_per_view": sweep_ms, "pairs_max": Kmax,
+           "active_fraction": {"mean": float(np.mean(fracs)), "min": float(np.min(fracs)),
+                               "max": float(np.max(fracs))},
+           "views": rows,
+           "speedup_fwd_bwd": float(np.mean([r["plain_fwd_bwd_ms"] / r["gated_fwd_bwd_ms"] for r in rows]))}
+    print(json.dumps(out), flush=True)
+
+
+def run_cfg4(args):
+    """5M city, a batch of 4 1080p views (the aerial pose at headings 0, 90,
+    180, 270 degrees) through RasterizeFn, L1, backward and Adam."""
+    import torch
+
+    from paper_2605_13794_amd import gsmi as G
+    from paper_2605_13794_amd import scenes as S
+    from paper_2605_13794_amd.raster import Adam, DEFAULT_LRS, DeviceScene, Frame, rasterize
+    n = args.n if args.n != (1 << 20) else (5 << 20)
+    sc = S.city_scene(n, seed=3)
+    ds = DeviceScene(sc, "cuda:0", requires_grad=True)
+    del sc
+    dev = torch.device("cuda:0")
+    cams = [S.aerial_camera(args.width, args.height, h) for h in (0.0, 90.0, 180.0, 270.0)]
+    fr = Frame(cams, n, dev)
+    fr.forward(G.scene(*[p.detach() for p in ds.params()], lod=ds.lod), check=True)
+    fr.ensure_capacity(int(int(fr.n_pairs.item()) * 1.25) + 4096)
+    targets = torch.stack([torch.from_numpy(S.target_image(args.width, args.height, seed=10 + k)) for k in
+                           range(4)]).to(dev)
+    opt = Adam(ds.params(), DEFAULT_LRS)
+
+    def step():
+        imgs = rasterize(fr, ds)
+        loss = (imgs - targets).abs().mean()
+        loss.backward()
+        opt.step([p.grad for p in ds.params()], clear_grads=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    out = {"metric": METRIC, "value": 1 / sec, "unit": "it/s", "ms_per_step": 1e3 * sec,
+           "mpix_per_s": 4 * args.width * args.height / 1e6 / sec, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"aerial city {n} Gaussians, batch of 4 {args.width}x{args.height} views, "
+                                  f"RasterizeFn + L1 + Adam"},
+           "peak_allocated_gib": torch.cuda.max_memory_allocated() / 2**30,
+           "backward": "transmittance recomputed from the final T (no stored chain)"}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(scene, cam):
     """The float64 reference (test infrastructure) timed on the host for one
     full step of the same workload, single-threaded."""
@@ -242,12 +393,53 @@ def cpu_baseline(scene, cam):
                 imp_pairs=int(info["K"]))
 
 
+def serving(args):
+    """Continuous-batching server over the resident city: Poisson arrivals at
+    200 requests/s, resolutions uniform over {640x360, 1280x720, 1920x1080,
+    3840x2160}, random aerial poses.  Latency runs from arrival to the
+    completion event of the request's batch."""
+    import torch
+
+    from paper_2605_13794_amd import scenes as S
+    from paper_2605_13794_amd.raster import DeviceScene
+    from paper_2605_13794_amd.serve import GpuExecutor, Request, Scheduler, percentile, serve
+    t0 = time.time()
+    sc = S.city_scene(args.serve_n, seed=5)
+    ds = DeviceScene(sc, "cuda:0")
+    del sc
+    log(f"served scene {ds.n} Gaussians ready in {time.time() - t0:.1f}s")
+    total = args.serve_warmup + args.serve_seconds
+    n_req = int(total * 200 * 1.2) + 16
+    trace = [(t, cam) for t, cam in S.serving_requests(n_req, rate_hz=200.0, seed=6) if t < total]
+    reqs = [Request(rid=i, arrival=t, cam=cam) for i, (t, cam) in enumerate(trace)]
+    pool = 16 << 30
+    ex = GpuExecutor(ds, n_slots=3, max_batch=8)
+    sch = Scheduler(n_slots=3, max_batch=8, memory_budget=pool, pairs_per_px=2.0)
+    # one untimed request compiles nothing but warms the allocator and sizes buffers
+    serve([Request(rid=-1, arrival=0.0, cam=trace[0][1])], ex, sch)
+    torch.cuda.synchronize()
+    done, _ = serve(reqs, ex, sch)
+    meas = [r for r in done if r.arrival >= args.serve_warmup]
+    lat = [1e3 * r.latency for r in meas]
+    mpix = sum(r.pixels for r in meas) / 1e6
+    span = max(r.t_done for r in meas) - min(r.arrival for r in meas)
+    return {"requests": len(meas), "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "mean_ms": sum(lat) / len(lat), "mpix_per_s": mpix / span, "offered_req_per_s": 200.0,
+            "served_req_per_s": len(meas) / span, "batches": sch.n_batches, "memory_pool_gib": pool / 2**30,
+            "retries": sum(r.retries for r in done), "gaussians": ds.n, "slots": 3, "max_batch": 8,
+            "measured_s": args.serve_seconds}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.config == "cfg3":
+        return run_cfg3(args)
+    if args.config == "cfg4":
+        return run_cfg4(args)
     b = Bench(args)
     torch = b.torch
     K_all, K = b.size_buffers()
@@ -310,9 +502,15 @@ def main():
     if "gated_train_ms" in extras:
         out["gated_train_it_per_s"] = 1e3 / extras["gated_train_ms"]
         out["plain_train_it_per_s"] = 1e3 / extras["plain_train_ms"]
+    if args.serve_seconds > 0:
+        del b
+        torch.cuda.empty_cache()
+        log("serving trace ...")
+        out["serving"] = serving(args)
     if not args.no_cpu_baseline:
         log("timing the CPU reference on one step ...")
-        out["cpu_baseline"] = cpu_baseline(b.scene, b.cam)
+        from paper_2605_13794_amd import scenes as S
+        out["cpu_baseline"] = cpu_baseline(S.city_scene(args.n, seed=2), S.aerial_camera(args.width, args.height))
     print(json.dumps(out), flush=True)
 
 
