@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--kernel", default="render_bwd", help="kernel timed for the roofline entry")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the plain/gated side measurements")
+    ap.add_argument("--graph", action="store_true", help="capture the step in a HIP graph and replay it")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="measured seconds of the serving trace (0 disables serving)")
     ap.add_argument("--serve-warmup", type=float, default=2.0)
@@ -180,6 +181,23 @@ class Bench:
             k = int(fr.n_pairs.item())
             if k < 0 or k > fr.capacity:
                 raise RuntimeError(f"pair buffer overflow during timing: K={k} capacity={fr.capacity}")
+
+    def graphed(self, fn):
+        """Captures fn (no host synchronisation inside) into a HIP graph;
+        returns its replay."""
+        torch = self.torch
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        torch.cuda.synchronize()
+        self._graphs = getattr(self, "_graphs", []) + [g]
+        return g.replay
 
     def timed(self, fn, steps, warmup):
         torch = self.torch
@@ -447,7 +465,8 @@ def main():
     b.sweep()
     act_frac = int(b.n_act.item()) / b.n
     log(f"sweep done; active fraction {act_frac:.3f}")
-    sec = b.timed(b.step, args.steps, args.warmup)
+    step_fn = b.graphed(b.step) if args.graph else b.step
+    sec = b.timed(step_fn, args.steps, args.warmup)
     b.check_capacity()
     log(f"step {sec * 1e3:.3f} ms")
     extras = {}
@@ -488,6 +507,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "launch": "hip graph replay" if args.graph else "eager",
         "config": {"workload": f"aerial city {b.n} Gaussians, one {args.width}x{args.height} view per step: "
                                f"importance refresh + gated (r>={args.rmin}px, drop {args.drop:.0%} by score) "
                                f"fwd+bwd L1 + Adam",

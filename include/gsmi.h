@@ -275,12 +275,16 @@ int gs_l1_loss(const float* rgb, const float* target, int64_t n_vals, float* los
  * per-rank optimizer state (Sec. 3.1) implies it:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
  * p -= lr_k * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
- * With clear_grads != 0 each gradient is reset to 0 after it is read, ready
- * for the next accumulating gs_render_bwd.  n_groups <= 8, step >= 1.
+ * The step number is `step` (>= 1), or, if step_dev is non-NULL, the device
+ * counter *step_dev + 1, which the call then increments on the device (so a
+ * captured HIP graph replays successive steps).  With clear_grads != 0 each
+ * gradient is reset to 0 after it is read, ready for the next accumulating
+ * gs_render_bwd.  n_groups <= 8.
  */
 int gs_adam_step(float* const* params, float* const* grads, float* const* m,
                  float* const* v, const int64_t* counts, int n_groups, const float* lr,
-                 float b1, float b2, float eps, int step, int clear_grads, hipStream_t stream);
+                 float b1, float b2, float eps, int step, int32_t* step_dev, int clear_grads,
+                 hipStream_t stream);
 
 #ifdef __cplusplus
 }

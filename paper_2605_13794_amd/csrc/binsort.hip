@@ -74,12 +74,17 @@ __global__ __launch_bounds__(256) void k_scan_reduce(EmitIn E, int64_t n_total, 
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-// One workgroup: exclusive scan of the block sums, total pair count.
+// One workgroup: exclusive scan of the block sums, total pair count; also
+// clears the sort's histograms, partition counters and error flag.
 __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ block_sums, int64_t n_blocks,
                                                      int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                     uint32_t* __restrict__ n_sorted) {
+                                                     uint32_t* __restrict__ n_sorted, uint32_t* __restrict__ hist,
+                                                     uint32_t* __restrict__ counters, uint32_t* __restrict__ err) {
     __shared__ uint32_t lds4[4];
     __shared__ uint64_t carry_s;
+    for (int k = threadIdx.x; k < 8 * 256; k += 256) hist[k] = 0;
+    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *err = 0;
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
     for (int64_t b0 = 0; b0 < n_blocks; b0 += 256) {
@@ -322,23 +327,27 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ 
     }
 }
 
-// tile_ranges[t] = first index of tile t, tile_ranges[T + t] = one past last.
+// Tile ranges from the sorted keys: boundary b (0 <= b <= n_tiles) is the
+// first position whose tile id is >= b, found by binary search; tile t spans
+// [boundary t, boundary t+1).  Empty tiles get start == end, and when nothing
+// was sorted every range is empty.  Thread 0 also turns a timed-out look-back
+// wait of the sort into a negative pair count.
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys,
                                                      const uint32_t* __restrict__ n_sorted, uint32_t n_tiles,
-                                                     uint32_t* __restrict__ ranges) {
+                                                     uint32_t* __restrict__ ranges, const uint32_t* __restrict__ err,
+                                                     int64_t* __restrict__ n_pairs) {
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b == 0 && *err) *n_pairs = -1;
+    if (b > n_tiles) return;
     const uint32_t n = *n_sorted;
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const uint32_t t = uint32_t(keys[i] >> 32);
-        // neighbours within the wavefront come from the lane next door
-        const uint32_t tprev_lane = __shfl_up(t, 1, 64);
-        const uint32_t tnext_lane = __shfl_down(t, 1, 64);
-        const uint32_t l = lane_id();
-        const uint32_t tprev = (i == 0) ? 0xffffffffu : (l > 0 ? tprev_lane : uint32_t(keys[i - 1] >> 32));
-        const uint32_t tnext = (i + 1 >= n) ? 0xffffffffu : (l < 63 && i + 1 < n ? tnext_lane : uint32_t(keys[i + 1] >> 32));
-        if (t >= n_tiles) continue;
-        if (t != tprev) ranges[t] = i;
-        if (t != tnext) ranges[n_tiles + t] = i + 1;
+    uint32_t lo = 0, hi = n;  // first index with tile >= b
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (uint32_t(keys[mid] >> 32) < b) lo = mid + 1;
+        else hi = mid;
     }
+    if (b < n_tiles) ranges[b] = lo;
+    if (b > 0) ranges[n_tiles + b - 1] = lo;
 }
 
 struct SortWs {
@@ -369,17 +378,6 @@ static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity) {
     s.vals_alt = cv.take<uint32_t>(size_t(capacity > 0 ? capacity : 1));
     s.bytes = cv.used();
     return s;
-}
-
-// A timed-out look-back wait (never expected) is reported as a negative count.
-__global__ void k_sort_report(const uint32_t* __restrict__ err, int64_t* __restrict__ n_pairs) {
-    if (threadIdx.x == 0 && *err) *n_pairs = -1;
-}
-
-__global__ void k_sort_init(uint32_t* hist, uint32_t* counters, uint32_t* err) {
-    for (int k = threadIdx.x; k < 8 * 256; k += blockDim.x) hist[k] = 0;
-    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
-    if (threadIdx.x == 0) *err = 0;
 }
 
 }  // namespace gsmi
@@ -429,15 +427,16 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     const int passes = (32 + tile_bits + 7) / 8;
     if (passes > 8) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
 
-    hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, S.hist, S.counters, S.err);
-    if ((rc = fill_u32(tile_ranges, 0u, size_t(2 * total_tiles), stream))) return rc;
     const int64_t nb = (n_total + kScanItems - 1) / kScanItems;
     if (nb > 0)
         launch("scan_reduce", k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, stream, S.block_sums, nb, n_pairs_dev, capacity,
-                       S.n_sorted);
+                       S.n_sorted, S.hist, S.counters, S.err);
     if ((rc = check_launch("gs_bin_sort scan"))) return rc;
-    if (capacity == 0) return GS_OK;
+    if (capacity == 0) {
+        rc = fill_u32(tile_ranges, 0u, size_t(2 * total_tiles), stream);
+        return rc;
+    }
     // Emission target: the ping-pong buffer that ends in keys/vals after `passes` passes.
     uint64_t* kb[2] = {keys, S.keys_alt};
     uint32_t* vb[2] = {vals, S.vals_alt};
@@ -459,9 +458,8 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
                            (p + 1 < passes) ? S.status[(p + 1) & 1] : nullptr, S.counters + p, S.err, 8 * p);
         cur = nxt;
     }
-    hipLaunchKernelGGL(k_sort_report, dim3(1), dim3(64), 0, stream, S.err, n_pairs_dev);
     if ((rc = check_launch("gs_bin_sort sort"))) return rc;
-    launch("tile_ranges", k_tile_ranges, dim3(unsigned(std::min<int64_t>(4096, (capacity + 255) / 256))), dim3(256), 0,
-                       stream, keys, S.n_sorted, uint32_t(total_tiles), tile_ranges);
+    launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream, keys,
+           S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err, n_pairs_dev);
     return check_launch("gs_bin_sort ranges");
 }

@@ -122,12 +122,20 @@ struct AdamGroups {
     float* m[8];
     float* v[8];
     int64_t start[9];  // prefix of counts (flattened element space)
-    float lr_bc[8];    // lr / (1 - b1^t)
+    float lr[8];
     int n;
 };
 
-__global__ __launch_bounds__(256) void k_adam(AdamGroups G, float b1, float b2, float eps,
-                                              float inv_sqrt_bc2, int64_t total, int clear) {
+// Bias corrections come from the host step, or from a device step counter
+// (t = *step_dev + 1) so that a captured graph replays correct steps.
+__global__ __launch_bounds__(256) void k_adam(AdamGroups G, float b1, float b2, float eps, float inv_bc1,
+                                              float inv_sqrt_bc2, int64_t total, int clear,
+                                              const int32_t* __restrict__ step_dev) {
+    if (step_dev) {
+        const float t = float(*step_dev + 1);
+        inv_bc1 = 1.f / (1.f - powf(b1, t));
+        inv_sqrt_bc2 = rsqrtf(1.f - powf(b2, t));
+    }
     for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
         int k = 0;
         while (k + 1 < G.n && e >= G.start[k + 1]) ++k;
@@ -139,8 +147,12 @@ __global__ __launch_bounds__(256) void k_adam(AdamGroups G, float b1, float b2, 
         G.m[k][i] = m;
         G.v[k][i] = v;
         float denom = sqrtf(v) * inv_sqrt_bc2 + eps;
-        G.p[k][i] -= G.lr_bc[k] * m / denom;
+        G.p[k][i] -= G.lr[k] * inv_bc1 * m / denom;
     }
+}
+
+__global__ void k_adam_tick(int32_t* __restrict__ step_dev) {
+    if (threadIdx.x == 0) *step_dev += 1;
 }
 
 }  // namespace gsmi
@@ -203,9 +215,11 @@ extern "C" int gs_l1_loss(const float* rgb, const float* target, int64_t n_vals,
 
 extern "C" int gs_adam_step(float* const* params, float* const* grads, float* const* m,
                             float* const* v, const int64_t* counts, int n_groups, const float* lr,
-                            float b1, float b2, float eps, int step, int clear_grads, hipStream_t stream) {
-    if (n_groups < 1 || n_groups > 8 || !params || !grads || !m || !v || !counts || !lr || step < 1)
+                            float b1, float b2, float eps, int step, int32_t* step_dev, int clear_grads,
+                            hipStream_t stream) {
+    if (n_groups < 1 || n_groups > 8 || !params || !grads || !m || !v || !counts || !lr || (step < 1 && !step_dev))
         return fail(GS_ERR_INVALID_ARG, "gs_adam_step: bad arguments");
+    if (step < 1) step = 1;
     AdamGroups G;
     memset(&G, 0, sizeof(G));
     G.n = n_groups;
@@ -217,13 +231,14 @@ extern "C" int gs_adam_step(float* const* params, float* const* grads, float* co
             return fail(GS_ERR_INVALID_ARG, "gs_adam_step: group %d", k);
         G.p[k] = params[k]; G.g[k] = grads[k]; G.m[k] = m[k]; G.v[k] = v[k];
         G.start[k + 1] = G.start[k] + counts[k];
-        G.lr_bc[k] = float(double(lr[k]) / bc1);
+        G.lr[k] = lr[k];
     }
     const int64_t total = G.start[n_groups];
     if (total == 0) return GS_OK;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    launch("adam", k_adam, dim3(unsigned(blocks)), dim3(256), 0, stream, G, b1, b2, eps,
-                       float(1.0 / std::sqrt(bc2)), total, clear_grads ? 1 : 0);
+    launch("adam", k_adam, dim3(unsigned(blocks)), dim3(256), 0, stream, G, b1, b2, eps, float(1.0 / bc1),
+           float(1.0 / std::sqrt(bc2)), total, clear_grads ? 1 : 0, static_cast<const int32_t*>(step_dev));
+    if (step_dev) hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(64), 0, stream, step_dev);
     return check_launch("gs_adam_step");
 }

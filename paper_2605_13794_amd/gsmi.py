@@ -83,7 +83,7 @@ def lib() -> ctypes.CDLL:
         L.gs_importance.argtypes = [P, P, c_i64, P, P, c_f, c_f, P, P, P, P, P, P, P, c_sz, P]
         L.gs_score_keep_bits.argtypes = [P, c_i64, c_i64, P, P, c_sz, P]
         L.gs_l1_loss.argtypes = [P, P, c_i64, P, P, P, c_sz, P]
-        L.gs_adam_step.argtypes = [P, P, P, P, P, c_int, P, c_f, c_f, c_f, c_int, c_int, P]
+        L.gs_adam_step.argtypes = [P, P, P, P, P, c_int, P, c_f, c_f, c_f, c_int, P, c_int, P]
         L.gs_profile_kernel.argtypes = [ctypes.c_char_p, P, P]
         for name in EXPORTED:
             if name not in ("gs_workspace_size", "gs_last_error", "gs_num_tiles"):
@@ -249,12 +249,12 @@ def gs_l1_loss(rgb, target, n_vals, loss_dev, grad, ws, stream=None):
                             stream_handle(stream)), "gs_l1_loss")
 
 
-def gs_adam_step(params, grads_, m, v, lrs, b1, b2, eps, step, clear_grads=False, stream=None):
+def gs_adam_step(params, grads_, m, v, lrs, b1, b2, eps, step, clear_grads=False, step_dev=None, stream=None):
     n = len(params)
     counts = (c_i64 * n)(*[int(p.numel()) for p in params])
     lr = (c_f * n)(*[float(x) for x in lrs])
     _check(lib().gs_adam_step(_ptr_array(params), _ptr_array(grads_), _ptr_array(m), _ptr_array(v), counts, n, lr,
-                              float(b1), float(b2), float(eps), int(step), int(bool(clear_grads)),
+                              float(b1), float(b2), float(eps), int(step), ptr(step_dev), int(bool(clear_grads)),
                               stream_handle(stream)), "gs_adam_step")
 
 

@@ -207,7 +207,9 @@ def rasterize(frame: Frame, dscene: DeviceScene, active=None, n_in_dev=None):
 
 
 class Adam:
-    """Adam over the scene's parameter tensors through gs_adam_step."""
+    """Adam over the scene's parameter tensors through gs_adam_step.  The
+    step counter lives on the device, so a captured graph replays successive
+    steps."""
 
     def __init__(self, params, lrs, b1=0.9, b2=0.999, eps=1e-15):
         self.params = list(params)
@@ -215,12 +217,11 @@ class Adam:
         self.m = [torch.zeros_like(p) for p in self.params]
         self.v = [torch.zeros_like(p) for p in self.params]
         self.b1, self.b2, self.eps = b1, b2, eps
-        self.t = 0
+        self.t_dev = torch.zeros(1, dtype=torch.int32, device=self.params[0].device)
 
     def step(self, grads, clear_grads=False, stream=None):
-        self.t += 1
         G.gs_adam_step([p.detach() for p in self.params], grads, self.m, self.v, self.lrs, self.b1, self.b2,
-                       self.eps, self.t, clear_grads, stream)
+                       self.eps, 0, clear_grads, self.t_dev, stream)
 
 
 DEFAULT_LRS = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)  # mean, log_scale, quat, opacity_logit, sh
