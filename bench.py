@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the plain/gated side measurements")
     ap.add_argument("--graph", action="store_true", help="capture the step in a HIP graph and replay it")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="measured seconds of the serving trace (0 disables serving)")
     ap.add_argument("--serve-warmup", type=float, default=2.0)
@@ -448,8 +450,22 @@ def serving(args):
             "measured_s": args.serve_seconds}
 
 
+def copy_calibration():
+    """A plain copy of 1 GiB (reads 1 GiB, writes 1 GiB), five times, for
+    scaling the HBM byte counters of the profiler."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 4, "reps": 5}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)

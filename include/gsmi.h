@@ -208,11 +208,16 @@ int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int n_cams, int
  * out_rgb[c] [3][H_c][W_c], out_T[c] [H_c][W_c] final transmittance,
  * out_last[c] [H_c][W_c] = 1 + list position of the last composited
  * Gaussian (0 if none).  bg: host float[3].
+ * chain (optional, NULL = not stored): [K][256] floats, K = the pair count of
+ * gs_bin_sort; entry (k, s) receives the transmittance in front of sorted
+ * pair k at pixel slot s of its tile (s = lane + 64 r for the pixel at
+ * column lane % 16, row lane / 16 + 4 r), written where that pair is
+ * composited.  It lets gs_render_bwd read the chain instead of recomputing.
  */
 int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, int n_cams,
                   const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
                   float* const* out_rgb, float* const* out_T, uint32_t* const* out_last,
-                  hipStream_t stream);
+                  float* chain, hipStream_t stream);
 
 /*
  * Backward of gs_render_fwd and gs_project: given dL/dC (grad_rgb[c],
@@ -228,13 +233,15 @@ int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, int n_cams,
  * through culls, clamps and skip/stop decisions).
  * If grads2d is non-NULL it receives the screen-space partials of camera 0
  * ([9][n_in]: d mean2d (2), d conic (3), d opacity (1), d rgb (3)).
+ * chain: NULL (recompute T from the final T) or the chain the forward stored;
+ * then T_k is read instead of recomputed.
  * Workspace: GS_OP_RENDER_BWD (n = n_in, n_cams).
  */
 int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in,
                   const int64_t* n_in_dev, const gs_projected* proj, const gs_camera* cams,
                   int n_cams, const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
                   float* const* out_T, uint32_t* const* out_last, float* const* grad_rgb,
-                  gs_grads* grads, float* grads2d, void* ws, size_t ws_bytes,
+                  const float* chain, gs_grads* grads, float* grads2d, void* ws, size_t ws_bytes,
                   hipStream_t stream);
 
 /*

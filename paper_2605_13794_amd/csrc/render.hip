@@ -76,9 +76,14 @@ struct FwdOut {
     float* rgb[GS_MAX_CAMS];
     float* T[GS_MAX_CAMS];
     uint32_t* last[GS_MAX_CAMS];
+    float* chain;  // optional: [pairs][256] transmittance before each composited position
     float bg[3];
 };
 
+// Slot of pixel (lane, row r) inside a tile's 256-float block of the chain.
+__device__ __forceinline__ uint32_t chain_slot(int lane, int r) { return uint32_t(lane + 64 * r); }
+
+template <bool kChain>
 __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges, uint32_t n_tiles, FwdOut O) {
     __shared__ float4 sA[64];
@@ -123,6 +128,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
                 const bool stop = ok && (Tn < kTMin);
                 const bool comp = ok && !stop;
                 const float wgt = comp ? alpha * T[r] : 0.f;
+                if (kChain && comp) O.chain[size_t(b0 + i) * 256 + chain_slot(lane, r)] = T[r];
                 C0[r] = fmaf(wgt, b.z, C0[r]);
                 C1[r] = fmaf(wgt, b.w, C1[r]);
                 C2[r] = fmaf(wgt, cb, C2[r]);
@@ -155,6 +161,7 @@ struct BwdImg {
     const uint32_t* last[GS_MAX_CAMS];
     const float* grad[GS_MAX_CAMS];
     float* d2[GS_MAX_CAMS];  // [9][n_in]
+    const float* chain;      // optional stored transmittance chain
     int64_t n_in;
     float bg[3];
 };
@@ -165,6 +172,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     return v;
 }
 
+template <bool kChain>
 __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges, uint32_t n_tiles, BwdImg I) {
     __shared__ float4 sA[64];
@@ -234,7 +242,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
                 any |= ok;
                 const float om = 1.f - alpha;
                 const float rom = fast_rcp(om);
-                const float Tk = ok ? T[r] * rom : T[r];
+                float Tk = ok ? T[r] * rom : T[r];
+                if (kChain && ok) Tk = I.chain[size_t(b0 + uint32_t(i)) * 256 + chain_slot(lane, r)];
                 const float dLda = g0[r] * (Tk * (b.z - acc0[r])) + g1[r] * (Tk * (b.w - acc1[r])) +
                                    g2[r] * (Tk * (rw.w - acc2[r])) - gbg[r] * rom;
                 const float aT = alpha * Tk;
@@ -401,7 +410,7 @@ size_t ws_render_bwd(int64_t n, int n_cams) {
 
 extern "C" int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, int n_cams, const uint32_t* vals,
                              const uint32_t* tile_ranges, const float* bg, float* const* out_rgb,
-                             float* const* out_T, uint32_t* const* out_last, hipStream_t stream) {
+                             float* const* out_T, uint32_t* const* out_last, float* chain, hipStream_t stream) {
     if (!proj || !tile_ranges || !bg || !out_rgb || !out_T || !out_last)
         return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: null argument");
     RenderCams A;
@@ -415,16 +424,22 @@ extern "C" int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, in
         O.rgb[c] = out_rgb[c]; O.T[c] = out_T[c]; O.last[c] = out_last[c];
     }
     O.bg[0] = bg[0]; O.bg[1] = bg[1]; O.bg[2] = bg[2];
+    O.chain = chain;
     if (tt == 0) return GS_OK;
-    launch("render_fwd", k_render_fwd, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges, uint32_t(tt), O);
+    if (O.chain)
+        launch("render_fwd", k_render_fwd<true>, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges,
+               uint32_t(tt), O);
+    else
+        launch("render_fwd", k_render_fwd<false>, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges,
+               uint32_t(tt), O);
     return check_launch("gs_render_fwd");
 }
 
 extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
                              const gs_projected* proj, const gs_camera* cams, int n_cams, const uint32_t* vals,
                              const uint32_t* tile_ranges, const float* bg, float* const* out_T,
-                             uint32_t* const* out_last, float* const* grad_rgb, gs_grads* grads, float* grads2d,
-                             void* ws, size_t ws_bytes, hipStream_t stream) {
+                             uint32_t* const* out_last, float* const* grad_rgb, const float* chain, gs_grads* grads,
+                             float* grads2d, void* ws, size_t ws_bytes, hipStream_t stream) {
     int rc = check_scene(scene);
     if (rc) return rc;
     if (!proj || !tile_ranges || !bg || !out_T || !out_last || !grad_rgb || !grads)
@@ -452,9 +467,17 @@ extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, i
         if ((rc = fill_u32(I.d2[c], 0u, size_t(9) * size_t(n_in), stream))) return rc;
     }
     I.n_in = n_in;
+    I.chain = chain;
     I.bg[0] = bg[0]; I.bg[1] = bg[1]; I.bg[2] = bg[2];
     if (tt > 0 && n_in > 0)
-        launch("render_bwd", k_render_bwd, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges, uint32_t(tt), I);
+    {
+        if (chain)
+            launch("render_bwd", k_render_bwd<true>, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges,
+                   uint32_t(tt), I);
+        else
+            launch("render_bwd", k_render_bwd<false>, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges,
+                   uint32_t(tt), I);
+    }
     if ((rc = check_launch("gs_render_bwd blend"))) return rc;
     return launch_project_bwd(scene, active_idx, n_in, n_in_dev, cams, n_cams, d2c, proj, grads, stream);
 }

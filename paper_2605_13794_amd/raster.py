@@ -93,8 +93,11 @@ class FrameOutputs:
 class Frame:
     """All buffers of one rasterization pass over a batch of cameras."""
 
-    def __init__(self, cams, n_max: int, device="cuda", capacity: int | None = None, soa: bool = False):
+    def __init__(self, cams, n_max: int, device="cuda", capacity: int | None = None, soa: bool = False,
+                 store_chain: bool = False):
         assert 1 <= len(cams) <= G.GS_MAX_CAMS
+        self.store_chain = store_chain
+        self.chain = None
         self.device = torch.device(device)
         self.cams = list(cams)
         self.cam_arr = G.camera_array(self.cams)
@@ -150,8 +153,14 @@ class Frame:
 
     def render_fwd(self, bg=(0.0, 0.0, 0.0), stream=None):
         self.bg = tuple(float(x) for x in bg)
+        chain = None
+        if self.store_chain:
+            need = 256 * self.capacity
+            if self.chain is None or self.chain.numel() < need:
+                self.chain = torch.empty(need, dtype=F32, device=self.device)
+            chain = self.chain
         G.gs_render_fwd(self.proj_structs(), self.cam_arr, self.vals, self.ranges, self.bg, self.rgb, self.T,
-                        self.last, stream)
+                        self.last, chain, stream)
         return FrameOutputs(self.rgb, self.T, self.last)
 
     def forward(self, scn, active=None, n_in=None, n_in_dev=None, bg=(0.0, 0.0, 0.0), check=True, stream=None):
@@ -171,7 +180,8 @@ class Frame:
         g = grad_rgb if grad_rgb is not None else self.grad_rgb
         ws = self.ws_bwd.get(G.gs_workspace_size(G.GS_OP_RENDER_BWD, self.n_in, 0, 0, len(self.cams)))
         G.gs_render_bwd(scn, self.active, self.n_in, self.n_in_dev, self.proj_structs(), self.cam_arr, self.vals,
-                        self.ranges, self.bg, self.T, self.last, g, grd, grads2d, ws, stream)
+                        self.ranges, self.bg, self.T, self.last, g, grd, grads2d, ws,
+                        self.chain if self.store_chain else None, stream)
 
 
 class RasterizeFn(torch.autograd.Function):

@@ -175,7 +175,7 @@ class GpuExecutor:
             G.gs_bin_sort(projs, carr, self.n, s["keys"], s["vals"], s["cap"], s["ranges"], s["n_pairs"], ws,
                           stream)
             G.gs_render_fwd(projs, carr, s["vals"], s["ranges"], self.bg, [o[0] for o in out], [o[1] for o in out],
-                            [o[2] for o in out], stream)
+                            [o[2] for o in out], stream=stream)
             ev = torch.cuda.Event()
             ev.record(stream)
         s["event"], s["batch"], s["out"] = ev, batch, out

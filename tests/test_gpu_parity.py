@@ -235,10 +235,20 @@ def test_render_bwd_matches_reference(oracle, case):
                     G.grads(*grads), g2, ws)
     torch.cuda.synchronize()
     got = to_np(g2)
+    # the stored-chain backward gives the same partials
+    chain = torch.empty(max(K, 1) * 256, device=dev)
+    G.gs_render_fwd([pb.struct()], cams, v, r, bg, [img], [T], [last], chain=chain)
+    g3 = torch.empty(9, sc.n, device=dev)
+    G.gs_render_bwd(ds.struct(), None, sc.n, None, [pb.struct()], cams, v, r, bg, [T], [last], [gt],
+                    G.grads(*grads), g3, ws, chain=chain)
+    torch.cuda.synchronize()
+    got = to_np(g2)
     rows = {"mean2d": (0, 2), "conic": (2, 5), "opacity": (5, 6), "rgb": (6, 9)}
+    got3 = to_np(g3)
     for name, (a, b) in rows.items():
         refv = d2[name].reshape(b - a, -1)
         assert _rel_inf(got[a:b], refv) <= 1e-3, (name, _rel_inf(got[a:b], refv))
+        assert _rel_inf(got3[a:b], refv) <= 1e-3, ("stored chain", name, _rel_inf(got3[a:b], refv))
 
 
 # ---------------------------------------------------------------------------
