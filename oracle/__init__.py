@@ -392,3 +392,43 @@ def adam_step(p, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-15):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# --------------------------------------------------------------------------
+# Scheduled simplification passes (Sec. 3.2 "Scheduled simplification")
+# --------------------------------------------------------------------------
+def mass_keep(score, frac: float = 0.99):
+    """Second pass: the deterministic cumulative-mass cut keeps the smallest
+    prefix of (score descending, index ascending) whose summed score reaches
+    frac of the total (the crossing element included)."""
+    return top_mass(score, frac)
+
+
+def race_times(score, u):
+    """Exponential-race form of weighted sampling without replacement
+    (Efraimidis & Spirakis 2006): e_i = -ln(u_i) / s_i, +inf where s_i = 0.
+    Keeping the k smallest e_i (equivalently the k largest u_i^(1/s_i)) draws
+    k items without replacement with probabilities proportional to s."""
+    s = np.asarray(score, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        return np.where(s > 0, -np.log(u) / np.where(s > 0, s, 1.0), np.inf)
+
+
+def sample_keep(score, u, n_keep: int):
+    """First pass: stochastic importance-weighted sampling without replacement
+    of n_keep Gaussians, with the uniforms u in (0, 1] given; the kept set is
+    the n_keep smallest race times, ties by index."""
+    e = race_times(score, u)
+    n = e.shape[0]
+    order = np.lexsort((np.arange(n), e))
+    keep = np.zeros(n, dtype=bool)
+    keep[order[:n_keep]] = True
+    return keep
+
+
+def compact(arrays, keep):
+    """Component-major arrays [..., N] restricted to the kept Gaussians, in
+    ascending index order."""
+    keep = np.asarray(keep, dtype=bool)
+    return [np.ascontiguousarray(np.asarray(a)[..., keep]) for a in arrays]
