@@ -124,7 +124,8 @@ enum {
     GS_OP_RENDER_BWD = 2,
     GS_OP_IMPORTANCE = 3,
     GS_OP_SCORE_KEEP = 4,
-    GS_OP_L1_LOSS = 5
+    GS_OP_L1_LOSS = 5,
+    GS_OP_SIMPLIFY = 6
 };
 
 /* Bytes of workspace `op` needs for n Gaussians (per camera), n_pairs pair
@@ -267,6 +268,38 @@ int gs_importance(const gs_projected* proj, const gs_camera* cam, int64_t n,
  */
 int gs_score_keep_bits(const float* score, int64_t n, int64_t n_drop, uint32_t* keep_bits,
                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Second simplification pass (Sec. 3.2 "Scheduled simplification"): the
+ * deterministic cumulative-mass cut keeps the smallest prefix of (score
+ * descending, index ascending) whose summed score reaches mass_frac (0.99)
+ * of the total, the crossing element included; zero scores are never kept.
+ * keep_bits [ceil(n/32)]; *n_keep_dev = number kept.  Workspace:
+ * GS_OP_SIMPLIFY.
+ */
+int gs_mass_keep_bits(const float* score, int64_t n, float mass_frac, uint32_t* keep_bits,
+                      int64_t* n_keep_dev, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * First simplification pass (Sec. 3.2): importance-weighted sampling without
+ * replacement of n_keep Gaussians with probability proportional to the score,
+ * in the exponential-race form of Efraimidis & Spirakis: keep the n_keep
+ * smallest -ln(u_i) / s_i (+inf for s_i = 0), ties by index.  uniforms [n]
+ * in (0, 1] are the caller's random draws.  Workspace: GS_OP_SIMPLIFY.
+ */
+int gs_sample_keep_bits(const float* score, const float* uniforms, int64_t n, int64_t n_keep,
+                        uint32_t* keep_bits, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Compaction after a pass: for each of n_arrays component-major arrays
+ * (rows[a] x n elements of elem_bytes[a] = 4 or 1 bytes), dst[a] (rows[a] x
+ * n_keep) receives the kept columns in ascending index order.  n_keep must
+ * equal the number of set bits (read from gs_mass_keep_bits or known).
+ * n_arrays <= 16.  Workspace: GS_OP_SIMPLIFY.
+ */
+int gs_compact(const void* const* src, void* const* dst, const int32_t* rows, const int32_t* elem_bytes,
+               int n_arrays, int64_t n, int64_t n_keep, const uint32_t* keep_bits, void* ws,
+               size_t ws_bytes, hipStream_t stream);
 
 /*
  * L1 photometric term (Eq. 4 with lambda = 0): *loss_dev = mean |C - target|

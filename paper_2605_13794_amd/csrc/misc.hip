@@ -184,6 +184,7 @@ size_t ws_bin_sort(int64_t n_total, int64_t capacity, int64_t n_tiles);
 size_t ws_render_bwd(int64_t n, int n_cams);
 size_t ws_importance(int64_t n);
 size_t ws_score_keep(int64_t n);
+size_t ws_simplify(int64_t n);
 
 extern "C" size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t n_tiles, int n_cams) {
     if (n < 0) n = 0;
@@ -195,6 +196,7 @@ extern "C" size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t 
         case GS_OP_IMPORTANCE: return ws_importance(n);
         case GS_OP_SCORE_KEEP: return ws_score_keep(n);
         case GS_OP_L1_LOSS: return size_t(kL1Blocks) * sizeof(double);
+        case GS_OP_SIMPLIFY: return ws_simplify(n);
         default: return 0;
     }
 }

@@ -352,9 +352,13 @@ __global__ __launch_bounds__(256) void k_importance_fold(const float* __restrict
     if (vis) c_vis[i] += 1u;
 }
 
+// Keep bitmap from a selection: mode 1 selects the k smallest values (keep =
+// not selected for the score mask, keep = selected for race sampling); mode 0
+// selects the top-mass prefix (keep = selected).  Also counts the kept bits.
 __global__ __launch_bounds__(256) void k_keep_bits(const float* __restrict__ score, int64_t n,
                                                    const SelState* __restrict__ stp, const uint32_t* __restrict__ eq_off,
-                                                   uint32_t* __restrict__ keep) {
+                                                   uint32_t* __restrict__ keep, int mode, int keep_selected,
+                                                   unsigned long long* __restrict__ n_keep) {
     __shared__ uint32_t w4[4];
     const SelState s = *stp;
     const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
@@ -364,9 +368,63 @@ __global__ __launch_bounds__(256) void k_keep_bits(const float* __restrict__ sco
     uint32_t tot;
     const uint32_t r = block_rank(eq, w4, &tot);
     const uint32_t rank_eq = eq ? eq_off[blockIdx.x] + r : 0u;
-    const bool drop = in && selected(x, rank_eq, s, 1);
-    const uint64_t m = ballot(in && !drop);
+    const bool sel = in && selected(x, rank_eq, s, mode);
+    const bool k = in && (keep_selected ? sel : !sel);
+    const uint64_t m = ballot(k);
     store_bits(keep, n, int64_t(blockIdx.x) * kBlk + (threadIdx.x / 64) * 64, m);
+    if (n_keep) {
+        uint32_t cnt;
+        block_rank(k, w4, &cnt);
+        if (threadIdx.x == 0 && cnt) atomicAdd(n_keep, (unsigned long long)cnt);
+    }
+}
+
+// Race times of weighted sampling without replacement: -ln(u) / s, +inf for s = 0.
+__global__ __launch_bounds__(256) void k_race_times(const float* __restrict__ score, const float* __restrict__ u,
+                                                    int64_t n, float* __restrict__ e) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float s = score[i];
+    e[i] = s > 0.f ? -logf(u[i]) / s : __uint_as_float(0x7f800000u);
+}
+
+// Compaction of component-major arrays by a keep bitmap.
+struct CompactArgs {
+    const void* src[16];
+    void* dst[16];
+    int32_t rows[16];
+    int32_t bytes[16];
+    int n_arrays;
+};
+
+__global__ __launch_bounds__(256) void k_keep_count(const uint32_t* __restrict__ keep, int64_t n,
+                                                    uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t w4[4];
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    uint32_t tot;
+    block_rank(i < n && bit_of(keep, i), w4, &tot);
+    if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_compact_arrays(CompactArgs A, const uint32_t* __restrict__ keep, int64_t n,
+                                                        int64_t n_keep, const uint32_t* __restrict__ offs) {
+    __shared__ uint32_t w4[4];
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    const bool k = i < n && bit_of(keep, i);
+    uint32_t tot;
+    const int64_t r = int64_t(offs[blockIdx.x]) + block_rank(k, w4, &tot);
+    if (!k || r >= n_keep) return;
+    for (int a = 0; a < A.n_arrays; ++a) {
+        if (A.bytes[a] == 4) {
+            const float* s = static_cast<const float*>(A.src[a]);
+            float* d = static_cast<float*>(A.dst[a]);
+            for (int c = 0; c < A.rows[a]; ++c) d[int64_t(c) * n_keep + r] = s[int64_t(c) * n + i];
+        } else {
+            const uint8_t* s = static_cast<const uint8_t*>(A.src[a]);
+            uint8_t* d = static_cast<uint8_t*>(A.dst[a]);
+            for (int c = 0; c < A.rows[a]; ++c) d[int64_t(c) * n_keep + r] = s[int64_t(c) * n + i];
+        }
+    }
 }
 
 struct SelWs {
@@ -529,6 +587,87 @@ extern "C" int gs_score_keep_bits(const float* score, int64_t n, int64_t n_drop,
     int rc;
     if ((rc = run_select(score, n, 1, 0.f, uint64_t(n_drop), S, stream))) return rc;
     const int64_t nb = (n + kBlk - 1) / kBlk;
-    hipLaunchKernelGGL(k_keep_bits, dim3(unsigned(nb)), dim3(256), 0, stream, score, n, S.st, S.eq_cnt, keep_bits);
+    hipLaunchKernelGGL(k_keep_bits, dim3(unsigned(nb)), dim3(256), 0, stream, score, n, S.st, S.eq_cnt, keep_bits, 1,
+                       0, static_cast<unsigned long long*>(nullptr));
     return check_launch("gs_score_keep_bits");
+}
+
+size_t ws_simplify(int64_t n) {
+    Carve cv(nullptr);
+    carve_sel(cv, n);
+    cv.take<float>(size_t(n > 0 ? n : 1));
+    cv.take<uint32_t>(size_t((n + kBlk - 1) / kBlk + 1));
+    return cv.used();
+}
+
+extern "C" int gs_mass_keep_bits(const float* score, int64_t n, float mass_frac, uint32_t* keep_bits,
+                                 int64_t* n_keep_dev, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!score || !keep_bits || !n_keep_dev) return fail(GS_ERR_INVALID_ARG, "gs_mass_keep_bits: null argument");
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_mass_keep_bits: bad n");
+    if (!(mass_frac > 0.f) || mass_frac > 1.f) return fail(GS_ERR_INVALID_ARG, "gs_mass_keep_bits: mass_frac in (0, 1]");
+    const size_t need = ws_simplify(n);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_mass_keep_bits: workspace needs %zu bytes (256-aligned)", need);
+    int rc;
+    if ((rc = fill_u32(n_keep_dev, 0u, 2, stream))) return rc;
+    if (n == 0) return GS_OK;
+    Carve cv(ws);
+    SelWs S = carve_sel(cv, n);
+    if ((rc = run_select(score, n, 0, mass_frac, 0, S, stream))) return rc;
+    const int64_t nb = (n + kBlk - 1) / kBlk;
+    hipLaunchKernelGGL(k_keep_bits, dim3(unsigned(nb)), dim3(256), 0, stream, score, n, S.st, S.eq_cnt, keep_bits, 0,
+                       1, reinterpret_cast<unsigned long long*>(n_keep_dev));
+    return check_launch("gs_mass_keep_bits");
+}
+
+extern "C" int gs_sample_keep_bits(const float* score, const float* uniforms, int64_t n, int64_t n_keep,
+                                   uint32_t* keep_bits, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!score || !uniforms || !keep_bits) return fail(GS_ERR_INVALID_ARG, "gs_sample_keep_bits: null argument");
+    if (n < 0 || n >= (int64_t(1) << 31) || n_keep < 0 || n_keep > n)
+        return fail(GS_ERR_INVALID_ARG, "gs_sample_keep_bits: need 0 <= n_keep <= n < 2^31");
+    const size_t need = ws_simplify(n);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_sample_keep_bits: workspace needs %zu bytes (256-aligned)", need);
+    if (n == 0) return GS_OK;
+    Carve cv(ws);
+    SelWs S = carve_sel(cv, n);
+    float* e = cv.take<float>(size_t(n));
+    hipLaunchKernelGGL(k_race_times, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream, score, uniforms, n, e);
+    int rc;
+    if ((rc = run_select(e, n, 1, 0.f, uint64_t(n_keep), S, stream))) return rc;
+    const int64_t nb = (n + kBlk - 1) / kBlk;
+    hipLaunchKernelGGL(k_keep_bits, dim3(unsigned(nb)), dim3(256), 0, stream, e, n, S.st, S.eq_cnt, keep_bits, 1, 1,
+                       static_cast<unsigned long long*>(nullptr));
+    return check_launch("gs_sample_keep_bits");
+}
+
+extern "C" int gs_compact(const void* const* src, void* const* dst, const int32_t* rows, const int32_t* elem_bytes,
+                          int n_arrays, int64_t n, int64_t n_keep, const uint32_t* keep_bits, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+    if (n_arrays < 1 || n_arrays > 16 || !src || !dst || !rows || !elem_bytes || !keep_bits)
+        return fail(GS_ERR_INVALID_ARG, "gs_compact: bad arguments");
+    if (n < 0 || n >= (int64_t(1) << 31) || n_keep < 0 || n_keep > n)
+        return fail(GS_ERR_INVALID_ARG, "gs_compact: need 0 <= n_keep <= n < 2^31");
+    CompactArgs A;
+    memset(&A, 0, sizeof(A));
+    A.n_arrays = n_arrays;
+    for (int a = 0; a < n_arrays; ++a) {
+        if ((elem_bytes[a] != 4 && elem_bytes[a] != 1) || rows[a] < 1 || (n > 0 && (!src[a] || !dst[a])))
+            return fail(GS_ERR_INVALID_ARG, "gs_compact: array %d", a);
+        A.src[a] = src[a]; A.dst[a] = dst[a]; A.rows[a] = rows[a]; A.bytes[a] = elem_bytes[a];
+    }
+    const size_t need = ws_simplify(n);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_compact: workspace needs %zu bytes (256-aligned)", need);
+    if (n == 0 || n_keep == 0) return GS_OK;
+    Carve cv(ws);
+    SelWs S = carve_sel(cv, n);
+    (void)S;
+    cv.take<float>(size_t(n));
+    const int64_t nb = (n + kBlk - 1) / kBlk;
+    uint32_t* cnt = cv.take<uint32_t>(size_t(nb + 1));
+    hipLaunchKernelGGL(k_keep_count, dim3(unsigned(nb)), dim3(256), 0, stream, keep_bits, n, cnt);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, cnt, nb, static_cast<uint64_t*>(nullptr));
+    hipLaunchKernelGGL(k_compact_arrays, dim3(unsigned(nb)), dim3(256), 0, stream, A, keep_bits, n, n_keep, cnt);
+    return check_launch("gs_compact");
 }

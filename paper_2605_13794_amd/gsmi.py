@@ -21,14 +21,15 @@ GS_ERR_WORKSPACE = -3
 GS_ERR_HIP = -4
 
 GS_LOD_NONE, GS_LOD_LEVEL, GS_LOD_RADIUS = 0, 1, 2
-GS_OP_LOD_MASK, GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_IMPORTANCE, GS_OP_SCORE_KEEP, GS_OP_L1_LOSS = range(6)
+(GS_OP_LOD_MASK, GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_IMPORTANCE, GS_OP_SCORE_KEEP, GS_OP_L1_LOSS,
+ GS_OP_SIMPLIFY) = range(7)
 GS_MAX_CAMS = 8
 GS_MAX_PAIRS = 1 << 30
 REC_FLOATS = 12
 
 EXPORTED = ("gs_workspace_size", "gs_last_error", "gs_num_tiles", "gs_lod_mask", "gs_project", "gs_bin_sort",
             "gs_render_fwd", "gs_render_bwd", "gs_importance", "gs_score_keep_bits", "gs_l1_loss",
-            "gs_adam_step", "gs_profile_kernel")
+            "gs_adam_step", "gs_profile_kernel", "gs_mass_keep_bits", "gs_sample_keep_bits", "gs_compact")
 
 c_int, c_i32, c_i64, c_f, c_p, c_sz = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                        ctypes.c_void_p, ctypes.c_size_t)
@@ -85,6 +86,9 @@ def lib() -> ctypes.CDLL:
         L.gs_l1_loss.argtypes = [P, P, c_i64, P, P, P, c_sz, P]
         L.gs_adam_step.argtypes = [P, P, P, P, P, c_int, P, c_f, c_f, c_f, c_int, P, c_int, P]
         L.gs_profile_kernel.argtypes = [ctypes.c_char_p, P, P]
+        L.gs_mass_keep_bits.argtypes = [P, c_i64, c_f, P, P, P, c_sz, P]
+        L.gs_sample_keep_bits.argtypes = [P, P, c_i64, c_i64, P, P, c_sz, P]
+        L.gs_compact.argtypes = [P, P, P, P, c_int, c_i64, c_i64, P, P, c_sz, P]
         for name in EXPORTED:
             if name not in ("gs_workspace_size", "gs_last_error", "gs_num_tiles"):
                 getattr(L, name).restype = c_int
@@ -243,6 +247,25 @@ def gs_importance(proj: GsProjected, cam: GsCamera, n, vals, tile_ranges, mass_f
 def gs_score_keep_bits(score, n, n_drop, keep_bits, ws, stream=None):
     _check(lib().gs_score_keep_bits(ptr(score), int(n), int(n_drop), ptr(keep_bits), ptr(ws), ws.numel(),
                                     stream_handle(stream)), "gs_score_keep_bits")
+
+
+def gs_mass_keep_bits(score, n, mass_frac, keep_bits, n_keep_dev, ws, stream=None):
+    _check(lib().gs_mass_keep_bits(ptr(score), int(n), float(mass_frac), ptr(keep_bits), ptr(n_keep_dev), ptr(ws),
+                                   ws.numel(), stream_handle(stream)), "gs_mass_keep_bits")
+
+
+def gs_sample_keep_bits(score, uniforms, n, n_keep, keep_bits, ws, stream=None):
+    _check(lib().gs_sample_keep_bits(ptr(score), ptr(uniforms), int(n), int(n_keep), ptr(keep_bits), ptr(ws),
+                                     ws.numel(), stream_handle(stream)), "gs_sample_keep_bits")
+
+
+def gs_compact(src, dst, n, n_keep, keep_bits, ws, stream=None):
+    """src/dst: lists of tensors [rows, n] / [rows, n_keep] (float32 or uint8)."""
+    k = len(src)
+    rows = (ctypes.c_int32 * k)(*[1 if t.dim() == 1 else int(t.shape[0]) for t in src])
+    eb = (ctypes.c_int32 * k)(*[int(t.element_size()) for t in src])
+    _check(lib().gs_compact(_ptr_array(src), _ptr_array(dst), rows, eb, k, int(n), int(n_keep), ptr(keep_bits),
+                            ptr(ws), ws.numel(), stream_handle(stream)), "gs_compact")
 
 
 def gs_l1_loss(rgb, target, n_vals, loss_dev, grad, ws, stream=None):

@@ -1,0 +1,84 @@
+"""GPU parity of the simplification passes (cumulative-mass cut, weighted
+sampling without replacement, compaction) against the float64 reference."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from tests.gpuhelp import device, gsmi, to_np, u32
+
+pytestmark = pytest.mark.gpu
+
+
+def _scores(n, seed):
+    rng = np.random.default_rng(seed)
+    s = rng.lognormal(0.0, 1.5, n).astype(np.float32)
+    s[rng.random(n) < 0.2] = 0.0
+    s[rng.random(n) < 0.02] = np.float32(1.0)   # ties
+    return s
+
+
+@pytest.mark.parametrize("n", [1000, 4096 + 7, 1 << 20])
+def test_mass_keep_matches_reference(oracle, n):
+    dev = device()
+    G = gsmi()
+    s = _scores(n, n)
+    ref = oracle.mass_keep(s.astype(np.float64), 0.99)
+    st = torch.from_numpy(s).to(dev)
+    keep = torch.zeros((n + 31) // 32, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(G.gs_workspace_size(G.GS_OP_SIMPLIFY, n), dtype=torch.uint8, device=dev)
+    G.gs_mass_keep_bits(st, n, 0.99, keep, cnt, ws)
+    torch.cuda.synchronize()
+    got = oracle.unpack_bits(u32(keep), n)
+    assert int(cnt.item()) == int(got.sum())
+    # decisions may differ only where the cumulative mass sits at the cut
+    idx = np.nonzero(s > 0)[0]
+    order = idx[np.lexsort((idx, -s[idx].astype(np.float64)))]
+    cs = np.cumsum(s[order].astype(np.float64))
+    before = cs - s[order]
+    band = np.zeros(n, dtype=bool)
+    band[order[np.abs(before - 0.99 * cs[-1]) <= 1e-9 * cs[-1]]] = True
+    assert not ((got != ref) & ~band).any()
+
+
+@pytest.mark.parametrize("n", [1000, 1 << 20])
+def test_sample_keep_matches_reference(oracle, n):
+    dev = device()
+    G = gsmi()
+    s = _scores(n, n + 1)
+    rng = np.random.default_rng(5)
+    u = (1.0 - rng.random(n)).astype(np.float32)
+    n_keep = int(0.68 * n)
+    ref = oracle.sample_keep(s.astype(np.float64), u.astype(np.float64), n_keep)
+    keep = torch.zeros((n + 31) // 32, dtype=torch.int32, device=dev)
+    ws = torch.empty(G.gs_workspace_size(G.GS_OP_SIMPLIFY, n), dtype=torch.uint8, device=dev)
+    G.gs_sample_keep_bits(torch.from_numpy(s).to(dev), torch.from_numpy(u).to(dev), n, n_keep, keep, ws)
+    torch.cuda.synchronize()
+    got = oracle.unpack_bits(u32(keep), n)
+    assert got.sum() == n_keep
+    e = oracle.race_times(s, u)
+    tau = np.sort(e, kind="stable")[n_keep - 1]
+    band = np.abs(e - tau) <= 1e-5 * abs(tau) if np.isfinite(tau) else (e == tau)
+    assert not ((got != ref) & ~band).any()
+
+
+def test_compact_matches_reference(oracle):
+    dev = device()
+    G = gsmi()
+    n = 100_003
+    rng = np.random.default_rng(2)
+    arrays = [rng.standard_normal((3, n)).astype(np.float32), rng.standard_normal((48, n)).astype(np.float32),
+              rng.standard_normal(n).astype(np.float32), rng.integers(0, 8, n).astype(np.uint8)]
+    keep = rng.random(n) < 0.61
+    n_keep = int(keep.sum())
+    ref = oracle.compact(arrays, keep)
+    src = [torch.from_numpy(a).to(dev) for a in arrays]
+    dst = [torch.empty(*(a.shape[:-1] + (n_keep,)), dtype=t.dtype, device=dev) for a, t in zip(arrays, src)]
+    kb = torch.from_numpy(oracle.pack_bits(keep).view(np.int32)).to(dev)
+    ws = torch.empty(G.gs_workspace_size(G.GS_OP_SIMPLIFY, n), dtype=torch.uint8, device=dev)
+    G.gs_compact(src, dst, n, n_keep, kb, ws)
+    torch.cuda.synchronize()
+    for r, d in zip(ref, dst):
+        np.testing.assert_array_equal(to_np(d), r)
