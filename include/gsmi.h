@@ -125,7 +125,9 @@ enum {
     GS_OP_IMPORTANCE = 3,
     GS_OP_SCORE_KEEP = 4,
     GS_OP_L1_LOSS = 5,
-    GS_OP_SIMPLIFY = 6
+    GS_OP_SIMPLIFY = 6,
+    GS_OP_PHOTO_LOSS = 7, /* n = width * 65536 + height */
+    GS_OP_SCALE_REG = 8
 };
 
 /* Bytes of workspace `op` needs for n Gaussians (per camera), n_pairs pair
@@ -308,6 +310,29 @@ int gs_compact(const void* const* src, void* const* dst, const int32_t* rows, co
  */
 int gs_l1_loss(const float* rgb, const float* target, int64_t n_vals, float* loss_dev,
                float* grad, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Photometric term of the paper's objective (Sec. 3.4, Eq. 4) for one view:
+ * loss = scale * [(1 - lambda) mean|C - I| + lambda (1 - mean SSIM(C, I))]
+ * with SSIM over an 11x11 Gaussian window (sigma 1.5), constants (0.01)^2
+ * and (0.03)^2, local statistics zero-padded at the image border; grad =
+ * d loss / dC.  rgb, target, grad: [3][height][width].  Use scale = 1/B to
+ * average a batch of B views.  Deterministic.  Workspace: gs_workspace_size
+ * (GS_OP_PHOTO_LOSS, width * 65536 + height, ...).
+ */
+int gs_photo_loss(const float* rgb, const float* target, int32_t width, int32_t height, float lambda,
+                  float scale, float* loss_dev, float* grad, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Scale regulariser (Sec. 3.4, Eq. 5): *loss_dev = beta * mean over the
+ * visible entries (radius > 0 in `radius`, the projection of this view) of
+ * the smallest scale exp(min_j log_scale_j), and grad_log_scale (+=) gets
+ * beta / |V| * s_min on the arg-min axis (first axis on ties).  Entry j is
+ * Gaussian active_idx[j] as in gs_project.  Workspace: GS_OP_SCALE_REG.
+ */
+int gs_scale_reg(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
+                 const int32_t* radius, float beta, float* loss_dev, float* grad_log_scale, void* ws,
+                 size_t ws_bytes, hipStream_t stream);
 
 /*
  * Adam with bias correction (Kingma & Ba), one fused launch over n_groups

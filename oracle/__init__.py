@@ -432,3 +432,66 @@ def compact(arrays, keep):
     ascending index order."""
     keep = np.asarray(keep, dtype=bool)
     return [np.ascontiguousarray(np.asarray(a)[..., keep]) for a in arrays]
+
+
+# --------------------------------------------------------------------------
+# The paper's objective (Sec. 3.4, Eqs. 4-5)
+# --------------------------------------------------------------------------
+SSIM_SIZE = 11
+SSIM_SIGMA = 1.5
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window(size: int = SSIM_SIZE, sigma: float = SSIM_SIGMA) -> np.ndarray:
+    """Normalised 1-D Gaussian window (the 2-D window is its outer product)."""
+    x = np.arange(size, dtype=np.float64) - (size - 1) / 2.0
+    g = np.exp(-x * x / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def ssim_map(img, tgt):
+    """Per-pixel SSIM (Wang et al. 2004) of two [3][H][W] images with an 11x11
+    Gaussian window (sigma 1.5), constants (0.01)^2 and (0.03)^2 for a unit
+    dynamic range, local statistics by zero-padded 'same' convolution (the
+    paper does not state its SSIM settings; these are the customary ones).
+    Differentiable float64 torch expression."""
+    x = torch.as_tensor(img, dtype=torch.float64)
+    y = torch.as_tensor(tgt, dtype=torch.float64)
+    g = torch.from_numpy(ssim_window())
+    w = torch.outer(g, g)[None, None].repeat(3, 1, 1, 1)
+    conv = lambda t: torch.nn.functional.conv2d(t[None], w, padding=SSIM_SIZE // 2, groups=3)[0]  # noqa: E731
+    mx, my = conv(x), conv(y)
+    sxx = conv(x * x) - mx * mx
+    syy = conv(y * y) - my * my
+    sxy = conv(x * y) - mx * my
+    return ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+
+
+def photo_loss(img, tgt, lam: float = 0.2):
+    """Eq. 4 for one view: (1 - lambda) mean|C - I| + lambda (1 - mean SSIM).
+    Returns (loss, dL/dC) with the gradient from autograd (sign(0) = 0 in the
+    L1 part, as torch's abs)."""
+    x = torch.as_tensor(np.asarray(img, dtype=np.float64)).clone().requires_grad_(True)
+    y = torch.as_tensor(np.asarray(tgt, dtype=np.float64))
+    L = (1 - lam) * (x - y).abs().mean() + lam * (1 - ssim_map(x, y).mean())
+    (g,) = torch.autograd.grad(L, x)
+    return float(L.item()), g.numpy()
+
+
+def scale_reg(log_scale, visible, beta: float = 10.0):
+    """Eq. 5 regulariser: beta * mean over the visible set of the smallest
+    scale axis, and its gradient with respect to the log-scales (the
+    derivative flows to the arg-min axis only; first axis wins ties)."""
+    ls = np.asarray(log_scale, dtype=np.float64)
+    vis = np.asarray(visible, dtype=bool)
+    nv = int(vis.sum())
+    grad = np.zeros_like(ls)
+    if nv == 0:
+        return 0.0, grad
+    j = np.argmin(ls, axis=0)
+    smin = np.exp(ls[j, np.arange(ls.shape[1])])
+    L = beta * smin[vis].sum() / nv
+    cols = np.nonzero(vis)[0]
+    grad[j[cols], cols] = beta * smin[cols] / nv
+    return float(L), grad

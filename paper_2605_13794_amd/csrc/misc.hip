@@ -185,6 +185,8 @@ size_t ws_render_bwd(int64_t n, int n_cams);
 size_t ws_importance(int64_t n);
 size_t ws_score_keep(int64_t n);
 size_t ws_simplify(int64_t n);
+size_t ws_photo(int32_t W, int32_t H);
+size_t ws_scale_reg();
 
 extern "C" size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t n_tiles, int n_cams) {
     if (n < 0) n = 0;
@@ -197,6 +199,8 @@ extern "C" size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t 
         case GS_OP_SCORE_KEEP: return ws_score_keep(n);
         case GS_OP_L1_LOSS: return size_t(kL1Blocks) * sizeof(double);
         case GS_OP_SIMPLIFY: return ws_simplify(n);
+        case GS_OP_PHOTO_LOSS: return ws_photo(int32_t(n / 65536), int32_t(n % 65536));
+        case GS_OP_SCALE_REG: return ws_scale_reg();
         default: return 0;
     }
 }

@@ -22,14 +22,15 @@ GS_ERR_HIP = -4
 
 GS_LOD_NONE, GS_LOD_LEVEL, GS_LOD_RADIUS = 0, 1, 2
 (GS_OP_LOD_MASK, GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_IMPORTANCE, GS_OP_SCORE_KEEP, GS_OP_L1_LOSS,
- GS_OP_SIMPLIFY) = range(7)
+ GS_OP_SIMPLIFY, GS_OP_PHOTO_LOSS, GS_OP_SCALE_REG) = range(9)
 GS_MAX_CAMS = 8
 GS_MAX_PAIRS = 1 << 30
 REC_FLOATS = 12
 
 EXPORTED = ("gs_workspace_size", "gs_last_error", "gs_num_tiles", "gs_lod_mask", "gs_project", "gs_bin_sort",
             "gs_render_fwd", "gs_render_bwd", "gs_importance", "gs_score_keep_bits", "gs_l1_loss",
-            "gs_adam_step", "gs_profile_kernel", "gs_mass_keep_bits", "gs_sample_keep_bits", "gs_compact")
+            "gs_adam_step", "gs_profile_kernel", "gs_mass_keep_bits", "gs_sample_keep_bits", "gs_compact",
+            "gs_photo_loss", "gs_scale_reg")
 
 c_int, c_i32, c_i64, c_f, c_p, c_sz = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                        ctypes.c_void_p, ctypes.c_size_t)
@@ -89,6 +90,8 @@ def lib() -> ctypes.CDLL:
         L.gs_mass_keep_bits.argtypes = [P, c_i64, c_f, P, P, P, c_sz, P]
         L.gs_sample_keep_bits.argtypes = [P, P, c_i64, c_i64, P, P, c_sz, P]
         L.gs_compact.argtypes = [P, P, P, P, c_int, c_i64, c_i64, P, P, c_sz, P]
+        L.gs_photo_loss.argtypes = [P, P, c_i32, c_i32, c_f, c_f, P, P, P, c_sz, P]
+        L.gs_scale_reg.argtypes = [P, P, c_i64, P, P, c_f, P, P, P, c_sz, P]
         for name in EXPORTED:
             if name not in ("gs_workspace_size", "gs_last_error", "gs_num_tiles"):
                 getattr(L, name).restype = c_int
@@ -266,6 +269,17 @@ def gs_compact(src, dst, n, n_keep, keep_bits, ws, stream=None):
     eb = (ctypes.c_int32 * k)(*[int(t.element_size()) for t in src])
     _check(lib().gs_compact(_ptr_array(src), _ptr_array(dst), rows, eb, k, int(n), int(n_keep), ptr(keep_bits),
                             ptr(ws), ws.numel(), stream_handle(stream)), "gs_compact")
+
+
+def gs_photo_loss(rgb, target, width, height, lam, scale, loss_dev, grad, ws, stream=None):
+    _check(lib().gs_photo_loss(ptr(rgb), ptr(target), int(width), int(height), float(lam), float(scale),
+                               ptr(loss_dev), ptr(grad), ptr(ws), ws.numel(), stream_handle(stream)), "gs_photo_loss")
+
+
+def gs_scale_reg(scn: GsScene, active_idx, n_in, n_in_dev, radius, beta, loss_dev, grad_log_scale, ws, stream=None):
+    _check(lib().gs_scale_reg(ctypes.byref(scn), ptr(active_idx), int(n_in), ptr(n_in_dev), ptr(radius), float(beta),
+                              ptr(loss_dev), ptr(grad_log_scale), ptr(ws), ws.numel(), stream_handle(stream)),
+           "gs_scale_reg")
 
 
 def gs_l1_loss(rgb, target, n_vals, loss_dev, grad, ws, stream=None):
