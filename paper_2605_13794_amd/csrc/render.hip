@@ -52,14 +52,29 @@ __device__ __forceinline__ TileCtx tile_ctx(const RenderCams& A, const uint32_t*
 
 // Staged record: (mx, my, na, nb), (nc, o, r, g), (b), with the conic scaled
 // so that the log2-domain exponent is na dx^2 + nb dx dy + nc dy^2.
-__device__ __forceinline__ void stage_record(const float* rec, uint32_t j, float4& A, float4& B, float& C) {
-    const float4* p = reinterpret_cast<const float4*>(rec) + size_t(j) * 3;
-    const float4 q0 = p[0];
-    const float4 q1 = p[1];
-    const float q2 = p[2].x;
-    A = make_float4(q0.x, q0.y, -0.5f * kLog2e * q0.z, -kLog2e * q0.w);
-    B = make_float4(-0.5f * kLog2e * q1.x, q1.y, q1.z, q1.w);
-    C = q2;
+// A raw render record held in registers while the previous batch is blended.
+struct RawRec {
+    float4 q0, q1;
+    float q2;
+    uint32_t j;
+};
+
+__device__ __forceinline__ void fetch_record(const float* rec, const uint32_t* vals, uint32_t base, uint32_t end,
+                                             int lane, RawRec& R) {
+    if (base + uint32_t(lane) < end) {
+        R.j = vals[base + lane];
+        const float4* p = reinterpret_cast<const float4*>(rec) + size_t(R.j) * 3;
+        R.q0 = p[0];
+        R.q1 = p[1];
+        R.q2 = p[2].x;
+    }
+}
+
+__device__ __forceinline__ float4 scaled_a(const RawRec& R) {
+    return make_float4(R.q0.x, R.q0.y, -0.5f * kLog2e * R.q0.z, -kLog2e * R.q0.w);
+}
+__device__ __forceinline__ float4 scaled_b(const RawRec& R) {
+    return make_float4(-0.5f * kLog2e * R.q1.x, R.q1.y, R.q1.z, R.q1.w);
 }
 
 // alpha of a staged record at one pixel; identical in forward and backward.
@@ -99,17 +114,17 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
         T[r] = 1.f; C0[r] = C1[r] = C2[r] = 0.f; last[r] = 0; done[r] = !t.valid[r];
     }
     const int lane = threadIdx.x;
+    RawRec R = {};
+    fetch_record(rec, vals, t.start, t.end, lane, R);
     for (uint32_t b0 = t.start; b0 < t.end; b0 += 64) {
         if (__all(done[0] && done[1] && done[2] && done[3])) break;
         const uint32_t nb = min(64u, t.end - b0);
         __syncthreads();
         if (uint32_t(lane) < nb) {
-            float4 a, b;
-            float cc;
-            stage_record(rec, vals[b0 + lane], a, b, cc);
-            sA[lane] = a; sB[lane] = b; sC[lane] = cc;
+            sA[lane] = scaled_a(R); sB[lane] = scaled_b(R); sC[lane] = R.q2;
         }
         __syncthreads();
+        fetch_record(rec, vals, b0 + 64, t.end, lane, R);  // next batch in flight during the blend
         for (uint32_t i = 0; i < nb; ++i) {
             const float4 a = sA[i];
             const float4 b = sB[i];
@@ -204,22 +219,25 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
     const int64_t n_in = I.n_in;
     float* d2 = I.d2[t.c];
     const uint32_t stop_at = t.start + min(lmax, t.end - t.start);
+    RawRec R = {};
+    if (stop_at > t.start) {
+        const uint32_t nb0 = min(64u, stop_at - t.start);
+        fetch_record(rec, vals, stop_at - nb0, stop_at, lane, R);
+    }
     for (uint32_t b_end = stop_at; b_end > t.start;) {
         const uint32_t nb = min(64u, b_end - t.start);
         const uint32_t b0 = b_end - nb;
         __syncthreads();
         if (uint32_t(lane) < nb) {
-            const uint32_t j = vals[b0 + lane];
-            float4 a, b;
-            float cc;
-            stage_record(rec, j, a, b, cc);
-            const float4 q0 = reinterpret_cast<const float4*>(rec)[size_t(j) * 3];
-            const float qc = reinterpret_cast<const float4*>(rec)[size_t(j) * 3 + 1].x;
-            sA[lane] = a; sB[lane] = b;
-            sR[lane] = make_float4(q0.z, q0.w, qc, cc);
-            sJ[lane] = j;
+            sA[lane] = scaled_a(R); sB[lane] = scaled_b(R);
+            sR[lane] = make_float4(R.q0.z, R.q0.w, R.q1.x, R.q2);
+            sJ[lane] = R.j;
         }
         __syncthreads();
+        if (b0 > t.start) {  // the preceding batch, fetched during this one
+            const uint32_t nbn = min(64u, b0 - t.start);
+            fetch_record(rec, vals, b0 - nbn, b0, lane, R);
+        }
         for (int i = int(nb) - 1; i >= 0; --i) {
             const float4 a = sA[i];
             const float4 b = sB[i];
@@ -311,20 +329,20 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
 #pragma unroll
     for (int r = 0; r < 4; ++r) { T[r] = 1.f; done[r] = !t.valid[r]; }
     const int lane = threadIdx.x;
+    RawRec R = {};
+    fetch_record(rec, vals, t.start, t.end, lane, R);
     for (uint32_t b0 = t.start; b0 < t.end; b0 += 64) {
         if (__all(done[0] && done[1] && done[2] && done[3])) break;
         const uint32_t nb = min(64u, t.end - b0);
         __syncthreads();
         if (uint32_t(lane) < nb) {
-            const uint32_t j = vals[b0 + lane];
-            float4 a, b;
-            float cc;
-            stage_record(rec, j, a, b, cc);
-            sA[lane] = a;
+            const float4 b = scaled_b(R);
+            sA[lane] = scaled_a(R);
             sB[lane] = make_float2(b.x, b.y);
-            sJ[lane] = j;
+            sJ[lane] = R.j;
         }
         __syncthreads();
+        fetch_record(rec, vals, b0 + 64, t.end, lane, R);
         for (uint32_t i = 0; i < nb; ++i) {
             const float4 a = sA[i];
             const float2 b = sB[i];
