@@ -122,3 +122,13 @@ def tile_mask(tiles, width, height):
         ty, tx = divmod(int(t), TX)
         m[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = False
     return m
+
+
+def assert_same_ranges(got, ref):
+    """Tile ranges agree: every tile has the same list length, and non-empty
+    tiles the same start (an empty tile's start is not unique)."""
+    got = np.asarray(got).reshape(2, -1).astype(np.int64)
+    ref = np.asarray(ref).reshape(2, -1).astype(np.int64)
+    np.testing.assert_array_equal(got[1] - got[0], ref[1] - ref[0])
+    ne = ref[1] > ref[0]
+    np.testing.assert_array_equal(got[0][ne], ref[0][ne])
