@@ -38,8 +38,14 @@ PEAK_HBM_GBS = 8000.0
 # VALU lane-operation issue rate without packed FP32: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz (an FMA counts as one operation).
 PEAK_ALU_GOPS = 256 * 4 * 16 * 2.4
-# Algorithmic operations per Gaussian-pixel evaluation (see the design notes):
-OPS_PER_EVAL = {"render_fwd": 16.0, "render_bwd": 47.0, "importance_blend": 14.0}
+# Algorithmic operations of the backward blend (an FMA counts as one): every
+# list position below a pixel's `last` re-evaluates alpha (13 ops: offsets,
+# quadratic form, exp, opacity product, clamp, threshold test); each
+# composited (pixel, Gaussian) pair then costs 37 more (transmittance
+# recovery, dL/dalpha over 3 channels and the background term, the running
+# colour behind, colour, opacity, mean and conic partials).
+ALPHA_OPS = 13.0
+BWD_COMPOSITED_OPS = 37.0
 
 
 def parse():
@@ -52,7 +58,8 @@ def parse():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--drop", type=float, default=0.4, help="score-mask drop fraction")
     ap.add_argument("--rmin", type=float, default=0.5, help="projected-radius gate, px")
-    ap.add_argument("--kernel", default="render_bwd", help="kernel timed for the roofline entry")
+    ap.add_argument("--kernel", default="render_bwd", help="kernel timed for the roofline entry "
+                                                          "(render_bwd, or any kernel for its time only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the plain/gated side measurements")
     ap.add_argument("--graph", action="store_true", help="capture the step in a HIP graph and replay it")
@@ -479,11 +486,11 @@ def main():
     K_all, K = b.size_buffers()
     log(f"pairs: whole shard {K_all}, gated {K}")
     b.sweep()
-    act_frac = int(b.n_act.item()) / b.n
-    log(f"sweep done; active fraction {act_frac:.3f}")
     step_fn = b.graphed(b.step) if args.graph else b.step
     sec = b.timed(step_fn, args.steps, args.warmup)
     b.check_capacity()
+    act_frac = int(b.n_act.item()) / b.n
+    log(f"active fraction {act_frac:.3f}")
     log(f"step {sec * 1e3:.3f} ms")
     extras = {}
     if not args.quick:
@@ -497,15 +504,25 @@ def main():
     name = args.kernel
     reps = max(5, min(args.steps, 20))
     kms = b.kernel_time(name, b.step, reps)
-    # algorithmic work of one launch of that kernel on the gated frame
+    # algorithmic work of one launch of that kernel on the gated frame (the
+    # step leaves the gated frame's lists and forward outputs in place)
     last_sum = int(b.fr.last[0].to(torch.int64).sum().item())
     pairs = int(b.fr.n_pairs.item())
-    if name in OPS_PER_EVAL:
-        evals = last_sum
-        achieved = evals * OPS_PER_EVAL[name] / (kms * 1e-3) / 1e12
+    if name == "render_bwd":
+        G = b.G
+        a2 = torch.empty(b.n, dtype=torch.int32, device=b.dev)
+        w2, s2 = torch.empty(b.n, device=b.dev), torch.zeros(b.n, device=b.dev)
+        c2 = torch.zeros(b.n, dtype=torch.int32, device=b.dev)
+        cull2 = torch.zeros((b.n + 31) // 32, dtype=torch.int32, device=b.dev)
+        G.gs_importance(b.fr.proj[0].struct(), b.camc, b.n, b.fr.vals, b.fr.ranges, 0.99, 1e-6, w2, a2, s2, c2,
+                        c2.clone(), cull2, b.ws_imp)
+        composited = int(a2.to(torch.int64).sum().item())
+        ops = ALPHA_OPS * last_sum + BWD_COMPOSITED_OPS * composited
+        achieved = ops / (kms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_ALU_GOPS / 1e3, unit="TOP/s",
                     frac=achieved / (PEAK_ALU_GOPS / 1e3), traffic=None, kernel=name, ms=kms,
-                    evals=evals, ops_per_eval=OPS_PER_EVAL[name])
+                    positions=last_sum, composited=composited, ops_per_position=ALPHA_OPS,
+                    ops_per_composited=BWD_COMPOSITED_OPS)
     else:
         roof = dict(bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s", frac=None, traffic=None,
                     kernel=name, ms=kms)

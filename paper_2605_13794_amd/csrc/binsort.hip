@@ -107,26 +107,44 @@ __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ bloc
 
 __device__ __forceinline__ int64_t fdiv16(int64_t a) { return a >= 0 ? a / 16 : -((-a + 15) / 16); }
 
+// Emission: per 256 entries a block-wide scan of the tile counts gives every
+// wavefront a contiguous run of output pairs; the wavefront's lanes then write
+// consecutive pairs (each finds its entry by binary search over the 64 entry
+// starts in LDS), so large Gaussians are spread over the whole wavefront and
+// the stores are coalesced.
+struct EmitLds {
+    uint32_t start[4][65];
+    uint32_t base_tile[4][64];
+    uint32_t w[4][64];
+    uint32_t tx[4][64];
+    uint32_t dbits[4][64];
+    uint32_t j[4][64];
+};
+
 __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const uint32_t* __restrict__ block_offs,
                                               const uint32_t* __restrict__ n_sorted,
                                               uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     __shared__ uint32_t lds4[4];
+    __shared__ EmitLds L;
     if (*n_sorted == 0) return;  // nothing fits (or nothing to emit)
     const int64_t base = int64_t(blockIdx.x) * kScanItems;
+    const int w = threadIdx.x / 64;
+    const uint32_t lane = lane_id();
     uint32_t run = block_offs[blockIdx.x];
     for (int it = 0; it < kScanIters; ++it) {
         const int64_t e = base + int64_t(it) * kScanThreads + threadIdx.x;
-        const bool ok = e < n_total;
         int c = 0;
         int64_t j = 0;
         uint32_t cnt = 0;
-        if (ok) {
+        if (e < n_total) {
             c = int(e / E.n_in);
             j = e - int64_t(c) * E.n_in;
             cnt = E.tiles[c][j];
         }
         uint32_t tot;
         const uint32_t ex = block_excl_scan(cnt, lds4, &tot);
+        const uint32_t wave_ex0 = __shfl(ex, 0, 64);
+        uint32_t bt = 0, wd = 1, tx = 0, db = 0;
         if (cnt > 0) {
             const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
             const int64_t r = E.radius[c][j];
@@ -136,17 +154,37 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
             const int64_t x0 = min<int64_t>(max<int64_t>(fdiv16(xi - r), 0), TX);
             const int64_t x1 = min<int64_t>(max<int64_t>(fdiv16(xi + r) + 1, 0), TX);
             const int64_t y0 = min<int64_t>(max<int64_t>(fdiv16(yi - r), 0), TY);
-            const int64_t y1 = min<int64_t>(max<int64_t>(fdiv16(yi + r) + 1, 0), TY);
-            const uint32_t dbits = __float_as_uint(E.depth[c][j]);
-            uint32_t o = run + ex;
-            const uint32_t end = o + cnt;  // cnt == (x1-x0)*(y1-y0) by construction
-            for (int64_t ty = y0; ty < y1 && o < end; ++ty)
-                for (int64_t tx = x0; tx < x1 && o < end; ++tx, ++o) {
-                    const uint64_t tile = uint64_t(E.tile_off[c]) + uint64_t(ty * TX + tx);
-                    keys[o] = (tile << 32) | uint64_t(dbits);
-                    vals[o] = uint32_t(j);
-                }
+            bt = uint32_t(E.tile_off[c]) + uint32_t(y0 * TX + x0);
+            wd = uint32_t(max<int64_t>(x1 - x0, 1));
+            tx = uint32_t(TX);
+            db = __float_as_uint(E.depth[c][j]);
         }
+        L.start[w][lane] = ex - wave_ex0;
+        L.base_tile[w][lane] = bt;
+        L.w[w][lane] = wd;
+        L.tx[w][lane] = tx;
+        L.dbits[w][lane] = db;
+        L.j[w][lane] = uint32_t(j);
+        const uint32_t wave_tot = __shfl(ex + cnt, 63, 64) - wave_ex0;
+        if (lane == 63) L.start[w][64] = wave_tot;
+        __syncthreads();
+        const uint32_t out0 = run + wave_ex0;
+        for (uint32_t o = lane; o < wave_tot; o += 64) {
+            // last entry l with start[l] <= o (zero-count entries share the next start)
+            uint32_t lo = 0, hi = 64;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (L.start[w][mid] <= o) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t local = o - L.start[w][lo];
+            const uint32_t ww = L.w[w][lo];
+            const uint32_t dy = local / ww, dx = local - dy * ww;
+            const uint64_t tile = uint64_t(L.base_tile[w][lo] + dy * L.tx[w][lo] + dx);
+            keys[out0 + o] = (tile << 32) | uint64_t(L.dbits[w][lo]);
+            vals[out0 + o] = L.j[w][lo];
+        }
+        __syncthreads();
         run += tot;
     }
 }
@@ -155,9 +193,13 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
 // Onesweep LSD radix sort, 8-bit digits
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 256;
-constexpr int kSortPerThread = 15;
-constexpr int kPart = kSortThreads * kSortPerThread;  // 3840 keys per partition
 constexpr int kWaves = kSortThreads / 64;
+// Keys per thread: 15 (3,840-key partitions) for large pair counts, 5 (1,280)
+// when the pair buffer is small, so that enough workgroups fill the chip.
+constexpr int kIptLarge = 15;
+constexpr int kIptSmall = 5;
+constexpr int64_t kSmallSortCapacity = 2 << 20;
+constexpr int kPartMin = kSortThreads * kIptSmall;
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
@@ -166,17 +208,28 @@ constexpr uint32_t kSpinLimit = 1u << 24;
 // Global digit histograms of every pass in one read of the keys; also
 // clears the look-back status of the first pass.
 __global__ __launch_bounds__(256) void k_sort_hist(const uint64_t* __restrict__ keys,
-                                                   const uint32_t* __restrict__ n_sorted, int passes,
+                                                   const uint32_t* __restrict__ n_sorted, int passes, int part,
                                                    uint32_t* __restrict__ hist, uint32_t* __restrict__ status0) {
     __shared__ uint32_t h[8][256];
     for (int k = threadIdx.x; k < 8 * 256; k += 256) (&h[0][0])[k] = 0;
     __syncthreads();
     const uint32_t n = *n_sorted;
-    const uint32_t n_parts = (n + kPart - 1) / kPart;
+    const uint32_t n_parts = (n + part - 1) / part;
     for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const uint64_t key = keys[i];
-        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(key >> (8 * p)) & 255], 1u);
+    const uint32_t span = (n + 255) / 256 * 256;  // whole wavefronts iterate together
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < span; i += gridDim.x * 256) {
+        const bool valid = i < n;
+        const uint64_t key = valid ? keys[i] : 0ull;
+        const uint64_t vm = ballot(valid);
+        for (int p = 0; p < passes; ++p) {
+            const uint32_t d = uint32_t(key >> (8 * p)) & 255u;
+            const uint32_t d0 = __shfl(d, __ffsll((unsigned long long)vm) - 1, 64);
+            if (__all(!valid || d == d0)) {  // one digit across the wavefront: one add
+                if (vm && lane_id() == uint32_t(__ffsll((unsigned long long)vm) - 1)) atomicAdd(&h[p][d0], popc64(vm));
+            } else if (valid) {
+                atomicAdd(&h[p][d], 1u);
+            }
+        }
     }
     __syncthreads();
     for (int p = 0; p < passes; ++p) {
@@ -185,9 +238,10 @@ __global__ __launch_bounds__(256) void k_sort_hist(const uint64_t* __restrict__ 
     }
 }
 
+template <int IPT>
 struct SortLds {
-    uint64_t keys[kPart];
-    uint32_t vals[kPart];
+    uint64_t keys[kSortThreads * IPT];
+    uint32_t vals[kSortThreads * IPT];
     uint32_t wcnt[kWaves][256];
     uint32_t bin_start[256];
     uint32_t gbase[256];
@@ -196,6 +250,7 @@ struct SortLds {
     uint32_t part;
 };
 
+template <int IPT>
 __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ keys_in,
                                                    const uint32_t* __restrict__ vals_in,
                                                    uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -204,7 +259,9 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ 
                                                    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
                                                    uint32_t* __restrict__ counter, uint32_t* __restrict__ err,
                                                    int shift) {
-    __shared__ SortLds L;
+    constexpr int kSortPerThread = IPT;
+    constexpr int kPart = kSortThreads * IPT;
+    __shared__ SortLds<IPT> L;
     const uint32_t n = *n_sorted;
     const uint32_t n_parts = (n + kPart - 1) / kPart;
     const int tid = threadIdx.x;
@@ -366,7 +423,7 @@ static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity) {
     Carve cv(ws);
     SortWs s;
     const int64_t nb = (n_total + kScanItems - 1) / kScanItems + 1;
-    const int64_t np = (capacity + kPart - 1) / kPart + 1;
+    const int64_t np = (capacity + kPartMin - 1) / kPartMin + 1;
     s.block_sums = cv.take<uint32_t>(size_t(nb));
     s.n_sorted = cv.take<uint32_t>(4);
     s.hist = cv.take<uint32_t>(8 * 256);
@@ -444,18 +501,26 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     if (nb > 0)
         launch("emit", k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
                            S.n_sorted, kb[cur], vb[cur]);
-    const int64_t max_parts = (capacity + kPart - 1) / kPart;
+    const bool small = capacity <= kSmallSortCapacity;
+    const int part = kSortThreads * (small ? kIptSmall : kIptLarge);
+    const int64_t max_parts = (capacity + part - 1) / part;
     int hist_blocks = int(std::min<int64_t>(1024, (capacity + 4095) / 4096));
     if (hist_blocks < 1) hist_blocks = 1;
-    launch("sort_hist", k_sort_hist, dim3(hist_blocks), dim3(256), 0, stream, kb[cur], S.n_sorted, passes, S.hist,
-                       S.status[0]);
-    int grid = int(std::min<int64_t>(max_parts, 256 * 3));
+    launch("sort_hist", k_sort_hist, dim3(hist_blocks), dim3(256), 0, stream, kb[cur], S.n_sorted, passes, part,
+           S.hist, S.status[0]);
+    int grid = int(std::min<int64_t>(max_parts, 256 * (small ? 6 : 3)));
     if (grid < 1) grid = 1;
     for (int p = 0; p < passes; ++p) {
         const int nxt = cur ^ 1;
-        launch("sort_pass", k_sort_pass, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur], kb[nxt], vb[nxt],
-                           S.n_sorted, S.hist + p * 256, S.status[p & 1],
-                           (p + 1 < passes) ? S.status[(p + 1) & 1] : nullptr, S.counters + p, S.err, 8 * p);
+        uint32_t* st_next = (p + 1 < passes) ? S.status[(p + 1) & 1] : nullptr;
+        if (small)
+            launch("sort_pass", k_sort_pass<kIptSmall>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
+                   kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
+                   8 * p);
+        else
+            launch("sort_pass", k_sort_pass<kIptLarge>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
+                   kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
+                   8 * p);
         cur = nxt;
     }
     if ((rc = check_launch("gs_bin_sort sort"))) return rc;

@@ -1,5 +1,6 @@
 // Error reporting, workspace sizing, fill kernel, L1 loss and fused Adam.
 #include <cmath>
+#include <algorithm>
 #include <cstdarg>
 
 #include "common.h"
@@ -127,27 +128,63 @@ struct AdamGroups {
 };
 
 // Bias corrections come from the host step, or from a device step counter
-// (t = *step_dev + 1) so that a captured graph replays correct steps.
+// (t = *step_dev + 1) so that a captured graph replays correct steps.  One
+// grid row per group; float4 accesses when the group's arrays allow it.
+__device__ __forceinline__ void adam_one(float& p, float& g, float& m, float& v, bool& gz, float b1, float b2,
+                                         float eps, float lr_bc1, float inv_sqrt_bc2) {
+    gz = (g == 0.f);
+    m = fmaf(b1, m, (1.f - b1) * g);
+    v = fmaf(b2, v, (1.f - b2) * g * g);
+    p -= lr_bc1 * m / (sqrtf(v) * inv_sqrt_bc2 + eps);
+}
+
 __global__ __launch_bounds__(256) void k_adam(AdamGroups G, float b1, float b2, float eps, float inv_bc1,
                                               float inv_sqrt_bc2, int64_t total, int clear,
                                               const int32_t* __restrict__ step_dev) {
+    (void)total;
     if (step_dev) {
         const float t = float(*step_dev + 1);
         inv_bc1 = 1.f / (1.f - powf(b1, t));
         inv_sqrt_bc2 = rsqrtf(1.f - powf(b2, t));
     }
-    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
-        int k = 0;
-        while (k + 1 < G.n && e >= G.start[k + 1]) ++k;
-        int64_t i = e - G.start[k];
-        float g = G.g[k][i];
-        if (clear) G.g[k][i] = 0.f;
-        float m = fmaf(b1, G.m[k][i], (1.f - b1) * g);
-        float v = fmaf(b2, G.v[k][i], (1.f - b2) * g * g);
-        G.m[k][i] = m;
-        G.v[k][i] = v;
-        float denom = sqrtf(v) * inv_sqrt_bc2 + eps;
-        G.p[k][i] -= G.lr[k] * inv_bc1 * m / denom;
+    const int k = blockIdx.y;
+    const int64_t cnt = G.start[k + 1] - G.start[k];
+    const float lr_bc1 = G.lr[k] * inv_bc1;
+    float* __restrict__ P = G.p[k];
+    float* __restrict__ Gd = G.g[k];
+    float* __restrict__ M = G.m[k];
+    float* __restrict__ V = G.v[k];
+    const bool vec = ((reinterpret_cast<uintptr_t>(P) | reinterpret_cast<uintptr_t>(Gd) |
+                       reinterpret_cast<uintptr_t>(M) | reinterpret_cast<uintptr_t>(V)) & 15) == 0;
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    int64_t done = 0;
+    if (vec) {
+        const int64_t n4 = cnt / 4;
+        for (int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x; q < n4; q += stride) {
+            float4 p = reinterpret_cast<float4*>(P)[q];
+            float4 g = reinterpret_cast<const float4*>(Gd)[q];
+            float4 m = reinterpret_cast<float4*>(M)[q];
+            float4 v = reinterpret_cast<float4*>(V)[q];
+            bool z0, z1, z2, z3;
+            adam_one(p.x, g.x, m.x, v.x, z0, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
+            adam_one(p.y, g.y, m.y, v.y, z1, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
+            adam_one(p.z, g.z, m.z, v.z, z2, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
+            adam_one(p.w, g.w, m.w, v.w, z3, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
+            reinterpret_cast<float4*>(P)[q] = p;
+            reinterpret_cast<float4*>(M)[q] = m;
+            reinterpret_cast<float4*>(V)[q] = v;
+            if (clear && !(z0 && z1 && z2 && z3)) reinterpret_cast<float4*>(Gd)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        done = n4 * 4;
+    }
+    for (int64_t i = done + int64_t(blockIdx.x) * 256 + threadIdx.x; i < cnt; i += stride) {
+        float p = P[i], g = Gd[i], m = M[i], v = V[i];
+        bool z;
+        adam_one(p, g, m, v, z, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
+        P[i] = p;
+        M[i] = m;
+        V[i] = v;
+        if (clear && !z) Gd[i] = 0.f;
     }
 }
 
@@ -241,9 +278,13 @@ extern "C" int gs_adam_step(float* const* params, float* const* grads, float* co
     }
     const int64_t total = G.start[n_groups];
     if (total == 0) return GS_OK;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    launch("adam", k_adam, dim3(unsigned(blocks)), dim3(256), 0, stream, G, b1, b2, eps, float(1.0 / bc1),
+    int64_t maxc = 0;
+    for (int k = 0; k < n_groups; ++k) maxc = std::max<int64_t>(maxc, counts[k]);
+    int64_t blocks = (maxc / 4 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    launch("adam", k_adam, dim3(unsigned(blocks), unsigned(n_groups)), dim3(256), 0, stream, G, b1, b2, eps,
+           float(1.0 / bc1),
            float(1.0 / std::sqrt(bc2)), total, clear_grads ? 1 : 0, static_cast<const int32_t*>(step_dev));
     if (step_dev) hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(64), 0, stream, step_dev);
     return check_launch("gs_adam_step");

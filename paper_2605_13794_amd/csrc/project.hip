@@ -270,17 +270,32 @@ struct GradOut {
     float* sh;
 };
 
-__global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
-                                                     const int64_t* __restrict__ n_in_dev, CamSet C, BwdIn B,
-                                                     GradOut GO) {
+// Entries visible in at least one camera, appended to `list` (order is
+// irrelevant: entries are distinct Gaussians, so their gradients are disjoint).
+__global__ __launch_bounds__(256) void k_visible_list(int64_t n_in, const int64_t* __restrict__ n_in_dev, BwdIn B,
+                                                      int n_cams, uint32_t* __restrict__ list,
+                                                      uint32_t* __restrict__ count) {
     const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (j >= n_in) return;
     int64_t cnt = n_in;
     if (n_in_dev) cnt = min(cnt, *n_in_dev);
-    if (j >= cnt) return;
-    bool any = false;
-    for (int c = 0; c < C.n; ++c) any |= B.radius[c][j] > 0;
-    if (!any) return;
+    bool vis = false;
+    if (j < cnt)
+        for (int c = 0; c < n_cams; ++c) vis |= B.radius[c][j] > 0;
+    const uint64_t m = ballot(vis);
+    if (m == 0) return;
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(count, uint32_t(popc64(m)));
+    base = __shfl(base, 0, 64);
+    if (vis) list[base + popc64(m & lanemask_lt())] = uint32_t(j);
+}
+
+__global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
+                                                     const uint32_t* __restrict__ list,
+                                                     const uint32_t* __restrict__ count, CamSet C, BwdIn B,
+                                                     GradOut GO) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= *count) return;
+    const int64_t j = list[t];
     const int64_t i = active ? int64_t(active[j]) : j;
     if (i < 0 || i >= P.n) return;
     const int64_t N = P.n;
@@ -290,16 +305,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __
     float s[3], qn[4], R[9], M[9], S[6], qlen;
     covariance(ls, q, s, qn, R, M, S, qlen);
     const float opa = 1.f / (1.f + __expf(-P.opacity_logit[i]));
-    float sh[48];
-#pragma unroll
-    for (int k = 0; k < 48; ++k) sh[k] = P.sh[int64_t(k) * N + i];
 
     float dmu[3] = {0.f, 0.f, 0.f};
     float dS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric: 00 01 02 11 12 22
     float dlogit = 0.f;
-    float dsh[48];
-#pragma unroll
-    for (int k = 0; k < 48; ++k) dsh[k] = 0.f;
 
     for (int c = 0; c < C.n; ++c) {
         if (B.radius[c][j] <= 0) continue;
@@ -369,13 +378,19 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch)
             if (cb & (1u << ch)) drgb[ch] = 0.f;
+        // SH coefficients are streamed: d sh = d rgb * Y goes straight to the
+        // gradient (accumulated per camera), sh only feeds the direction term.
         float wsum[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            dsh[k * 3 + 0] += drgb[0] * Y[k];
-            dsh[k * 3 + 1] += drgb[1] * Y[k];
-            dsh[k * 3 + 2] += drgb[2] * Y[k];
-            wsum[k] = drgb[0] * sh[k * 3 + 0] + drgb[1] * sh[k * 3 + 1] + drgb[2] * sh[k * 3 + 2];
+            float acc = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const int64_t o = int64_t(k * 3 + ch) * N + i;
+                acc = fmaf(drgb[ch], P.sh[o], acc);
+                GO.sh[o] += drgb[ch] * Y[k];
+            }
+            wsum[k] = acc;
         }
         float gd[3];
         sh_basis_grad(x, y, z, wsum, gd);
@@ -415,8 +430,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __
         GO.log_scale[int64_t(k) * N + i] += dls[k];
     }
     GO.opacity_logit[i] += dlogit;
-#pragma unroll
-    for (int k = 0; k < 48; ++k) GO.sh[int64_t(k) * N + i] += dsh[k];
 }
 
 int fill_camset(const gs_camera* cams, int n_cams, CamSet& C) {
@@ -443,7 +456,7 @@ static int scene_ok(const gs_scene* s) {
 
 int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
                        const gs_camera* cams, int n_cams, const float* const* d2, const gs_projected* proj,
-                       const gs_grads* grads, hipStream_t stream) {
+                       const gs_grads* grads, uint32_t* list, uint32_t* count, hipStream_t stream) {
     CamSet C;
     int rc = fill_camset(cams, n_cams, C);
     if (rc) return rc;
@@ -457,8 +470,12 @@ int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t
     }
     GradOut G{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh};
     if (n_in == 0) return GS_OK;
+    int rc2 = fill_u32(count, 0u, 1, stream);
+    if (rc2) return rc2;
+    launch("visible_list", k_visible_list, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, n_in, n_in_dev, B,
+           n_cams, list, count);
     launch("project_bwd", k_project_bwd, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx,
-                       n_in, n_in_dev, C, B, G);
+           n_in, static_cast<const uint32_t*>(list), static_cast<const uint32_t*>(count), C, B, G);
     return check_launch("project backward");
 }
 

@@ -413,7 +413,7 @@ int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, cons
 
 int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
                        const gs_camera* cams, int n_cams, const float* const* d2, const gs_projected* proj,
-                       const gs_grads* grads, hipStream_t stream);
+                       const gs_grads* grads, uint32_t* list, uint32_t* count, hipStream_t stream);
 int check_scene(const gs_scene* s);
 
 }  // namespace gsmi
@@ -423,6 +423,8 @@ using namespace gsmi;
 size_t ws_render_bwd(int64_t n, int n_cams) {
     Carve cv(nullptr);
     cv.take<float>(size_t(9) * size_t(n > 0 ? n : 1) * size_t(n_cams));
+    cv.take<uint32_t>(size_t(n > 0 ? n : 1));
+    cv.take<uint32_t>(4);
     return cv.used();
 }
 
@@ -476,7 +478,10 @@ extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, i
     BwdImg I;
     memset(&I, 0, sizeof(I));
     const float* d2c[GS_MAX_CAMS];
-    float* base = static_cast<float*>(ws);
+    Carve cv(ws);
+    float* base = cv.take<float>(size_t(9) * size_t(n_in > 0 ? n_in : 1) * size_t(n_cams));
+    uint32_t* vis_list = cv.take<uint32_t>(size_t(n_in > 0 ? n_in : 1));
+    uint32_t* vis_count = cv.take<uint32_t>(4);
     for (int c = 0; c < n_cams; ++c) {
         if (!out_T[c] || !out_last[c] || !grad_rgb[c]) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: null image");
         I.T[c] = out_T[c]; I.last[c] = out_last[c]; I.grad[c] = grad_rgb[c];
@@ -497,5 +502,6 @@ extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, i
                    uint32_t(tt), I);
     }
     if ((rc = check_launch("gs_render_bwd blend"))) return rc;
-    return launch_project_bwd(scene, active_idx, n_in, n_in_dev, cams, n_cams, d2c, proj, grads, stream);
+    return launch_project_bwd(scene, active_idx, n_in, n_in_dev, cams, n_cams, d2c, proj, grads, vis_list, vis_count,
+                              stream);
 }

@@ -181,22 +181,131 @@ struct SelState {
     uint64_t k_rem;        // count mode: rank still to place inside the prefix range
 };
 
-// mode 0: mass (w > 0, descending), mode 1: count (ascending).
-__global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ v, int64_t n, int shift,
-                                                  const SelState* __restrict__ st, uint32_t* __restrict__ hcnt,
-                                                  double* __restrict__ hmass, double* __restrict__ total, int mode) {
+// Histograms of the 4 digit passes (8 bits each, most significant first).
+struct SelHist {
+    uint32_t cnt[4][256];
+    double mass[4][256];
+};
+
+// One digit pick, computed by all 256 threads of a block from that pass's
+// histogram; updates the shared state `s` (mode 0: top mass, mode 1: k-th
+// smallest).  Every block computes the same result.
+__device__ void block_pick(const uint32_t* __restrict__ hc, const double* __restrict__ hm, SelState& s, int shift,
+                          int mode, double* sd, unsigned long long* su, int* si) {
+    const int b = threadIdx.x;
+    const uint32_t c = hc[b];
+    if (mode == 0) {
+        // suffix sums of the bin masses: sd[b] = sum over bins >= b
+        sd[b] = hm[b];
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const double v = (b + o < 256) ? sd[b + o] : 0.0;
+            __syncthreads();
+            sd[b] += v;
+            __syncthreads();
+        }
+        if (b == 0) { si[0] = -1; si[1] = 256; }
+        __syncthreads();
+        const bool ok = s.active && c > 0 && (s.mass_above + sd[b] >= s.target);
+        if (ok) atomicMax(&si[0], b);
+        if (s.active && c > 0) atomicMin(&si[1], b);
+        __syncthreads();
+        if (b == 0 && s.active) {
+            int chosen = si[0] >= 0 ? si[0] : (si[1] < 256 ? si[1] : -1);  // rounding left the total short
+            if (chosen < 0) {
+                s.active = 0;
+            } else {
+                s.mass_above += (chosen < 255) ? sd[chosen + 1] : 0.0;
+                s.prefix |= uint32_t(chosen) << shift;
+                s.done_bits += 8;
+                if (shift == 0) {
+                    s.cnt_eq = hc[chosen];
+                    const double tau = double(__uint_as_float(s.prefix));
+                    double need = ceil((s.target - s.mass_above) / tau);
+                    if (need < 1.0) need = 1.0;
+                    if (need > double(s.cnt_eq)) need = double(s.cnt_eq);
+                    s.need_eq = uint32_t(need);
+                    s.take_all_eq = s.need_eq >= s.cnt_eq ? 1u : 0u;
+                }
+            }
+        }
+    } else {
+        // exclusive prefix counts: su[b] = sum over bins < b
+        su[b] = c;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const unsigned long long v = (b >= o) ? su[b - o] : 0ull;
+            __syncthreads();
+            su[b] += v;
+            __syncthreads();
+        }
+        const unsigned long long excl = su[b] - c;
+        if (b == 0) si[0] = 256;
+        __syncthreads();
+        if (s.active && excl + c >= s.k_rem) atomicMin(&si[0], b);
+        __syncthreads();
+        if (b == 0 && s.active) {
+            const int chosen = si[0];
+            if (chosen >= 256) {
+                s.active = 0;
+            } else {
+                s.k_rem -= (su[chosen] - hc[chosen]);
+                s.prefix |= uint32_t(chosen) << shift;
+                s.done_bits += 8;
+                if (shift == 0) {
+                    s.cnt_eq = hc[chosen];
+                    s.need_eq = uint32_t(s.k_rem);
+                    s.take_all_eq = s.need_eq >= s.cnt_eq ? 1u : 0u;
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ void init_state(SelState& s, int mode, double total, float frac, uint64_t k) {
+    memset(&s, 0, sizeof(s));
+    if (mode == 0) {
+        s.target = double(frac) * total;
+        s.active = total > 0.0 ? 1u : 0u;
+    } else {
+        s.k_rem = k;
+        s.active = k > 0 ? 1u : 0u;
+    }
+}
+
+// Histogram of digit pass `pass` (shift 24 - 8 pass) over the elements whose
+// higher digits match the picks of the earlier passes (replayed per block).
+// mode 0 also sums the total mass in pass 0.
+__global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ v, int64_t n, int pass,
+                                                  SelHist* __restrict__ H, double* __restrict__ total, int mode,
+                                                  float frac, uint64_t k) {
     __shared__ uint32_t lc[256];
     __shared__ double lm[256];
+    __shared__ double sd[256];
+    __shared__ unsigned long long su[256];
+    __shared__ int si[2];
+    __shared__ SelState st;
+    const int shift = 24 - 8 * pass;
+    if (pass > 0) {
+        if (threadIdx.x == 0) init_state(st, mode, *total, frac, k);
+        __syncthreads();
+        for (int p = 0; p < pass; ++p) block_pick(H->cnt[p], H->mass[p], st, 24 - 8 * p, mode, sd, su, si);
+    } else if (threadIdx.x == 0) {
+        memset(&st, 0, sizeof(st));
+        st.active = 1;
+    }
     lc[threadIdx.x] = 0;
     lm[threadIdx.x] = 0.0;
     __syncthreads();
-    const uint32_t pre = st->prefix;
+    if (!st.active) return;
+    const uint32_t pre = st.prefix;
     const uint32_t hi_mask = shift >= 24 ? 0u : (0xffffffffu << (shift + 8));
     double tsum = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
         const float x = v[i];
         if (mode == 0 && !(x > 0.f)) continue;
-        if (mode == 0 && shift == 24) tsum += double(x);
+        if (mode == 0 && pass == 0) tsum += double(x);
         const uint32_t b = __float_as_uint(x);
         if ((b & hi_mask) != (pre & hi_mask)) continue;
         const uint32_t d = (b >> shift) & 255u;
@@ -205,98 +314,39 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ v, i
     }
     __syncthreads();
     if (lc[threadIdx.x]) {
-        atomicAdd(&hcnt[threadIdx.x], lc[threadIdx.x]);
-        if (mode == 0) atomicAdd(&hmass[threadIdx.x], lm[threadIdx.x]);
+        atomicAdd(&H->cnt[pass][threadIdx.x], lc[threadIdx.x]);
+        if (mode == 0) atomicAdd(&H->mass[pass][threadIdx.x], lm[threadIdx.x]);
     }
-    if (mode == 0 && shift == 24) {
-        // block sum of tsum
-        __shared__ double red[256];
-        red[threadIdx.x] = tsum;
+    if (mode == 0 && pass == 0) {
+        sd[threadIdx.x] = tsum;
         __syncthreads();
         for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            if (threadIdx.x < o) sd[threadIdx.x] += sd[threadIdx.x + o];
             __syncthreads();
         }
-        if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(total, red[0]);
+        if (threadIdx.x == 0 && sd[0] != 0.0) atomicAdd(total, sd[0]);
     }
 }
 
-// One thread: choose the digit bin, update the state, clear the histogram.
-__global__ void k_sel_pick(SelState* __restrict__ st, uint32_t* __restrict__ hcnt, double* __restrict__ hmass,
-                           const double* __restrict__ total, int shift, int mode, float frac) {
-    if (threadIdx.x != 0) return;
-    SelState s = *st;
-    if (shift == 24) {
-        if (mode == 0) {
-            s.target = double(frac) * (*total);
-            s.mass_above = 0.0;
-            s.active = (*total > 0.0) ? 1u : 0u;
-        }
-    }
-    if (s.active) {
-        int chosen = -1;
-        if (mode == 0) {
-            double acc = s.mass_above;
-            int lowest = -1;
-            for (int b = 255; b >= 0; --b) {
-                if (hcnt[b] == 0) continue;
-                lowest = b;
-                if (acc + hmass[b] >= s.target) { chosen = b; break; }
-                acc += hmass[b];
-            }
-            if (chosen < 0) {  // rounding left the total just short: take the smallest bin
-                chosen = lowest;
-                acc = s.mass_above;
-                for (int b = 255; b > chosen; --b) acc += hmass[b];
-            }
-            if (chosen < 0) {
-                s.active = 0;
-            } else {
-                s.mass_above = acc;
-            }
-        } else {
-            uint64_t acc = 0;
-            for (int b = 0; b < 256; ++b) {
-                if (acc + hcnt[b] >= s.k_rem) { chosen = b; break; }
-                acc += hcnt[b];
-            }
-            if (chosen < 0) s.active = 0;
-            else s.k_rem -= acc;
-        }
-        if (chosen >= 0) {
-            s.prefix |= uint32_t(chosen) << shift;
-            s.done_bits += 8;
-            if (shift == 0) {
-                s.cnt_eq = hcnt[chosen];
-                if (mode == 0) {
-                    const double tau = double(__uint_as_float(s.prefix));
-                    double need = ceil((s.target - s.mass_above) / tau);
-                    if (need < 1.0) need = 1.0;
-                    if (need > double(s.cnt_eq)) need = double(s.cnt_eq);
-                    s.need_eq = uint32_t(need);
-                } else {
-                    s.need_eq = uint32_t(s.k_rem);
-                }
-                s.take_all_eq = s.need_eq >= s.cnt_eq ? 1u : 0u;
-            }
-        }
-    }
-    for (int b = 0; b < 256; ++b) { hcnt[b] = 0; hmass[b] = 0.0; }
-    *st = s;
+// Final state from the four histograms (one block).
+__global__ __launch_bounds__(256) void k_sel_final(const SelHist* __restrict__ H, const double* __restrict__ total,
+                                                   SelState* __restrict__ out, int mode, float frac, uint64_t k) {
+    __shared__ double sd[256];
+    __shared__ unsigned long long su[256];
+    __shared__ int si[2];
+    __shared__ SelState st;
+    if (threadIdx.x == 0) init_state(st, mode, *total, frac, k);
+    __syncthreads();
+    for (int p = 0; p < 4; ++p) block_pick(H->cnt[p], H->mass[p], st, 24 - 8 * p, mode, sd, su, si);
+    if (threadIdx.x == 0) *out = st;
 }
 
-__global__ void k_sel_init(SelState* __restrict__ st, uint32_t* __restrict__ hcnt, double* __restrict__ hmass,
-                           double* __restrict__ total, int mode, uint64_t k) {
-    if (threadIdx.x == 0) {
-        SelState s;
-        memset(&s, 0, sizeof(s));
-        s.active = mode == 1 ? (k > 0 ? 1u : 0u) : 0u;
-        s.k_rem = k;
-        *st = s;
-        *total = 0.0;
+__global__ void k_sel_init(SelHist* __restrict__ H, double* __restrict__ total) {
+    for (int k = threadIdx.x; k < 4 * 256; k += blockDim.x) {
+        (&H->cnt[0][0])[k] = 0;
+        (&H->mass[0][0])[k] = 0.0;
     }
-    hcnt[threadIdx.x] = 0;
-    hmass[threadIdx.x] = 0.0;
+    if (threadIdx.x == 0) *total = 0.0;
 }
 
 // Per-block count of elements equal to the threshold (only when ranks matter).
@@ -429,8 +479,7 @@ __global__ __launch_bounds__(256) void k_compact_arrays(CompactArgs A, const uin
 
 struct SelWs {
     SelState* st;
-    uint32_t* hcnt;
-    double* hmass;
+    SelHist* hist;
     double* total;
     uint32_t* eq_cnt;
     uint64_t* tot64;
@@ -441,8 +490,7 @@ static SelWs carve_sel(Carve& cv, int64_t n) {
     SelWs s;
     const int64_t nb = (n + kBlk - 1) / kBlk + 1;
     s.st = cv.take<SelState>(1);
-    s.hcnt = cv.take<uint32_t>(256);
-    s.hmass = cv.take<double>(256);
+    s.hist = cv.take<SelHist>(1);
     s.total = cv.take<double>(1);
     s.eq_cnt = cv.take<uint32_t>(size_t(nb));
     s.tot64 = cv.take<uint64_t>(1);
@@ -453,11 +501,10 @@ static SelWs carve_sel(Carve& cv, int64_t n) {
 static int run_select(const float* v, int64_t n, int mode, float frac, uint64_t k, const SelWs& W, hipStream_t s) {
     const int64_t nb = (n + kBlk - 1) / kBlk;
     const int hb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096)));
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, W.st, W.hcnt, W.hmass, W.total, mode, k);
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        launch("sel_hist", k_sel_hist, dim3(hb), dim3(256), 0, s, v, n, shift, W.st, W.hcnt, W.hmass, W.total, mode);
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, s, W.st, W.hcnt, W.hmass, W.total, shift, mode, frac);
-    }
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, W.hist, W.total);
+    for (int pass = 0; pass < 4; ++pass)
+        launch("sel_hist", k_sel_hist, dim3(hb), dim3(256), 0, s, v, n, pass, W.hist, W.total, mode, frac, k);
+    hipLaunchKernelGGL(k_sel_final, dim3(1), dim3(256), 0, s, W.hist, W.total, W.st, mode, frac, k);
     if (nb > 0) {
         hipLaunchKernelGGL(k_eq_count, dim3(unsigned(nb)), dim3(256), 0, s, v, n, W.st, W.eq_cnt);
         hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, s, W.eq_cnt, nb, W.tot64);
