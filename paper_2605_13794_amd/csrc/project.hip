@@ -178,17 +178,32 @@ __global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __rest
     }
     const int64_t N = P.n;
     float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
-    bool any = false;
+    const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
+    // Conservative pre-cull per camera: the largest eigenvalue of the screen
+    // covariance is at most s_max^2 |J|_F^2 + 0.3 (the camera rotation is
+    // orthonormal), so a centre farther off-screen than that 3-sigma bound
+    // (+1 px for the ceiling and rounding) has an empty tile rectangle.
+    const float smax2 = __expf(2.f * fmaxf(fmaxf(ls[0], ls[1]), ls[2]));
+    uint32_t maybe = 0;
     for (int c = 0; c < C.n; ++c) {
         const DevCam& K = C.cam[c];
-        const float tz = fmaf(K.R[6], mu[0], fmaf(K.R[7], mu[1], fmaf(K.R[8], mu[2], K.t[2])));
-        any |= tz > K.znear;
+        Geo G0;
+        geo_camera(K, mu, G0);
+        if (!(G0.tz > K.znear)) continue;
+        const float rz = 1.f / G0.tz;
+        const float ux = fminf(fmaxf(G0.tx * rz, -K.limx), K.limx);
+        const float uy = fminf(fmaxf(G0.ty * rz, -K.limy), K.limy);
+        const float F = (K.fx * rz) * (K.fx * rz) * (1.f + ux * ux) + (K.fy * rz) * (K.fy * rz) * (1.f + uy * uy);
+        const float rb = 3.f * sqrtf(smax2 * F + kDilation) * 1.001f + 2.f;
+        const float mx = fmaf(K.fx, G0.tx * rz, K.cx), my = fmaf(K.fy, G0.ty * rz, K.cy);
+        const bool off = (mx + rb < -1.f) || (mx - rb > float(K.TX * GS_TILE) + 1.f) || (my + rb < -1.f) ||
+                         (my - rb > float(K.TY * GS_TILE) + 1.f);
+        if (!off) maybe |= 1u << c;
     }
-    if (!any) {
+    if (!maybe) {
         for (int c = 0; c < C.n; ++c) culled_out(O, c, j, n_in);
         return;
     }
-    const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
     const float q[4] = {P.quat[i], P.quat[N + i], P.quat[2 * N + i], P.quat[3 * N + i]};
     float s[3], qn[4], R[9], M[9], S[6], qlen;
     covariance(ls, q, s, qn, R, M, S, qlen);
@@ -199,7 +214,7 @@ __global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __rest
         const DevCam& K = C.cam[c];
         Geo G;
         geo_camera(K, mu, G);
-        if (!(G.tz > K.znear)) { culled_out(O, c, j, n_in); continue; }
+        if (!((maybe >> c) & 1u) || !(G.tz > K.znear)) { culled_out(O, c, j, n_in); continue; }
         geo_cov(K, S, G);
         if (!(G.det > 0.f)) { culled_out(O, c, j, n_in); continue; }
         const float idet = 1.f / G.det;
