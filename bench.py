@@ -177,11 +177,11 @@ class Bench:
         scn = self.ds.struct()
         self.fr_all.project(scn)
         K_all = self.fr_all.bin_sort(check=True)
-        self.fr_all.ensure_capacity(int(K_all * 1.25) + 4096)
+        self.fr_all.set_capacity(int(K_all * 1.25) + 4096)
         self.gate()
         self.fr.project(scn, self.active, self.n, self.n_act)
         K = self.fr.bin_sort(check=True)
-        self.fr.ensure_capacity(int(K * 1.25) + 4096)
+        self.fr.set_capacity(int(K * 1.25) + 4096)
         self.torch.cuda.synchronize()
         return K_all, K
 

@@ -127,7 +127,8 @@ enum {
     GS_OP_L1_LOSS = 5,
     GS_OP_SIMPLIFY = 6,
     GS_OP_PHOTO_LOSS = 7, /* n = width * 65536 + height */
-    GS_OP_SCALE_REG = 8
+    GS_OP_SCALE_REG = 8,
+    GS_OP_PROJECT = 9
 };
 
 /* Bytes of workspace `op` needs for n Gaussians (per camera), n_pairs pair
@@ -177,11 +178,12 @@ int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs_lod_params
  * transform, near cull, EWA Jacobian (off-axis clamp 1.3x the half field of
  * view), screen covariance + 0.3 I, conic, radius ceil(3 sqrt(lambda_max)),
  * 16x16 tile rectangle, SH degree-3 colour + 0.5 clamped at 0, depth.
- * out[c] receives camera c.  n_cams <= GS_MAX_CAMS.
+ * out[c] receives camera c.  n_cams <= GS_MAX_CAMS.  Workspace: GS_OP_PROJECT
+ * (n = n_in).
  */
 int gs_project(const gs_scene* scene, const int32_t* active_idx, int64_t n_in,
                const int64_t* n_in_dev, const gs_camera* cams, int n_cams,
-               const gs_projected* out, hipStream_t stream);
+               const gs_projected* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Tile binning and depth sort (Appendix A: the depth-ordered Gaussians of each

@@ -9,7 +9,7 @@ namespace gsmi {
 // Emission
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = 256;
-constexpr int kScanIters = 16;
+constexpr int kScanIters = 4;
 constexpr int kScanItems = kScanThreads * kScanIters;  // entries per block
 
 struct EmitIn {

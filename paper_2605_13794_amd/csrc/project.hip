@@ -164,25 +164,12 @@ __device__ __forceinline__ void culled_out(const ProjOut& O, int c, int64_t j, i
     if (O.rgb[c]) { O.rgb[c][j] = 0.f; O.rgb[c][n + j] = 0.f; O.rgb[c][2 * n + j] = 0.f; }
 }
 
-__global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
-                                                 const int64_t* __restrict__ n_in_dev, CamSet C, ProjOut O) {
-    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (j >= n_in) return;
-    int64_t cnt = n_in;
-    if (n_in_dev) cnt = min(cnt, *n_in_dev);
-    int64_t i = j;
-    if (active) i = j < cnt ? int64_t(active[j]) : -1;
-    if (j >= cnt || i < 0 || i >= P.n) {
-        for (int c = 0; c < C.n; ++c) culled_out(O, c, j, n_in);
-        return;
-    }
-    const int64_t N = P.n;
-    float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
-    const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
-    // Conservative pre-cull per camera: the largest eigenvalue of the screen
-    // covariance is at most s_max^2 |J|_F^2 + 0.3 (the camera rotation is
-    // orthonormal), so a centre farther off-screen than that 3-sigma bound
-    // (+1 px for the ceiling and rounding) has an empty tile rectangle.
+// Conservative pre-cull per camera: the largest eigenvalue of the screen
+// covariance is at most s_max^2 |J|_F^2 + 0.3 (the camera rotation is
+// orthonormal), so a centre farther off-screen than that 3-sigma bound
+// (+1 px for the ceiling and rounding) has an empty tile rectangle.
+// Returns the cameras in which the Gaussian may be visible.
+__device__ __forceinline__ uint32_t maybe_visible(const CamSet& C, const float mu[3], const float ls[3]) {
     const float smax2 = __expf(2.f * fmaxf(fmaxf(ls[0], ls[1]), ls[2]));
     uint32_t maybe = 0;
     for (int c = 0; c < C.n; ++c) {
@@ -200,10 +187,75 @@ __global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __rest
                          (my - rb > float(K.TY * GS_TILE) + 1.f);
         if (!off) maybe |= 1u << c;
     }
-    if (!maybe) {
-        for (int c = 0; c < C.n; ++c) culled_out(O, c, j, n_in);
-        return;
+    return maybe;
+}
+
+// Pass 1 (low register count): entries that cannot be visible in any camera
+// get their culled outputs; the others are appended to `list` (one atomic per
+// workgroup of kCullChunk entries).
+constexpr int kCullChunk = 2048;
+
+__global__ __launch_bounds__(256) void k_project_cull(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
+                                                      const int64_t* __restrict__ n_in_dev, CamSet C, ProjOut O,
+                                                      uint32_t* __restrict__ list, uint32_t* __restrict__ count) {
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t base_s;
+    int64_t cnt = n_in;
+    if (n_in_dev) cnt = min(cnt, *n_in_dev);
+    const int64_t j0 = int64_t(blockIdx.x) * kCullChunk;
+    const int w = threadIdx.x / 64;
+    const int64_t N = P.n;
+    constexpr int kIt = kCullChunk / 256;
+    uint32_t keep_bits = 0;  // per iteration: this thread's entry is a candidate
+    uint32_t mine = 0;
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int64_t j = j0 + it * 256 + threadIdx.x;
+        bool cand = false;
+        if (j < n_in) {
+            int64_t i = j;
+            if (active) i = j < cnt ? int64_t(active[j]) : -1;
+            if (j < cnt && i >= 0 && i < N) {
+                const float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
+                const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
+                cand = maybe_visible(C, mu, ls) != 0;
+            }
+            if (!cand)
+                for (int c = 0; c < C.n; ++c) culled_out(O, c, j, n_in);
+        }
+        keep_bits |= uint32_t(cand) << it;
+        mine += popc64(ballot(cand));
     }
+    if (lane_id() == 0) wsum[w] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base_s = tot ? atomicAdd(count, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t off = base_s;
+    for (int k = 0; k < w; ++k) off += wsum[k];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const bool cand = (keep_bits >> it) & 1u;
+        const uint64_t m = ballot(cand);
+        if (cand) list[off + popc64(m & lanemask_lt())] = uint32_t(j0 + it * 256 + threadIdx.x);
+        off += popc64(m);
+    }
+}
+
+// Pass 2: full projection of the candidates.
+__global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
+                                                 const uint32_t* __restrict__ list,
+                                                 const uint32_t* __restrict__ count, CamSet C, ProjOut O) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= *count) return;
+    const int64_t j = list[t];
+    const int64_t i = active ? int64_t(active[j]) : j;
+    const int64_t N = P.n;
+    float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
+    const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
+    const uint32_t maybe = maybe_visible(C, mu, ls);
     const float q[4] = {P.quat[i], P.quat[N + i], P.quat[2 * N + i], P.quat[3 * N + i]};
     float s[3], qn[4], R[9], M[9], S[6], qlen;
     covariance(ls, q, s, qn, R, M, S, qlen);
@@ -287,21 +339,45 @@ struct GradOut {
 
 // Entries visible in at least one camera, appended to `list` (order is
 // irrelevant: entries are distinct Gaussians, so their gradients are disjoint).
+// One workgroup handles kVisChunk entries: it counts them, reserves its slice
+// with a single atomic, then writes them (two reads of the radius values).
+constexpr int kVisChunk = 4096;
+
 __global__ __launch_bounds__(256) void k_visible_list(int64_t n_in, const int64_t* __restrict__ n_in_dev, BwdIn B,
                                                       int n_cams, uint32_t* __restrict__ list,
                                                       uint32_t* __restrict__ count) {
-    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t base_s;
     int64_t cnt = n_in;
     if (n_in_dev) cnt = min(cnt, *n_in_dev);
-    bool vis = false;
-    if (j < cnt)
-        for (int c = 0; c < n_cams; ++c) vis |= B.radius[c][j] > 0;
-    const uint64_t m = ballot(vis);
-    if (m == 0) return;
-    uint32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(count, uint32_t(popc64(m)));
-    base = __shfl(base, 0, 64);
-    if (vis) list[base + popc64(m & lanemask_lt())] = uint32_t(j);
+    const int64_t j0 = int64_t(blockIdx.x) * kVisChunk;
+    const int w = threadIdx.x / 64;
+    uint32_t mine = 0;
+    for (int it = 0; it < kVisChunk / 256; ++it) {
+        const int64_t j = j0 + it * 256 + threadIdx.x;
+        bool vis = false;
+        if (j < cnt)
+            for (int c = 0; c < n_cams; ++c) vis |= B.radius[c][j] > 0;
+        mine += popc64(ballot(vis));
+    }
+    if (lane_id() == 0) wsum[w] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base_s = tot ? atomicAdd(count, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t off = base_s;
+    for (int k = 0; k < w; ++k) off += wsum[k];
+    for (int it = 0; it < kVisChunk / 256; ++it) {
+        const int64_t j = j0 + it * 256 + threadIdx.x;
+        bool vis = false;
+        if (j < cnt)
+            for (int c = 0; c < n_cams; ++c) vis |= B.radius[c][j] > 0;
+        const uint64_t m = ballot(vis);
+        if (vis) list[off + popc64(m & lanemask_lt())] = uint32_t(j);
+        off += popc64(m);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
@@ -383,36 +459,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __
         dmu[0] += K.R[0] * dtx + K.R[3] * dty + K.R[6] * dtz;
         dmu[1] += K.R[1] * dtx + K.R[4] * dty + K.R[7] * dtz;
         dmu[2] += K.R[2] * dtx + K.R[5] * dty + K.R[8] * dtz;
-        // colour
-        const float vx = mu[0] - K.campos[0], vy = mu[1] - K.campos[1], vz = mu[2] - K.campos[2];
-        const float len = sqrtf(vx * vx + vy * vy + vz * vz);
-        const float il = 1.f / len;
-        const float x = vx * il, y = vy * il, z = vz * il;
-        float Y[16];
-        sh_basis(x, y, z, Y);
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-            if (cb & (1u << ch)) drgb[ch] = 0.f;
-        // SH coefficients are streamed: d sh = d rgb * Y goes straight to the
-        // gradient (accumulated per camera), sh only feeds the direction term.
-        float wsum[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            float acc = 0.f;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const int64_t o = int64_t(k * 3 + ch) * N + i;
-                acc = fmaf(drgb[ch], P.sh[o], acc);
-                GO.sh[o] += drgb[ch] * Y[k];
-            }
-            wsum[k] = acc;
-        }
-        float gd[3];
-        sh_basis_grad(x, y, z, wsum, gd);
-        const float dot = gd[0] * x + gd[1] * y + gd[2] * z;
-        dmu[0] += (gd[0] - dot * x) * il;
-        dmu[1] += (gd[1] - dot * y) * il;
-        dmu[2] += (gd[2] - dot * z) * il;
+        (void)drgb;
+        (void)cb;
     }
     // Sigma = M M^T: dM = 2 dSigma_sym M
     const float D[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
@@ -445,6 +493,56 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __
         GO.log_scale[int64_t(k) * N + i] += dls[k];
     }
     GO.opacity_logit[i] += dlogit;
+}
+
+// Colour part of the backward: d sh = d rgb * Y (zero on clamped channels),
+// and the view-direction term of the mean gradient through the SH basis.
+__global__ __launch_bounds__(256) void k_project_bwd_sh(SceneP P, const int32_t* __restrict__ active,
+                                                        int64_t n_in, const uint32_t* __restrict__ list,
+                                                        const uint32_t* __restrict__ count, CamSet C, BwdIn B,
+                                                        GradOut GO) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= *count) return;
+    const int64_t j = list[t];
+    const int64_t i = active ? int64_t(active[j]) : j;
+    if (i < 0 || i >= P.n) return;
+    const int64_t N = P.n;
+    const float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
+    float dmu[3] = {0.f, 0.f, 0.f};
+    for (int c = 0; c < C.n; ++c) {
+        if (B.radius[c][j] <= 0) continue;
+        const DevCam& K = C.cam[c];
+        const float* d2 = B.d2[c];
+        const uint8_t cb = B.clamp[c][j];
+        float drgb[3] = {d2[6 * n_in + j], d2[7 * n_in + j], d2[8 * n_in + j]};
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+            if (cb & (1u << ch)) drgb[ch] = 0.f;
+        const float vx = mu[0] - K.campos[0], vy = mu[1] - K.campos[1], vz = mu[2] - K.campos[2];
+        const float il = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
+        const float x = vx * il, y = vy * il, z = vz * il;
+        float Y[16];
+        sh_basis(x, y, z, Y);
+        float wsum[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            float acc = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const int64_t o = int64_t(k * 3 + ch) * N + i;
+                acc = fmaf(drgb[ch], P.sh[o], acc);
+                GO.sh[o] += drgb[ch] * Y[k];
+            }
+            wsum[k] = acc;
+        }
+        float gd[3];
+        sh_basis_grad(x, y, z, wsum, gd);
+        const float dot = gd[0] * x + gd[1] * y + gd[2] * z;
+        dmu[0] += (gd[0] - dot * x) * il;
+        dmu[1] += (gd[1] - dot * y) * il;
+        dmu[2] += (gd[2] - dot * z) * il;
+    }
+    for (int k = 0; k < 3; ++k) GO.mean[int64_t(k) * N + i] += dmu[k];
 }
 
 int fill_camset(const gs_camera* cams, int n_cams, CamSet& C) {
@@ -487,10 +585,12 @@ int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t
     if (n_in == 0) return GS_OK;
     int rc2 = fill_u32(count, 0u, 1, stream);
     if (rc2) return rc2;
-    launch("visible_list", k_visible_list, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, n_in, n_in_dev, B,
-           n_cams, list, count);
+    launch("visible_list", k_visible_list, dim3(unsigned((n_in + kVisChunk - 1) / kVisChunk)), dim3(256), 0, stream,
+           n_in, n_in_dev, B, n_cams, list, count);
     launch("project_bwd", k_project_bwd, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx,
            n_in, static_cast<const uint32_t*>(list), static_cast<const uint32_t*>(count), C, B, G);
+    launch("project_bwd_sh", k_project_bwd_sh, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P,
+           active_idx, n_in, static_cast<const uint32_t*>(list), static_cast<const uint32_t*>(count), C, B, G);
     return check_launch("project backward");
 }
 
@@ -500,8 +600,16 @@ int check_scene(const gs_scene* s) { return scene_ok(s); }
 
 using namespace gsmi;
 
+size_t ws_project(int64_t n_in) {
+    Carve cv(nullptr);
+    cv.take<uint32_t>(size_t(n_in > 0 ? n_in : 1));
+    cv.take<uint32_t>(4);
+    return cv.used();
+}
+
 extern "C" int gs_project(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
-                          const gs_camera* cams, int n_cams, const gs_projected* out, hipStream_t stream) {
+                          const gs_camera* cams, int n_cams, const gs_projected* out, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
     int rc = scene_ok(scene);
     if (rc) return rc;
     if (n_in < 0 || n_in >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_project: n_in out of range");
@@ -521,9 +629,18 @@ extern "C" int gs_project(const gs_scene* scene, const int32_t* active_idx, int6
         O.clamp[c] = p.clamp_bits; O.mean2d[c] = p.mean2d; O.conic[c] = p.conic; O.opacity[c] = p.opacity;
         O.rgb[c] = p.rgb;
     }
+    const size_t need = ws_project(n_in);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_project: workspace needs %zu bytes (256-aligned)", need);
     if (n_in == 0) return GS_OK;
     SceneP P{scene->mean, scene->log_scale, scene->quat, scene->opacity_logit, scene->sh, scene->n};
+    Carve cv(ws);
+    uint32_t* list = cv.take<uint32_t>(size_t(n_in));
+    uint32_t* count = cv.take<uint32_t>(4);
+    if ((rc = fill_u32(count, 0u, 1, stream))) return rc;
+    launch("project_cull", k_project_cull, dim3(unsigned((n_in + kCullChunk - 1) / kCullChunk)), dim3(256), 0, stream,
+           P, active_idx, n_in, n_in_dev, C, O, list, count);
     launch("project", k_project, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx, n_in,
-                       n_in_dev, C, O);
+           static_cast<const uint32_t*>(list), static_cast<const uint32_t*>(count), C, O);
     return check_launch("gs_project");
 }

@@ -10,10 +10,14 @@ constexpr int kBlk = 256;  // elements per block, one per thread
 
 // Exclusive scan of per-block counts in place (one workgroup); writes the
 // total to *total if non-null.
+struct SelState;
+__device__ bool ties_need_ranks(const SelState* s);
+
 __global__ __launch_bounds__(256) void k_scan_counts(uint32_t* __restrict__ cnt, int64_t nb,
-                                                     uint64_t* __restrict__ total) {
+                                                     uint64_t* __restrict__ total, const SelState* __restrict__ gate) {
     __shared__ uint32_t w4[4];
     __shared__ uint64_t carry_s;
+    if (gate && !ties_need_ranks(gate)) return;  // no tie ranks needed: offsets unused
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
     for (int64_t b0 = 0; b0 < nb; b0 += 256) {
@@ -180,6 +184,8 @@ struct SelState {
     double mass_above;     // mass mode: sum of values above the prefix range
     uint64_t k_rem;        // count mode: rank still to place inside the prefix range
 };
+
+__device__ bool ties_need_ranks(const SelState* s) { return s->active && !s->take_all_eq; }
 
 // Histograms of the 4 digit passes (8 bits each, most significant first).
 struct SelHist {
@@ -500,14 +506,15 @@ static SelWs carve_sel(Carve& cv, int64_t n) {
 
 static int run_select(const float* v, int64_t n, int mode, float frac, uint64_t k, const SelWs& W, hipStream_t s) {
     const int64_t nb = (n + kBlk - 1) / kBlk;
-    const int hb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096)));
+    const int hb = int(std::min<int64_t>(2048, std::max<int64_t>(1, (n + 1023) / 1024)));
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, W.hist, W.total);
     for (int pass = 0; pass < 4; ++pass)
         launch("sel_hist", k_sel_hist, dim3(hb), dim3(256), 0, s, v, n, pass, W.hist, W.total, mode, frac, k);
     hipLaunchKernelGGL(k_sel_final, dim3(1), dim3(256), 0, s, W.hist, W.total, W.st, mode, frac, k);
     if (nb > 0) {
         hipLaunchKernelGGL(k_eq_count, dim3(unsigned(nb)), dim3(256), 0, s, v, n, W.st, W.eq_cnt);
-        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, s, W.eq_cnt, nb, W.tot64);
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, s, W.eq_cnt, nb, W.tot64,
+                           static_cast<const SelState*>(W.st));
     }
     return check_launch("radix select");
 }
@@ -588,7 +595,8 @@ extern "C" int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs
     launch("gate", k_gate, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_gate, c_act, c_keep);
     hipLaunchKernelGGL(k_gate_decide, dim3(1), dim3(256), 0, stream, c_gate, c_act, c_keep, nb, n,
                        params->fallback_ratio, flag);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, c_act, nb, tot);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, c_act, nb, tot,
+                       static_cast<const SelState*>(nullptr));
     launch("compact", k_compact, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_act, flag, active_idx);
     hipLaunchKernelGGL(k_store_count, dim3(1), dim3(64), 0, stream, tot, n_active_dev);
     return check_launch("gs_lod_mask");
@@ -714,7 +722,8 @@ extern "C" int gs_compact(const void* const* src, void* const* dst, const int32_
     const int64_t nb = (n + kBlk - 1) / kBlk;
     uint32_t* cnt = cv.take<uint32_t>(size_t(nb + 1));
     hipLaunchKernelGGL(k_keep_count, dim3(unsigned(nb)), dim3(256), 0, stream, keep_bits, n, cnt);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, cnt, nb, static_cast<uint64_t*>(nullptr));
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, cnt, nb, static_cast<uint64_t*>(nullptr),
+                       static_cast<const SelState*>(nullptr));
     hipLaunchKernelGGL(k_compact_arrays, dim3(unsigned(nb)), dim3(256), 0, stream, A, keep_bits, n, n_keep, cnt);
     return check_launch("gs_compact");
 }

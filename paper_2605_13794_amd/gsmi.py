@@ -22,7 +22,7 @@ GS_ERR_HIP = -4
 
 GS_LOD_NONE, GS_LOD_LEVEL, GS_LOD_RADIUS = 0, 1, 2
 (GS_OP_LOD_MASK, GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_IMPORTANCE, GS_OP_SCORE_KEEP, GS_OP_L1_LOSS,
- GS_OP_SIMPLIFY, GS_OP_PHOTO_LOSS, GS_OP_SCALE_REG) = range(9)
+ GS_OP_SIMPLIFY, GS_OP_PHOTO_LOSS, GS_OP_SCALE_REG, GS_OP_PROJECT) = range(10)
 GS_MAX_CAMS = 8
 GS_MAX_PAIRS = 1 << 30
 REC_FLOATS = 12
@@ -78,7 +78,7 @@ def lib() -> ctypes.CDLL:
         L.gs_num_tiles.restype = c_i64
         L.gs_num_tiles.argtypes = [c_i32, c_i32]
         L.gs_lod_mask.argtypes = [P, P, P, P, P, P, P, c_sz, P]
-        L.gs_project.argtypes = [P, P, c_i64, P, P, c_int, P, P]
+        L.gs_project.argtypes = [P, P, c_i64, P, P, c_int, P, P, c_sz, P]
         L.gs_bin_sort.argtypes = [P, P, c_int, c_i64, P, P, c_i64, P, P, P, c_sz, P]
         L.gs_render_fwd.argtypes = [P, P, c_int, P, P, P, P, P, P, P, P]
         L.gs_render_bwd.argtypes = [P, P, c_i64, P, P, P, c_int, P, P, P, P, P, P, P, P, P, P, c_sz, P]
@@ -209,10 +209,10 @@ def gs_lod_mask(scn: GsScene, cam: GsCamera, params: GsLodParams, keep_bits, act
                              stream_handle(stream)), "gs_lod_mask")
 
 
-def gs_project(scn: GsScene, active_idx, n_in, n_in_dev, cams, outs, stream=None):
+def gs_project(scn: GsScene, active_idx, n_in, n_in_dev, cams, outs, ws, stream=None):
     outs_arr = (GsProjected * len(outs))(*outs)
     _check(lib().gs_project(ctypes.byref(scn), ptr(active_idx), int(n_in), ptr(n_in_dev), cams, len(cams),
-                            outs_arr, stream_handle(stream)), "gs_project")
+                            outs_arr, ptr(ws), ws.numel(), stream_handle(stream)), "gs_project")
 
 
 def gs_bin_sort(projs, cams, n_in, keys, vals, capacity, tile_ranges, n_pairs_dev, ws, stream=None):

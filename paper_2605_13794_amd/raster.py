@@ -109,6 +109,7 @@ class Frame:
         self.capacity = 0
         self.keys = self.vals = None
         self.ws_sort = Workspace(self.device)
+        self.ws_proj = Workspace(self.device)
         self.ws_bwd = Workspace(self.device)
         self.ws_loss = Workspace(self.device)
         self.rgb = [torch.empty(3, c.height, c.width, dtype=F32, device=self.device) for c in cams]
@@ -125,9 +126,16 @@ class Frame:
         cap = int(min(max(cap, 1), G.GS_MAX_PAIRS - 1))
         if cap <= self.capacity:
             return
+        self.set_capacity(cap)
+
+    def set_capacity(self, cap: int):
+        """Pair buffers of exactly `cap` entries (the sort picks its partition
+        size from the capacity, so an oversized buffer costs time)."""
+        cap = int(min(max(cap, 1), G.GS_MAX_PAIRS - 1))
         self.capacity = cap
         self.keys = torch.empty(cap, dtype=torch.int64, device=self.device)
         self.vals = torch.empty(cap, dtype=I32, device=self.device)
+        self.chain = None
 
     def proj_structs(self):
         return [p.struct() for p in self.proj]
@@ -136,7 +144,8 @@ class Frame:
     def project(self, scn: G.GsScene, active=None, n_in=None, n_in_dev=None, stream=None):
         self.n_in = self.n_max if n_in is None else int(n_in)
         self.active, self.n_in_dev = active, n_in_dev
-        G.gs_project(scn, active, self.n_in, n_in_dev, self.cam_arr, self.proj_structs(), stream)
+        ws = self.ws_proj.get(G.gs_workspace_size(G.GS_OP_PROJECT, self.n_in))
+        G.gs_project(scn, active, self.n_in, n_in_dev, self.cam_arr, self.proj_structs(), ws, stream)
 
     def bin_sort(self, check: bool = True, stream=None):
         ws = self.ws_sort.get(G.gs_workspace_size(G.GS_OP_BIN_SORT, self.n_in, self.capacity, self.total_tiles,

@@ -143,7 +143,7 @@ class GpuExecutor:
         for _ in range(n_slots):
             s = dict(stream=torch.cuda.Stream(device=self.dev),
                      proj=[ProjBuffers(self.n, self.dev) for _ in range(max_batch)],
-                     ws=Workspace(self.dev), keys=None, vals=None, cap=0,
+                     ws=Workspace(self.dev), wsp=Workspace(self.dev), keys=None, vals=None, cap=0,
                      n_pairs=torch.zeros(1, dtype=torch.int64, device=self.dev),
                      ranges=None, event=None, batch=None, out=None)
             self.slots.append(s)
@@ -170,7 +170,8 @@ class GpuExecutor:
             out = [(torch.empty(3, c.height, c.width, device=self.dev),
                     torch.empty(c.height, c.width, device=self.dev),
                     torch.empty(c.height, c.width, dtype=torch.int32, device=self.dev)) for c in cams]
-            G.gs_project(self.ds.struct(), None, self.n, None, carr, projs, stream)
+            wsp = s["wsp"].get(G.gs_workspace_size(G.GS_OP_PROJECT, self.n))
+            G.gs_project(self.ds.struct(), None, self.n, None, carr, projs, wsp, stream)
             ws = s["ws"].get(G.gs_workspace_size(G.GS_OP_BIN_SORT, self.n, s["cap"], tiles, len(cams)))
             G.gs_bin_sort(projs, carr, self.n, s["keys"], s["vals"], s["cap"], s["ranges"], s["n_pairs"], ws,
                           stream)

@@ -55,7 +55,7 @@ def test_sizes_and_tiles(G):
 def test_host_side_errors(G):
     from paper_2605_13794_amd import scenes as S
     L = G.lib()
-    assert L.gs_project(None, None, 0, None, None, 0, None, None) == G.GS_ERR_INVALID_ARG
+    assert L.gs_project(None, None, 0, None, None, 0, None, None, 0, None) == G.GS_ERR_INVALID_ARG
     assert "scene" in G.gs_last_error()
     cams = G.camera_array([S.cube_camera()])
     assert L.gs_bin_sort(None, cams, 1, 10, None, None, 0, None, None, None, 0, None) == G.GS_ERR_INVALID_ARG
