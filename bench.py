@@ -122,6 +122,9 @@ class Bench:
         self.active = torch.empty(n, dtype=torch.int32, device=dev)
         self.n_act = torch.zeros(1, dtype=torch.int64, device=dev)
         self.lodp = G.lod_params(G.GS_LOD_RADIUS, fallback_ratio=0.95, radius_min_px=args.rmin, radius_sigma_k=1.0)
+        # second stream (default priority) for the importance refresh
+        self.s_imp = torch.cuda.Stream(device=dev)
+        self.ev_proj = torch.cuda.Event()
 
     # -- pieces ---------------------------------------------------------------
     def importance_view(self, fr, camc, view_row):
@@ -153,7 +156,7 @@ class Bench:
     def gate(self):
         self.G.gs_lod_mask(self.ds.struct(), self.camc, self.lodp, self.keep, self.active, self.n_act, self.ws_lod)
 
-    def train_iter(self, gated: bool):
+    def train_iter(self, gated: bool, before_adam=None):
         fr = self.fr if gated else self.fr_all
         scn = self.ds.struct()
         if gated:
@@ -165,11 +168,29 @@ class Bench:
         fr.render_fwd()
         fr.l1_loss([self.target])
         fr.backward(scn, self.grads_s)
+        if before_adam is not None:
+            before_adam()
         self.adam.step(self.grads, clear_grads=True)
 
     def step(self):
-        self.importance_view(self.fr_all, self.camc, self.sweep_views)
-        self.train_iter(gated=True)
+        """One step: the view's importance refresh runs on its own stream
+        beside the gated training iteration.  The refresh reads the parameters
+        only in its projection, so Adam waits for that projection (an event),
+        and the next step's refresh waits for Adam; the step ends when both
+        streams are done."""
+        torch, G = self.torch, self.G
+        main = torch.cuda.current_stream()
+        side = self.s_imp
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            fr = self.fr_all
+            fr.project(self.ds.struct())
+            self.ev_proj.record(side)
+            fr.bin_sort(check=False)
+            G.gs_importance(fr.proj[0].struct(), self.camc, self.n, fr.vals, fr.ranges, 0.99, 1e-6, self.w, self.a,
+                            self.score, self.c_rad, self.c_vis, self.cull[self.sweep_views], self.ws_imp)
+        self.train_iter(gated=True, before_adam=lambda: main.wait_event(self.ev_proj))
+        main.wait_stream(side)
 
     # -- setup ---------------------------------------------------------------
     def size_buffers(self):

@@ -204,6 +204,7 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr int kLookWin = 8;  // predecessors read per look-back round trip
 
 // Global digit histograms of every pass in one read of the keys; also
 // clears the look-back status of the first pass.
@@ -275,6 +276,11 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ 
         const uint32_t ex = block_excl_scan(v, L.scan4, &tot);
         L.dig_off[tid] = ex;
     }
+    // With at least as many workgroups as partitions, the first n_parts
+    // workgroups claim one partition each and the rest leave at once, so the
+    // claim counter sees n_parts atomics; a smaller grid loops.
+    if (blockIdx.x >= n_parts) return;
+    const bool one_each = gridDim.x >= n_parts;
     for (;;) {
         if (tid == 0) L.part = atomicAdd(counter, 1u);
         for (int k = tid; k < kWaves * 256; k += 256) (&L.wcnt[0][0])[k] = 0;
@@ -333,22 +339,38 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ 
                 st_agent(st, kFlagInc | total);
             } else {
                 st_agent(st, kFlagAgg | total);
+                // Walk back kLookWin predecessors per round trip: their status
+                // words are loaded together, then consumed in order up to the
+                // first inclusive prefix (done) or the first one not yet
+                // published (poll again from there).  Partition 0 always
+                // publishes an inclusive prefix, so the walk never passes it.
                 int64_t p = int64_t(part) - 1;
                 uint32_t spins = 0;
-                while (p >= 0) {
-                    const uint32_t s = ld_agent(status + size_t(p) * 256 + tid);
-                    const uint32_t flag = s & ~kValMask;
-                    if (flag == 0u) {
+                bool found = false;
+                while (!found) {
+                    uint32_t sw[kLookWin];
+#pragma unroll
+                    for (int q = 0; q < kLookWin; ++q)
+                        sw[q] = (p - q >= 0) ? ld_agent(status + size_t(p - q) * 256 + tid) : 0u;
+                    int used = 0;
+                    bool stop = false;
+#pragma unroll
+                    for (int q = 0; q < kLookWin; ++q) {
+                        const uint32_t flag = sw[q] & ~kValMask;
+                        if (!stop && flag != 0u) excl += sw[q] & kValMask;
+                        found = found || (!stop && flag == kFlagInc);
+                        if (!stop && flag == kFlagAgg) used = q + 1;
+                        stop = stop || flag != kFlagAgg;
+                    }
+                    if (found) break;
+                    p -= used;
+                    if (used < kLookWin) {  // status at p not yet published
                         if (++spins > kSpinLimit) {
                             atomicOr(err, 1u);
                             break;
                         }
                         __builtin_amdgcn_s_sleep(1);
-                        continue;
                     }
-                    excl += s & kValMask;
-                    if (flag == kFlagInc) break;
-                    --p;
                 }
                 st_agent(st, kFlagInc | ((excl + total) & kValMask));
             }
@@ -380,6 +402,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ 
                 vals_out[g] = L.vals[i];
             }
         }
+        if (one_each) break;
         __syncthreads();
     }
 }

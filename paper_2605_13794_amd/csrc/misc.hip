@@ -161,19 +161,27 @@ __global__ __launch_bounds__(256) void k_adam(AdamGroups G, float b1, float b2, 
     if (vec) {
         const int64_t n4 = cnt / 4;
         for (int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x; q < n4; q += stride) {
-            float4 p = reinterpret_cast<float4*>(P)[q];
-            float4 g = reinterpret_cast<const float4*>(Gd)[q];
-            float4 m = reinterpret_cast<float4*>(M)[q];
-            float4 v = reinterpret_cast<float4*>(V)[q];
-            bool z0, z1, z2, z3;
-            adam_one(p.x, g.x, m.x, v.x, z0, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
-            adam_one(p.y, g.y, m.y, v.y, z1, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
-            adam_one(p.z, g.z, m.z, v.z, z2, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
-            adam_one(p.w, g.w, m.w, v.w, z3, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
-            reinterpret_cast<float4*>(P)[q] = p;
-            reinterpret_cast<float4*>(M)[q] = m;
-            reinterpret_cast<float4*>(V)[q] = v;
-            if (clear && !(z0 && z1 && z2 && z3)) reinterpret_cast<float4*>(Gd)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            // streamed once per step: non-temporal loads and stores keep the
+            // 2 GB pass from evicting the caches the other kernels use
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4 p4 = __builtin_nontemporal_load(reinterpret_cast<f4*>(P) + q);
+            const f4 g4 = __builtin_nontemporal_load(reinterpret_cast<const f4*>(Gd) + q);
+            const f4 m4 = __builtin_nontemporal_load(reinterpret_cast<f4*>(M) + q);
+            const f4 v4 = __builtin_nontemporal_load(reinterpret_cast<f4*>(V) + q);
+            float p[4] = {p4.x, p4.y, p4.z, p4.w}, g[4] = {g4.x, g4.y, g4.z, g4.w};
+            float m[4] = {m4.x, m4.y, m4.z, m4.w}, v[4] = {v4.x, v4.y, v4.z, v4.w};
+            bool all_zero = true;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                bool z;
+                adam_one(p[e], g[e], m[e], v[e], z, b1, b2, eps, lr_bc1, inv_sqrt_bc2);
+                all_zero = all_zero && z;
+            }
+            __builtin_nontemporal_store(f4{p[0], p[1], p[2], p[3]}, reinterpret_cast<f4*>(P) + q);
+            __builtin_nontemporal_store(f4{m[0], m[1], m[2], m[3]}, reinterpret_cast<f4*>(M) + q);
+            __builtin_nontemporal_store(f4{v[0], v[1], v[2], v[3]}, reinterpret_cast<f4*>(V) + q);
+            if (clear && !all_zero)
+                __builtin_nontemporal_store(f4{0.f, 0.f, 0.f, 0.f}, reinterpret_cast<f4*>(Gd) + q);
         }
         done = n4 * 4;
     }

@@ -496,7 +496,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __
 }
 
 // Colour part of the backward: d sh = d rgb * Y (zero on clamped channels),
-// and the view-direction term of the mean gradient through the SH basis.
+// and the view-direction term of the mean gradient through the SH basis.  The
+// 48 coefficients are loaded once, the SH gradient is summed over the cameras
+// in registers, and the accumulation into the caller's gradient loads all 48
+// old values before storing any, so the loads of a thread are all in flight
+// together.
 __global__ __launch_bounds__(256) void k_project_bwd_sh(SceneP P, const int32_t* __restrict__ active,
                                                         int64_t n_in, const uint32_t* __restrict__ list,
                                                         const uint32_t* __restrict__ count, CamSet C, BwdIn B,
@@ -508,6 +512,12 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(SceneP P, const int32_t*
     if (i < 0 || i >= P.n) return;
     const int64_t N = P.n;
     const float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
+    float shv[48], gacc[48];
+#pragma unroll
+    for (int o = 0; o < 48; ++o) {
+        shv[o] = P.sh[int64_t(o) * N + i];
+        gacc[o] = 0.f;
+    }
     float dmu[3] = {0.f, 0.f, 0.f};
     for (int c = 0; c < C.n; ++c) {
         if (B.radius[c][j] <= 0) continue;
@@ -529,9 +539,8 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(SceneP P, const int32_t*
             float acc = 0.f;
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                const int64_t o = int64_t(k * 3 + ch) * N + i;
-                acc = fmaf(drgb[ch], P.sh[o], acc);
-                GO.sh[o] += drgb[ch] * Y[k];
+                acc = fmaf(drgb[ch], shv[k * 3 + ch], acc);
+                gacc[k * 3 + ch] = fmaf(drgb[ch], Y[k], gacc[k * 3 + ch]);
             }
             wsum[k] = acc;
         }
@@ -542,6 +551,11 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(SceneP P, const int32_t*
         dmu[1] += (gd[1] - dot * y) * il;
         dmu[2] += (gd[2] - dot * z) * il;
     }
+    float old[48];
+#pragma unroll
+    for (int o = 0; o < 48; ++o) old[o] = GO.sh[int64_t(o) * N + i];
+#pragma unroll
+    for (int o = 0; o < 48; ++o) GO.sh[int64_t(o) * N + i] = old[o] + gacc[o];
     for (int k = 0; k < 3; ++k) GO.mean[int64_t(k) * N + i] += dmu[k];
 }
 

@@ -506,7 +506,7 @@ static SelWs carve_sel(Carve& cv, int64_t n) {
 
 static int run_select(const float* v, int64_t n, int mode, float frac, uint64_t k, const SelWs& W, hipStream_t s) {
     const int64_t nb = (n + kBlk - 1) / kBlk;
-    const int hb = int(std::min<int64_t>(2048, std::max<int64_t>(1, (n + 1023) / 1024)));
+    const int hb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096)));
     hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, W.hist, W.total);
     for (int pass = 0; pass < 4; ++pass)
         launch("sel_hist", k_sel_hist, dim3(hb), dim3(256), 0, s, v, n, pass, W.hist, W.total, mode, frac, k);
