@@ -270,11 +270,25 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ 
     const uint32_t lane = lane_id();
 
     // Global exclusive offsets of each digit (scan of this pass's histogram).
+    bool trivial;
     {
         const uint32_t v = hist_pass[tid];
         uint32_t tot;
         const uint32_t ex = block_excl_scan(v, L.scan4, &tot);
         L.dig_off[tid] = ex;
+        trivial = __syncthreads_or(v == n) != 0;
+    }
+    if (trivial) {
+        // every key has the same digit: the stable pass is the identity, so
+        // the pass is a copy (and clears the next pass's look-back status)
+        const uint32_t stride = gridDim.x * kSortThreads;
+        for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n; i += stride) {
+            keys_out[i] = keys_in[i];
+            vals_out[i] = vals_in[i];
+        }
+        if (status_next)
+            for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n_parts * 256u; i += stride) status_next[i] = 0;
+        return;
     }
     // With at least as many workgroups as partitions, the first n_parts
     // workgroups claim one partition each and the rest leave at once, so the

@@ -194,6 +194,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
     __shared__ float4 sB[64];
     __shared__ float4 sR[64];  // (raw conic a, b, c, b channel)
     __shared__ uint32_t sJ[64];
+    __shared__ float4 sRed[4][3];  // per row of 16 lanes: the nine partial sums
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
     const int W = A.W[t.c];
@@ -238,10 +239,17 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
             const uint32_t nbn = min(64u, b0 - t.start);
             fetch_record(rec, vals, b0 - nbn, b0, lane, R);
         }
+        // the next record's LDS reads are issued one iteration ahead
+        float4 a_n = sA[nb - 1], b_n = sB[nb - 1], rw_n = sR[nb - 1];
         for (int i = int(nb) - 1; i >= 0; --i) {
-            const float4 a = sA[i];
-            const float4 b = sB[i];
-            const float4 rw = sR[i];
+            const float4 a = a_n;
+            const float4 b = b_n;
+            const float4 rw = rw_n;
+            if (i > 0) {
+                a_n = sA[i - 1];
+                b_n = sB[i - 1];
+                rw_n = sR[i - 1];
+            }
             const uint32_t pos = b0 - t.start + uint32_t(i);  // 0-based list position
             const float dx = a.x - t.fxp;
             const float ebase = a.z * dx * dx;
@@ -285,27 +293,30 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
                 }
             }
             if (__any(any)) {
-                s_mx = wave_sum_to_last(s_mx);
-                s_my = wave_sum_to_last(s_my);
-                s_ca = wave_sum_to_last(s_ca);
-                s_cb = wave_sum_to_last(s_cb);
-                s_cc = wave_sum_to_last(s_cc);
-                s_op = wave_sum_to_last(s_op);
-                s_r = wave_sum_to_last(s_r);
-                s_g = wave_sum_to_last(s_g);
-                s_b = wave_sum_to_last(s_b);
-                if (lane == 63) {
-                    const int64_t j = sJ[i];
-                    atomicAdd(d2 + j, s_mx);
-                    atomicAdd(d2 + n_in + j, s_my);
-                    atomicAdd(d2 + 2 * n_in + j, s_ca);
-                    atomicAdd(d2 + 3 * n_in + j, s_cb);
-                    atomicAdd(d2 + 4 * n_in + j, s_cc);
-                    atomicAdd(d2 + 5 * n_in + j, s_op);
-                    atomicAdd(d2 + 6 * n_in + j, s_r);
-                    atomicAdd(d2 + 7 * n_in + j, s_g);
-                    atomicAdd(d2 + 8 * n_in + j, s_b);
+                // rows of 16 lanes reduce with DPP; the four row sums of each
+                // partial meet in LDS, and lanes 0..8 each add one partial
+                // (a single atomic instruction for the nine)
+                s_mx = row_sum16(s_mx);
+                s_my = row_sum16(s_my);
+                s_ca = row_sum16(s_ca);
+                s_cb = row_sum16(s_cb);
+                s_cc = row_sum16(s_cc);
+                s_op = row_sum16(s_op);
+                s_r = row_sum16(s_r);
+                s_g = row_sum16(s_g);
+                s_b = row_sum16(s_b);
+                if ((lane & 15) == 15) {
+                    sRed[lane >> 4][0] = make_float4(s_mx, s_my, s_ca, s_cb);
+                    sRed[lane >> 4][1] = make_float4(s_cc, s_op, s_r, s_g);
+                    sRed[lane >> 4][2].x = s_b;
                 }
+                __builtin_amdgcn_wave_barrier();
+                if (lane < 9) {
+                    const float* rr = reinterpret_cast<const float*>(&sRed[0][0]);
+                    const float v = (rr[lane] + rr[12 + lane]) + (rr[24 + lane] + rr[36 + lane]);
+                    atomicAdd(d2 + int64_t(lane) * n_in + sJ[i], v);
+                }
+                __builtin_amdgcn_wave_barrier();
             }
         }
         b_end = b0;

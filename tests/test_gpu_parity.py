@@ -150,6 +150,28 @@ def test_bin_sort_large_many_passes(oracle):
     assert_same_ranges(u32(fr.ranges), ranges)
 
 
+def test_bin_sort_equal_depths(oracle):
+    """Every Gaussian at one depth: the four depth digit passes see a single
+    digit each, and the order inside a tile is the index order."""
+    dev = device()
+    sc = S.city_scene(1 << 20, seed=2)
+    idx = np.nonzero((np.abs(sc.mean[0]) < 200) & (sc.mean[1] > -60) & (sc.mean[1] < 200))[0][:60000]
+    sc = sc.subset(idx)
+    cam = S.aerial_camera(1920, 1080)
+    _, _, pr = oracle.project(sc.arrays(), cam)
+    prf = pr.rounded_f32()
+    prf = type(prf)(prf.mean2d, np.full_like(prf.depth, 211.25), prf.conic, prf.opacity, prf.rgb, prf.radius)
+    K, keys, vals, ranges = oracle.bin_sort(prf, cam.width, cam.height)
+    assert K > 20000
+    fr = _frame([cam], sc.n, dev, capacity=K)
+    fr.proj[0] = upload_projection(prf, cam.width, cam.height, dev)
+    assert fr.bin_sort() == K
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(fr.keys[:K]).view(np.uint64), keys)
+    np.testing.assert_array_equal(u32(fr.vals[:K]), vals)
+    assert_same_ranges(u32(fr.ranges), ranges)
+
+
 def test_bin_sort_empty_and_overflow(oracle):
     dev = device()
     G = gsmi()
