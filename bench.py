@@ -69,10 +69,18 @@ def parse():
                     help="measured seconds of the serving trace (0 disables serving)")
     ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--serve-n", type=int, default=8 << 20, help="Gaussians of the served scene")
+    ap.add_argument("--layout", default="morton", choices=["morton", "generated"],
+                    help="memory order of the Gaussians: Morton order of the means, or the generator's order")
     ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg3", "cfg4"],
                     help="cfg2: 1M city, one 1080p view (default line); cfg3: 8M city, 64-view importance "
                          "sweep and gated vs ungated views; cfg4: 5M city, batch of 4 1080p views with Adam")
     return ap.parse_args()
+
+
+def layout(scene, args):
+    """Memory order of the shard: Morton order of the means (default), or the
+    generator's random order."""
+    return scene.spatially_ordered() if args.layout == "morton" else scene
 
 
 def log(msg):
@@ -94,7 +102,7 @@ class Bench:
         dev = self.dev
         self.args = args
         t0 = time.time()
-        self.scene = S.city_scene(args.n, seed=2)
+        self.scene = layout(S.city_scene(args.n, seed=2), args)
         self.cam = S.aerial_camera(args.width, args.height)
         log(f"scene {self.scene.n} Gaussians generated in {time.time() - t0:.1f}s")
         self.ds = DeviceScene(self.scene, dev)
@@ -275,7 +283,7 @@ def run_cfg3(args):
     from paper_2605_13794_amd import scenes as S
     from paper_2605_13794_amd.raster import DeviceScene, Frame, Workspace
     n = args.n if args.n != (1 << 20) else (8 << 20)
-    sc = S.city_scene(n, seed=5)
+    sc = layout(S.city_scene(n, seed=5), args)
     ds = DeviceScene(sc, "cuda:0")
     del sc
     dev = torch.device("cuda:0")
@@ -372,7 +380,7 @@ def run_cfg4(args):
     from paper_2605_13794_amd import scenes as S
     from paper_2605_13794_amd.raster import Adam, DEFAULT_LRS, DeviceScene, Frame, rasterize
     n = args.n if args.n != (1 << 20) else (5 << 20)
-    sc = S.city_scene(n, seed=3)
+    sc = layout(S.city_scene(n, seed=3), args)
     ds = DeviceScene(sc, "cuda:0", requires_grad=True)
     del sc
     dev = torch.device("cuda:0")
@@ -464,7 +472,7 @@ def serving(args):
     from paper_2605_13794_amd.raster import DeviceScene
     from paper_2605_13794_amd.serve import GpuExecutor, Request, Scheduler, percentile, serve
     t0 = time.time()
-    sc = S.city_scene(args.serve_n, seed=5)
+    sc = layout(S.city_scene(args.serve_n, seed=5), args)
     ds = DeviceScene(sc, "cuda:0")
     del sc
     log(f"served scene {ds.n} Gaussians ready in {time.time() - t0:.1f}s")
@@ -577,7 +585,8 @@ def main():
         "config": {"workload": f"aerial city {b.n} Gaussians, one {args.width}x{args.height} view per step: "
                                f"importance refresh + gated (r>={args.rmin}px, drop {args.drop:.0%} by score) "
                                f"fwd+bwd L1 + Adam",
-                   "gaussians": b.n, "width": args.width, "height": args.height, "views_per_step": 1},
+                   "gaussians": b.n, "width": args.width, "height": args.height, "views_per_step": 1,
+                   "layout": args.layout},
         "mpix_per_s": px / 1e6 / sec,
         "active_fraction": act_frac,
         "pairs_gated": pairs,
@@ -596,7 +605,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU reference on one step ...")
         from paper_2605_13794_amd import scenes as S
-        out["cpu_baseline"] = cpu_baseline(S.city_scene(args.n, seed=2), S.aerial_camera(args.width, args.height))
+        out["cpu_baseline"] = cpu_baseline(layout(S.city_scene(args.n, seed=2), args),
+                                           S.aerial_camera(args.width, args.height))
     print(json.dumps(out), flush=True)
 
 

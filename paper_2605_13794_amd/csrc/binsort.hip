@@ -9,7 +9,7 @@ namespace gsmi {
 // Emission
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = 256;
-constexpr int kScanIters = 4;
+constexpr int kScanIters = 1;
 constexpr int kScanItems = kScanThreads * kScanIters;  // entries per block
 
 struct EmitIn {
@@ -107,18 +107,18 @@ __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ bloc
 
 __device__ __forceinline__ int64_t fdiv16(int64_t a) { return a >= 0 ? a / 16 : -((-a + 15) / 16); }
 
-// Emission: per 256 entries a block-wide scan of the tile counts gives every
-// wavefront a contiguous run of output pairs; the wavefront's lanes then write
-// consecutive pairs (each finds its entry by binary search over the 64 entry
-// starts in LDS), so large Gaussians are spread over the whole wavefront and
-// the stores are coalesced.
+// Emission: per 256 entries a block-wide scan of the tile counts gives the
+// block a contiguous run of output pairs; all 256 threads then write
+// consecutive pairs of that run (each finds its entry by binary search over the
+// 256 entry starts in LDS), so the stores are coalesced and the work of large
+// Gaussians, or of runs of visible entries, is spread over the whole block.
 struct EmitLds {
-    uint32_t start[4][65];
-    uint32_t base_tile[4][64];
-    uint32_t w[4][64];
-    uint32_t tx[4][64];
-    uint32_t dbits[4][64];
-    uint32_t j[4][64];
+    uint32_t start[kScanThreads + 1];
+    uint32_t base_tile[kScanThreads];
+    uint32_t w[kScanThreads];
+    uint32_t tx[kScanThreads];
+    uint32_t dbits[kScanThreads];
+    uint32_t j[kScanThreads];
 };
 
 __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const uint32_t* __restrict__ block_offs,
@@ -128,11 +128,10 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
     __shared__ EmitLds L;
     if (*n_sorted == 0) return;  // nothing fits (or nothing to emit)
     const int64_t base = int64_t(blockIdx.x) * kScanItems;
-    const int w = threadIdx.x / 64;
-    const uint32_t lane = lane_id();
+    const uint32_t tid = threadIdx.x;
     uint32_t run = block_offs[blockIdx.x];
     for (int it = 0; it < kScanIters; ++it) {
-        const int64_t e = base + int64_t(it) * kScanThreads + threadIdx.x;
+        const int64_t e = base + int64_t(it) * kScanThreads + tid;
         int c = 0;
         int64_t j = 0;
         uint32_t cnt = 0;
@@ -143,7 +142,6 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
         }
         uint32_t tot;
         const uint32_t ex = block_excl_scan(cnt, lds4, &tot);
-        const uint32_t wave_ex0 = __shfl(ex, 0, 64);
         uint32_t bt = 0, wd = 1, tx = 0, db = 0;
         if (cnt > 0) {
             const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
@@ -159,30 +157,28 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
             tx = uint32_t(TX);
             db = __float_as_uint(E.depth[c][j]);
         }
-        L.start[w][lane] = ex - wave_ex0;
-        L.base_tile[w][lane] = bt;
-        L.w[w][lane] = wd;
-        L.tx[w][lane] = tx;
-        L.dbits[w][lane] = db;
-        L.j[w][lane] = uint32_t(j);
-        const uint32_t wave_tot = __shfl(ex + cnt, 63, 64) - wave_ex0;
-        if (lane == 63) L.start[w][64] = wave_tot;
+        L.start[tid] = ex;
+        L.base_tile[tid] = bt;
+        L.w[tid] = wd;
+        L.tx[tid] = tx;
+        L.dbits[tid] = db;
+        L.j[tid] = uint32_t(j);
+        if (tid == 0) L.start[kScanThreads] = tot;
         __syncthreads();
-        const uint32_t out0 = run + wave_ex0;
-        for (uint32_t o = lane; o < wave_tot; o += 64) {
+        for (uint32_t o = tid; o < tot; o += kScanThreads) {
             // last entry l with start[l] <= o (zero-count entries share the next start)
-            uint32_t lo = 0, hi = 64;
+            uint32_t lo = 0, hi = kScanThreads;
             while (hi - lo > 1) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (L.start[w][mid] <= o) lo = mid;
+                if (L.start[mid] <= o) lo = mid;
                 else hi = mid;
             }
-            const uint32_t local = o - L.start[w][lo];
-            const uint32_t ww = L.w[w][lo];
+            const uint32_t local = o - L.start[lo];
+            const uint32_t ww = L.w[lo];
             const uint32_t dy = local / ww, dx = local - dy * ww;
-            const uint64_t tile = uint64_t(L.base_tile[w][lo] + dy * L.tx[w][lo] + dx);
-            keys[out0 + o] = (tile << 32) | uint64_t(L.dbits[w][lo]);
-            vals[out0 + o] = L.j[w][lo];
+            const uint64_t tile = uint64_t(L.base_tile[lo] + dy * L.tx[lo] + dx);
+            keys[run + o] = (tile << 32) | uint64_t(L.dbits[lo]);
+            vals[run + o] = L.j[lo];
         }
         __syncthreads();
         run += tot;

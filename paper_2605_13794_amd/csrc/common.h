@@ -22,6 +22,10 @@ constexpr float kDilation = 0.3f;
 constexpr float kJacClamp = 1.3f;
 // Render record stride in floats (three float4).
 constexpr int kRec = 12;
+// Screen-space partials of one (entry, camera) in the backward: d mean2d (2),
+// d conic (3), d opacity (1), d rgb (3), padded to 12 floats (48 B) so that one
+// atomic instruction of nine lanes updates one record.
+constexpr int kD2Stride = 12;
 
 // ---------------------------------------------------------------------------
 // Host-side error reporting

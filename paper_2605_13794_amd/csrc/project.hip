@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __rest
 // d opacity, d rgb r, g, b) of every camera -> parameter gradients.
 // ---------------------------------------------------------------------------
 struct BwdIn {
-    const float* d2[GS_MAX_CAMS];       // [9][n_in]
+    float* d2[GS_MAX_CAMS];             // [n_in][kD2Stride]
     const int32_t* radius[GS_MAX_CAMS];
     const uint8_t* clamp[GS_MAX_CAMS];
 };
@@ -375,9 +375,33 @@ __global__ __launch_bounds__(256) void k_visible_list(int64_t n_in, const int64_
         if (j < cnt)
             for (int c = 0; c < n_cams; ++c) vis |= B.radius[c][j] > 0;
         const uint64_t m = ballot(vis);
-        if (vis) list[off + popc64(m & lanemask_lt())] = uint32_t(j);
+        if (vis) {
+            list[off + popc64(m & lanemask_lt())] = uint32_t(j);
+            // the blend accumulates into these records with atomics; only
+            // visible entries are ever written or read, so only they are cleared
+            for (int c = 0; c < n_cams; ++c) {
+                if (B.radius[c][j] <= 0) continue;
+                float4* r = reinterpret_cast<float4*>(B.d2[c] + j * kD2Stride);
+                r[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+                r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+                r[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
         off += popc64(m);
     }
+}
+
+// Copies the partials of camera 0 to the caller's [9][n_in] array (visible
+// entries; the others were set to zero beforehand).
+__global__ __launch_bounds__(256) void k_export_d2(const float* __restrict__ d2, int64_t n_in,
+                                                   const uint32_t* __restrict__ list, const uint32_t* __restrict__ count,
+                                                   const int32_t* __restrict__ radius, float* __restrict__ out) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= *count) return;
+    const int64_t j = list[t];
+    if (radius[j] <= 0) return;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[int64_t(k) * n_in + j] = d2[j * kD2Stride + k];
 }
 
 __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
@@ -404,11 +428,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __
     for (int c = 0; c < C.n; ++c) {
         if (B.radius[c][j] <= 0) continue;
         const DevCam& K = C.cam[c];
-        const float* d2 = B.d2[c];
-        const float dmx = d2[j], dmy = d2[n_in + j];
-        const float dca = d2[2 * n_in + j], dcb = d2[3 * n_in + j], dcc = d2[4 * n_in + j];
-        const float dop = d2[5 * n_in + j];
-        float drgb[3] = {d2[6 * n_in + j], d2[7 * n_in + j], d2[8 * n_in + j]};
+        const float4* d2 = reinterpret_cast<const float4*>(B.d2[c] + j * kD2Stride);
+        const float4 q0 = d2[0], q1 = d2[1];
+        const float dmx = q0.x, dmy = q0.y;
+        const float dca = q0.z, dcb = q0.w, dcc = q1.x;
+        const float dop = q1.y;
+        float drgb[3] = {q1.z, q1.w, d2[2].x};
         const uint8_t cb = B.clamp[c][j];
         Geo G;
         geo_camera(K, mu, G);
@@ -522,9 +547,9 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(SceneP P, const int32_t*
     for (int c = 0; c < C.n; ++c) {
         if (B.radius[c][j] <= 0) continue;
         const DevCam& K = C.cam[c];
-        const float* d2 = B.d2[c];
+        const float* d2 = B.d2[c] + j * kD2Stride;
         const uint8_t cb = B.clamp[c][j];
-        float drgb[3] = {d2[6 * n_in + j], d2[7 * n_in + j], d2[8 * n_in + j]};
+        float drgb[3] = {d2[6], d2[7], d2[8]};
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch)
             if (cb & (1u << ch)) drgb[ch] = 0.f;
@@ -581,30 +606,54 @@ static int scene_ok(const gs_scene* s) {
     return GS_OK;
 }
 
-int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
-                       const gs_camera* cams, int n_cams, const float* const* d2, const gs_projected* proj,
-                       const gs_grads* grads, uint32_t* list, uint32_t* count, hipStream_t stream) {
-    CamSet C;
-    int rc = fill_camset(cams, n_cams, C);
-    if (rc) return rc;
-    SceneP P{scene->mean, scene->log_scale, scene->quat, scene->opacity_logit, scene->sh, scene->n};
-    BwdIn B;
+static void fill_bwdin(BwdIn& B, float* const* d2, const gs_projected* proj, int n_cams) {
     memset(&B, 0, sizeof(B));
     for (int c = 0; c < n_cams; ++c) {
         B.d2[c] = d2[c];
         B.radius[c] = proj[c].radius;
         B.clamp[c] = proj[c].clamp_bits;
     }
-    GradOut G{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh};
+}
+
+// Entries visible in some camera, listed once; their partial records are
+// cleared for the blend's atomics.
+int launch_visible_list(int64_t n_in, const int64_t* n_in_dev, int n_cams, float* const* d2, const gs_projected* proj,
+                        uint32_t* list, uint32_t* count, hipStream_t stream) {
+    BwdIn B;
+    fill_bwdin(B, d2, proj, n_cams);
+    int rc = fill_u32(count, 0u, 1, stream);
+    if (rc) return rc;
     if (n_in == 0) return GS_OK;
-    int rc2 = fill_u32(count, 0u, 1, stream);
-    if (rc2) return rc2;
     launch("visible_list", k_visible_list, dim3(unsigned((n_in + kVisChunk - 1) / kVisChunk)), dim3(256), 0, stream,
            n_in, n_in_dev, B, n_cams, list, count);
+    return check_launch("visible list");
+}
+
+int launch_export_d2(const float* d2, int64_t n_in, const uint32_t* list, const uint32_t* count,
+                     const int32_t* radius, float* out, hipStream_t stream) {
+    int rc = fill_u32(out, 0u, size_t(9) * size_t(n_in), stream);
+    if (rc) return rc;
+    if (n_in == 0) return GS_OK;
+    launch("export_d2", k_export_d2, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, d2, n_in, list, count,
+           radius, out);
+    return check_launch("export partials");
+}
+
+int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const gs_camera* cams,
+                       int n_cams, float* const* d2, const gs_projected* proj, const gs_grads* grads,
+                       const uint32_t* list, const uint32_t* count, hipStream_t stream) {
+    CamSet C;
+    int rc = fill_camset(cams, n_cams, C);
+    if (rc) return rc;
+    SceneP P{scene->mean, scene->log_scale, scene->quat, scene->opacity_logit, scene->sh, scene->n};
+    BwdIn B;
+    fill_bwdin(B, d2, proj, n_cams);
+    GradOut G{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh};
+    if (n_in == 0) return GS_OK;
     launch("project_bwd", k_project_bwd, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx,
-           n_in, static_cast<const uint32_t*>(list), static_cast<const uint32_t*>(count), C, B, G);
+           n_in, list, count, C, B, G);
     launch("project_bwd_sh", k_project_bwd_sh, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P,
-           active_idx, n_in, static_cast<const uint32_t*>(list), static_cast<const uint32_t*>(count), C, B, G);
+           active_idx, n_in, list, count, C, B, G);
     return check_launch("project backward");
 }
 

@@ -175,7 +175,7 @@ struct BwdImg {
     const float* T[GS_MAX_CAMS];
     const uint32_t* last[GS_MAX_CAMS];
     const float* grad[GS_MAX_CAMS];
-    float* d2[GS_MAX_CAMS];  // [9][n_in]
+    float* d2[GS_MAX_CAMS];  // [n_in][kD2Stride]
     const float* chain;      // optional stored transmittance chain
     int64_t n_in;
     float bg[3];
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
                 if (lane < 9) {
                     const float* rr = reinterpret_cast<const float*>(&sRed[0][0]);
                     const float v = (rr[lane] + rr[12 + lane]) + (rr[24 + lane] + rr[36 + lane]);
-                    atomicAdd(d2 + int64_t(lane) * n_in + sJ[i], v);
+                    atomicAdd(d2 + int64_t(sJ[i]) * kD2Stride + lane, v);
                 }
                 __builtin_amdgcn_wave_barrier();
             }
@@ -422,9 +422,13 @@ int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, cons
     return check_launch("importance blend");
 }
 
-int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
-                       const gs_camera* cams, int n_cams, const float* const* d2, const gs_projected* proj,
-                       const gs_grads* grads, uint32_t* list, uint32_t* count, hipStream_t stream);
+int launch_visible_list(int64_t n_in, const int64_t* n_in_dev, int n_cams, float* const* d2, const gs_projected* proj,
+                        uint32_t* list, uint32_t* count, hipStream_t stream);
+int launch_export_d2(const float* d2, int64_t n_in, const uint32_t* list, const uint32_t* count,
+                     const int32_t* radius, float* out, hipStream_t stream);
+int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const gs_camera* cams,
+                       int n_cams, float* const* d2, const gs_projected* proj, const gs_grads* grads,
+                       const uint32_t* list, const uint32_t* count, hipStream_t stream);
 int check_scene(const gs_scene* s);
 
 }  // namespace gsmi
@@ -433,7 +437,7 @@ using namespace gsmi;
 
 size_t ws_render_bwd(int64_t n, int n_cams) {
     Carve cv(nullptr);
-    cv.take<float>(size_t(9) * size_t(n > 0 ? n : 1) * size_t(n_cams));
+    cv.take<float>(size_t(kD2Stride) * size_t(n > 0 ? n : 1) * size_t(n_cams));
     cv.take<uint32_t>(size_t(n > 0 ? n : 1));
     cv.take<uint32_t>(4);
     return cv.used();
@@ -488,18 +492,17 @@ extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, i
         return fail(GS_ERR_WORKSPACE, "gs_render_bwd: workspace needs %zu bytes (256-aligned)", need);
     BwdImg I;
     memset(&I, 0, sizeof(I));
-    const float* d2c[GS_MAX_CAMS];
     Carve cv(ws);
-    float* base = cv.take<float>(size_t(9) * size_t(n_in > 0 ? n_in : 1) * size_t(n_cams));
+    float* base = cv.take<float>(size_t(kD2Stride) * size_t(n_in > 0 ? n_in : 1) * size_t(n_cams));
     uint32_t* vis_list = cv.take<uint32_t>(size_t(n_in > 0 ? n_in : 1));
     uint32_t* vis_count = cv.take<uint32_t>(4);
     for (int c = 0; c < n_cams; ++c) {
         if (!out_T[c] || !out_last[c] || !grad_rgb[c]) return fail(GS_ERR_INVALID_ARG, "gs_render_bwd: null image");
         I.T[c] = out_T[c]; I.last[c] = out_last[c]; I.grad[c] = grad_rgb[c];
-        I.d2[c] = (c == 0 && grads2d) ? grads2d : base + size_t(9) * size_t(n_in) * c;
-        d2c[c] = I.d2[c];
-        if ((rc = fill_u32(I.d2[c], 0u, size_t(9) * size_t(n_in), stream))) return rc;
+        I.d2[c] = base + size_t(kD2Stride) * size_t(n_in) * c;
     }
+    // visible entries first: the list clears their partial records
+    if ((rc = launch_visible_list(n_in, n_in_dev, n_cams, I.d2, proj, vis_list, vis_count, stream))) return rc;
     I.n_in = n_in;
     I.chain = chain;
     I.bg[0] = bg[0]; I.bg[1] = bg[1]; I.bg[2] = bg[2];
@@ -513,6 +516,7 @@ extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, i
                    uint32_t(tt), I);
     }
     if ((rc = check_launch("gs_render_bwd blend"))) return rc;
-    return launch_project_bwd(scene, active_idx, n_in, n_in_dev, cams, n_cams, d2c, proj, grads, vis_list, vis_count,
-                              stream);
+    if (grads2d && (rc = launch_export_d2(I.d2[0], n_in, vis_list, vis_count, proj[0].radius, grads2d, stream)))
+        return rc;
+    return launch_project_bwd(scene, active_idx, n_in, cams, n_cams, I.d2, proj, grads, vis_list, vis_count, stream);
 }

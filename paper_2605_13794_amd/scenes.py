@@ -58,6 +58,39 @@ class Scene:
                      lod=np.ascontiguousarray(self.lod[idx]))
 
 
+    def spatially_ordered(self) -> "Scene":
+        """The same Gaussians in Morton order of their means (see
+        morton_order): Gaussians close in space are close in memory, so a
+        view's visible set covers few, long index ranges."""
+        return self.subset(morton_order(self.mean))
+
+
+def _spread_bits3(v: np.ndarray) -> np.ndarray:
+    """Moves bit k of a 21-bit integer to bit 3k."""
+    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
+    v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+    v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+    v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+    v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+    v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
+    return v
+
+
+def morton_order(mean: np.ndarray, bits: int = 21) -> np.ndarray:
+    """Permutation sorting points [3][N] by the Morton (Z-order) code of their
+    coordinates quantised to 2^bits cells per axis over the bounding box;
+    equal codes keep their index order."""
+    mean = np.asarray(mean, dtype=np.float64)
+    if mean.shape[1] == 0:
+        return np.zeros(0, dtype=np.int64)
+    lo = mean.min(axis=1, keepdims=True)
+    span = np.maximum(mean.max(axis=1, keepdims=True) - lo, 1e-12)
+    top = (1 << bits) - 1
+    q = np.clip(np.floor((mean - lo) / span * top), 0, top).astype(np.uint64)
+    code = _spread_bits3(q[0]) | (_spread_bits3(q[1]) << np.uint64(1)) | (_spread_bits3(q[2]) << np.uint64(2))
+    return np.argsort(code, kind="stable")
+
+
 @dataclasses.dataclass
 class Camera:
     width: int
