@@ -121,14 +121,43 @@ struct EmitLds {
     uint32_t j[kScanThreads];
 };
 
+// Adds one key's digits to the per-pass LDS histograms; a digit shared by the
+// whole wavefront is added once.
+__device__ __forceinline__ void hist_add(uint32_t (*h)[256], uint64_t key, bool valid, int passes, int shift0) {
+    const uint64_t vm = ballot(valid);
+    if (!vm) return;
+    const int first = __ffsll((unsigned long long)vm) - 1;
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t d = uint32_t(key >> (shift0 + 8 * p)) & 255u;
+        const uint32_t d0 = __shfl(d, first, 64);
+        if (__all(!valid || d == d0)) {
+            if (lane_id() == uint32_t(first)) atomicAdd(&h[p][d0], popc64(vm));
+        } else if (valid) {
+            atomicAdd(&h[p][d], 1u);
+        }
+    }
+}
+
+// The emission also builds the digit histograms of the tile radix passes (LDS,
+// then one global add per non-empty bin) and clears the look-back status of
+// the first pass, so the sort needs no separate read of the keys.
 __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const uint32_t* __restrict__ block_offs,
                                               const uint32_t* __restrict__ n_sorted,
-                                              uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                              uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                              int passes, int shift0, int part, uint32_t* __restrict__ hist,
+                                              uint32_t* __restrict__ status0) {
     __shared__ uint32_t lds4[4];
     __shared__ EmitLds L;
-    if (*n_sorted == 0) return;  // nothing fits (or nothing to emit)
+    __shared__ uint32_t h[8][256];
+    const uint32_t n_s = *n_sorted;
+    if (n_s == 0) return;  // nothing fits (or nothing to emit)
     const int64_t base = int64_t(blockIdx.x) * kScanItems;
     const uint32_t tid = threadIdx.x;
+    {
+        const uint32_t n_parts = (n_s + uint32_t(part) - 1) / uint32_t(part);
+        for (uint32_t k = blockIdx.x * 256 + tid; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
+    }
+    for (int k = tid; k < passes * 256; k += 256) (&h[0][0])[k] = 0;
     uint32_t run = block_offs[blockIdx.x];
     for (int it = 0; it < kScanIters; ++it) {
         const int64_t e = base + int64_t(it) * kScanThreads + tid;
@@ -165,23 +194,34 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
         L.j[tid] = uint32_t(j);
         if (tid == 0) L.start[kScanThreads] = tot;
         __syncthreads();
-        for (uint32_t o = tid; o < tot; o += kScanThreads) {
-            // last entry l with start[l] <= o (zero-count entries share the next start)
-            uint32_t lo = 0, hi = kScanThreads;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (L.start[mid] <= o) lo = mid;
-                else hi = mid;
+        const uint32_t span = (tot + kScanThreads - 1) / kScanThreads * kScanThreads;
+        for (uint32_t o = tid; o < span; o += kScanThreads) {  // whole block iterates together
+            const bool valid = o < tot;
+            uint64_t key = 0;
+            if (valid) {
+                // last entry l with start[l] <= o (zero-count entries share the next start)
+                uint32_t lo = 0, hi = kScanThreads;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (L.start[mid] <= o) lo = mid;
+                    else hi = mid;
+                }
+                const uint32_t local = o - L.start[lo];
+                const uint32_t ww = L.w[lo];
+                const uint32_t dy = local / ww, dx = local - dy * ww;
+                const uint64_t tile = uint64_t(L.base_tile[lo] + dy * L.tx[lo] + dx);
+                key = (tile << 32) | uint64_t(L.dbits[lo]);
+                keys[run + o] = key;
+                vals[run + o] = L.j[lo];
             }
-            const uint32_t local = o - L.start[lo];
-            const uint32_t ww = L.w[lo];
-            const uint32_t dy = local / ww, dx = local - dy * ww;
-            const uint64_t tile = uint64_t(L.base_tile[lo] + dy * L.tx[lo] + dx);
-            keys[run + o] = (tile << 32) | uint64_t(L.dbits[lo]);
-            vals[run + o] = L.j[lo];
+            hist_add(h, key, valid, passes, shift0);
         }
         __syncthreads();
         run += tot;
+    }
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t v = h[p][tid];
+        if (v) atomicAdd(&hist[p * 256 + tid], v);
     }
 }
 
@@ -201,39 +241,6 @@ constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 24;
 constexpr int kLookWin = 8;  // predecessors read per look-back round trip
-
-// Global digit histograms of every pass in one read of the keys; also
-// clears the look-back status of the first pass.
-__global__ __launch_bounds__(256) void k_sort_hist(const uint64_t* __restrict__ keys,
-                                                   const uint32_t* __restrict__ n_sorted, int passes, int part,
-                                                   uint32_t* __restrict__ hist, uint32_t* __restrict__ status0) {
-    __shared__ uint32_t h[8][256];
-    for (int k = threadIdx.x; k < 8 * 256; k += 256) (&h[0][0])[k] = 0;
-    __syncthreads();
-    const uint32_t n = *n_sorted;
-    const uint32_t n_parts = (n + part - 1) / part;
-    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
-    const uint32_t span = (n + 255) / 256 * 256;  // whole wavefronts iterate together
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < span; i += gridDim.x * 256) {
-        const bool valid = i < n;
-        const uint64_t key = valid ? keys[i] : 0ull;
-        const uint64_t vm = ballot(valid);
-        for (int p = 0; p < passes; ++p) {
-            const uint32_t d = uint32_t(key >> (8 * p)) & 255u;
-            const uint32_t d0 = __shfl(d, __ffsll((unsigned long long)vm) - 1, 64);
-            if (__all(!valid || d == d0)) {  // one digit across the wavefront: one add
-                if (vm && lane_id() == uint32_t(__ffsll((unsigned long long)vm) - 1)) atomicAdd(&h[p][d0], popc64(vm));
-            } else if (valid) {
-                atomicAdd(&h[p][d], 1u);
-            }
-        }
-    }
-    __syncthreads();
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t v = h[p][threadIdx.x];
-        if (v) atomicAdd(&hist[p * 256 + threadIdx.x], v);
-    }
-}
 
 template <int IPT>
 struct SortLds {
@@ -440,6 +447,131 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
     if (b > 0) ranges[n_tiles + b - 1] = lo;
 }
 
+// ---------------------------------------------------------------------------
+// Depth order inside each tile
+// ---------------------------------------------------------------------------
+// After the radix passes over the tile bits, every tile's pairs are contiguous
+// and in emission order (ascending entry index).  One wavefront per tile then
+// orders its segment by depth, ties by position (= by index): a bitonic
+// network over the composite keys (depth bits << 32 | position) in LDS for
+// segments of up to kSegMax pairs, else a stable 8-bit LSD radix sort of the
+// depth bits through global memory (ping-pong between the two pair buffers).
+constexpr int kSegWaves = 2;
+constexpr int kSegMax = 2048;
+
+__device__ __forceinline__ void seg_bitonic(uint64_t* S, uint32_t n, uint32_t lane) {
+    uint32_t N = 2;
+    while (N < n) N <<= 1;
+    for (uint32_t i = n + lane; i < N; i += 64) S[i] = ~0ull;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t size = 2; size <= N; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t t = lane; t < N / 2; t += 64) {
+                const uint32_t i = ((t & ~(stride - 1)) << 1) | (t & (stride - 1));
+                const uint32_t j = i + stride;
+                const bool asc = (i & size) == 0;
+                const uint64_t a = S[i], b = S[j];
+                if ((a > b) == asc) {
+                    S[i] = b;
+                    S[j] = a;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// Stable LSD radix sort of a long segment by its 32 depth bits, one wavefront:
+// per 8-bit digit a histogram, a scan, and a scatter of 64-pair chunks in
+// order with ranks from eight ballots.  Four passes (a->b->a->b->a), then a
+// copy a -> b, so the result ends in b.
+__device__ void seg_lsd_global(uint64_t* ka, uint32_t* va, uint64_t* kb, uint32_t* vb, uint32_t n, uint32_t* hist,
+                               uint32_t lane) {
+    for (int pass = 0; pass < 4; ++pass) {
+        uint64_t* ks = (pass & 1) ? kb : ka;
+        uint32_t* vs = (pass & 1) ? vb : va;
+        uint64_t* kd = (pass & 1) ? ka : kb;
+        uint32_t* vd = (pass & 1) ? va : vb;
+        const int shift = 8 * pass;
+        for (int b = lane; b < 256; b += 64) hist[b] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = lane; i < n; i += 64) atomicAdd(&hist[uint32_t(ks[i] >> shift) & 255u], 1u);
+        __builtin_amdgcn_wave_barrier();
+        {   // exclusive scan of the 256 bins, four per lane
+            uint32_t c[4], sum = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { c[q] = hist[lane * 4 + q]; sum += c[q]; }
+            uint32_t inc = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(inc, o, 64);
+                if (lane >= uint32_t(o)) inc += t;
+            }
+            uint32_t run = inc - sum;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { hist[lane * 4 + q] = run; run += c[q]; }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t c0 = 0; c0 < n; c0 += 64) {
+            const uint32_t i = c0 + lane;
+            const bool valid = i < n;
+            const uint64_t key = valid ? ks[i] : 0ull;
+            const uint32_t val = valid ? vs[i] : 0u;
+            const uint32_t d = uint32_t(key >> shift) & 255u;
+            uint64_t peers = ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const bool on = (d >> bit) & 1u;
+                const uint64_t m = ballot(on);
+                peers &= on ? m : ~m;
+            }
+            const uint32_t before = popc64(peers & lanemask_lt());
+            const uint32_t base = hist[d];
+            if (valid) {
+                kd[base + before] = key;
+                vd[base + before] = val;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (valid && before == 0) hist[d] = base + popc64(peers);
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    for (uint32_t i = lane; i < n; i += 64) {
+        kb[i] = ka[i];
+        vb[i] = va[i];
+    }
+}
+
+// keys_in / vals_in are not const: a long segment uses its input range as
+// scratch (nothing else reads it afterwards).
+__global__ __launch_bounds__(64 * kSegWaves) void k_seg_sort(uint64_t* keys_in, uint32_t* vals_in,
+                                                             uint64_t* keys_out, uint32_t* vals_out,
+                                                             const uint32_t* __restrict__ ranges, uint32_t n_tiles,
+                                                             const uint32_t* __restrict__ n_sorted) {
+    __shared__ uint64_t S[kSegWaves][kSegMax];
+    __shared__ uint32_t H[kSegWaves][256];
+    const uint32_t n_s = *n_sorted;
+    if (n_s == 0) return;
+    const uint32_t w = threadIdx.x / 64, lane = lane_id();
+    const uint32_t tile = blockIdx.x * kSegWaves + w;
+    if (tile >= n_tiles) return;
+    const uint32_t start = ranges[tile], end = ranges[n_tiles + tile];
+    if (end <= start || end > n_s) return;  // empty (or ranges of a failed sort)
+    const uint32_t n = end - start;
+    if (n > uint32_t(kSegMax)) {
+        seg_lsd_global(keys_in + start, vals_in + start, keys_out + start, vals_out + start, n, H[w], lane);
+        return;
+    }
+    uint64_t* Sw = S[w];
+    for (uint32_t i = lane; i < n; i += 64) Sw[i] = (uint64_t(uint32_t(keys_in[start + i])) << 32) | i;
+    seg_bitonic(Sw, n, lane);
+    for (uint32_t i = lane; i < n; i += 64) {
+        const uint32_t p = uint32_t(Sw[i]);
+        keys_out[start + i] = keys_in[start + p];
+        vals_out[start + i] = vals_in[start + p];
+    }
+}
+
 struct SortWs {
     uint32_t* block_sums;
     uint32_t* n_sorted;
@@ -511,11 +643,12 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     E.n_cams = n_cams;
     E.n_in = n_in > 0 ? n_in : 1;
 
-    // key bits: 32 depth bits + enough for the global tile id
+    // radix passes over the global tile id only (bits 32 and up); the depth
+    // order inside each tile comes from the per-tile sort
     int tile_bits = 0;
     while ((int64_t(1) << tile_bits) < total_tiles) ++tile_bits;
-    const int passes = (32 + tile_bits + 7) / 8;
-    if (passes > 8) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
+    const int passes = (tile_bits + 7) / 8;
+    if (passes > 4) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
 
     const int64_t nb = (n_total + kScanItems - 1) / kScanItems;
     if (nb > 0)
@@ -527,20 +660,18 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         rc = fill_u32(tile_ranges, 0u, size_t(2 * total_tiles), stream);
         return rc;
     }
-    // Emission target: the ping-pong buffer that ends in keys/vals after `passes` passes.
+    // Emission target: the radix passes and then the per-tile sort each move
+    // the pairs to the other buffer; the per-tile sort reads the workspace copy
+    // and writes keys/vals.
     uint64_t* kb[2] = {keys, S.keys_alt};
     uint32_t* vb[2] = {vals, S.vals_alt};
-    int cur = (passes % 2 == 0) ? 0 : 1;
-    if (nb > 0)
-        launch("emit", k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
-                           S.n_sorted, kb[cur], vb[cur]);
+    int cur = (passes + 1) & 1;
     const bool small = capacity <= kSmallSortCapacity;
     const int part = kSortThreads * (small ? kIptSmall : kIptLarge);
     const int64_t max_parts = (capacity + part - 1) / part;
-    int hist_blocks = int(std::min<int64_t>(1024, (capacity + 4095) / 4096));
-    if (hist_blocks < 1) hist_blocks = 1;
-    launch("sort_hist", k_sort_hist, dim3(hist_blocks), dim3(256), 0, stream, kb[cur], S.n_sorted, passes, part,
-           S.hist, S.status[0]);
+    if (nb > 0)
+        launch("emit", k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
+               S.n_sorted, kb[cur], vb[cur], passes, 32, part, S.hist, S.status[0]);
     int grid = int(std::min<int64_t>(max_parts, 256 * (small ? 6 : 3)));
     if (grid < 1) grid = 1;
     for (int p = 0; p < passes; ++p) {
@@ -549,15 +680,21 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         if (small)
             launch("sort_pass", k_sort_pass<kIptSmall>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
                    kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
-                   8 * p);
+                   32 + 8 * p);
         else
             launch("sort_pass", k_sort_pass<kIptLarge>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
                    kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
-                   8 * p);
+                   32 + 8 * p);
         cur = nxt;
     }
     if ((rc = check_launch("gs_bin_sort sort"))) return rc;
-    launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream, keys,
-           S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err, n_pairs_dev);
-    return check_launch("gs_bin_sort ranges");
+    // cur == 1: the tile-ordered pairs are in the workspace copy
+    launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream,
+           static_cast<const uint64_t*>(kb[cur]), S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err, n_pairs_dev);
+    if ((rc = check_launch("gs_bin_sort ranges"))) return rc;
+    launch("seg_sort", k_seg_sort, dim3(unsigned((total_tiles + kSegWaves - 1) / kSegWaves)), dim3(64 * kSegWaves), 0,
+           stream, kb[cur], vb[cur], kb[0], vb[0],
+           static_cast<const uint32_t*>(tile_ranges), uint32_t(total_tiles),
+           static_cast<const uint32_t*>(S.n_sorted));
+    return check_launch("gs_bin_sort tile sort");
 }

@@ -172,6 +172,24 @@ def test_bin_sort_equal_depths(oracle):
     assert_same_ranges(u32(fr.ranges), ranges)
 
 
+def test_bin_sort_single_tile_long_segment(oracle):
+    """A 16x16 image is one tile: no tile-digit pass, and its segment is longer
+    than the per-tile LDS sort takes, so the global-memory radix path orders
+    it."""
+    dev = device()
+    sc = S.cube_scene(6000, seed=11)
+    cam = S.cube_camera(16, 16, f=16.0)
+    _, pr, prf, K, keys, vals, ranges = _ref_sorted(oracle, sc, cam)
+    assert K > 2048
+    fr = _frame([cam], sc.n, dev, capacity=K)
+    fr.proj[0] = upload_projection(prf, cam.width, cam.height, dev)
+    assert fr.bin_sort() == K
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(fr.keys[:K]).view(np.uint64), keys)
+    np.testing.assert_array_equal(u32(fr.vals[:K]), vals)
+    assert_same_ranges(u32(fr.ranges), ranges)
+
+
 def test_bin_sort_empty_and_overflow(oracle):
     dev = device()
     G = gsmi()
