@@ -87,13 +87,24 @@ __global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ bloc
     if (threadIdx.x == 0) *err = 0;
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
-    for (int64_t b0 = 0; b0 < n_blocks; b0 += 256) {
-        const int64_t b = b0 + threadIdx.x;
-        const uint32_t v = b < n_blocks ? block_sums[b] : 0u;
+    // 16 consecutive sums per thread, 4,096 per round
+    for (int64_t b0 = 0; b0 < n_blocks; b0 += 256 * 16) {
+        const int64_t bt = b0 + int64_t(threadIdx.x) * 16;
+        uint32_t v[16], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            v[q] = (bt + q < n_blocks) ? block_sums[bt + q] : 0u;
+            sum += v[q];
+        }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, lds4, &tot);
+        const uint32_t ex = block_excl_scan(sum, lds4, &tot);
         const uint64_t carry = carry_s;
-        if (b < n_blocks) block_sums[b] = uint32_t(carry + ex);  // fits: K < 2^32 checked below
+        uint64_t run = carry + ex;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            if (bt + q < n_blocks) block_sums[bt + q] = uint32_t(run);  // fits: K < 2^32 checked below
+            run += v[q];
+        }
         __syncthreads();
         if (threadIdx.x == 0) carry_s = carry + tot;
         __syncthreads();
@@ -544,31 +555,123 @@ __device__ void seg_lsd_global(uint64_t* ka, uint32_t* va, uint64_t* kb, uint32_
 
 // keys_in / vals_in are not const: a long segment uses its input range as
 // scratch (nothing else reads it afterwards).
-__global__ __launch_bounds__(64 * kSegWaves) void k_seg_sort(uint64_t* keys_in, uint32_t* vals_in,
-                                                             uint64_t* keys_out, uint32_t* vals_out,
-                                                             const uint32_t* __restrict__ ranges, uint32_t n_tiles,
-                                                             const uint32_t* __restrict__ n_sorted) {
-    __shared__ uint64_t S[kSegWaves][kSegMax];
-    __shared__ uint32_t H[kSegWaves][256];
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+    const uint32_t lo = uint32_t(__shfl_xor(int(uint32_t(v)), mask, 64));
+    const uint32_t hi = uint32_t(__shfl_xor(int(uint32_t(v >> 32)), mask, 64));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// Bitonic network over 64*E keys held in registers, element r*64 + lane in
+// k[r]: strides below 64 exchange across lanes, larger ones between registers.
+template <int E>
+__device__ __forceinline__ void reg_bitonic(uint64_t (&k)[E], uint32_t lane) {
+    constexpr uint32_t N = 64u * E;
+#pragma unroll
+    for (uint32_t size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= 64) {
+                const uint32_t rs = stride >> 6;
+#pragma unroll
+                for (uint32_t r = 0; r < uint32_t(E); ++r) {
+                    if (r & rs) continue;
+                    const uint32_t r2 = r | rs;
+                    const bool asc = ((r << 6) & size) == 0;
+                    const uint64_t a = k[r], b = k[r2];
+                    const bool sw = (a > b) == asc;
+                    k[r] = sw ? b : a;
+                    k[r2] = sw ? a : b;
+                }
+            } else {
+#pragma unroll
+                for (uint32_t r = 0; r < uint32_t(E); ++r) {
+                    const uint64_t o = shfl_xor_u64(k[r], int(stride));
+                    const bool asc = (((r << 6) | lane) & size) == 0;
+                    const bool lower = (lane & stride) == 0;
+                    const bool less = k[r] < o;
+                    // the lower element keeps the minimum when ascending
+                    k[r] = ((lower == asc) == less) ? k[r] : o;
+                }
+            }
+        }
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void seg_sort_regs(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* keys_out,
+                                              uint32_t* vals_out, uint32_t start, uint32_t n, uint32_t lane) {
+    uint64_t k[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t i = uint32_t(r) * 64 + lane;
+        k[r] = i < n ? (uint64_t(uint32_t(keys_in[start + i])) << 32) | i : ~0ull;
+    }
+    reg_bitonic<E>(k, lane);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t i = uint32_t(r) * 64 + lane;
+        if (i < n) {
+            const uint32_t p = uint32_t(k[r]);
+            keys_out[start + i] = keys_in[start + p];
+            vals_out[start + i] = vals_in[start + p];
+        }
+    }
+}
+
+// Pass A: one wavefront per tile; segments of up to kSegRegs pairs are sorted
+// in registers, longer ones are listed for pass B.
+constexpr uint32_t kSegRegs = 512;
+
+__global__ __launch_bounds__(256) void k_seg_sort(const uint64_t* __restrict__ keys_in,
+                                                  const uint32_t* __restrict__ vals_in,
+                                                  uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                  const uint32_t* __restrict__ ranges, uint32_t n_tiles,
+                                                  const uint32_t* __restrict__ n_sorted, uint32_t* __restrict__ long_list,
+                                                  uint32_t* __restrict__ long_count) {
     const uint32_t n_s = *n_sorted;
     if (n_s == 0) return;
-    const uint32_t w = threadIdx.x / 64, lane = lane_id();
-    const uint32_t tile = blockIdx.x * kSegWaves + w;
+    const uint32_t lane = lane_id();
+    const uint32_t tile = blockIdx.x * 4 + threadIdx.x / 64;
     if (tile >= n_tiles) return;
     const uint32_t start = ranges[tile], end = ranges[n_tiles + tile];
     if (end <= start || end > n_s) return;  // empty (or ranges of a failed sort)
     const uint32_t n = end - start;
-    if (n > uint32_t(kSegMax)) {
-        seg_lsd_global(keys_in + start, vals_in + start, keys_out + start, vals_out + start, n, H[w], lane);
-        return;
-    }
-    uint64_t* Sw = S[w];
-    for (uint32_t i = lane; i < n; i += 64) Sw[i] = (uint64_t(uint32_t(keys_in[start + i])) << 32) | i;
-    seg_bitonic(Sw, n, lane);
-    for (uint32_t i = lane; i < n; i += 64) {
-        const uint32_t p = uint32_t(Sw[i]);
-        keys_out[start + i] = keys_in[start + p];
-        vals_out[start + i] = vals_in[start + p];
+    if (n <= 64) seg_sort_regs<1>(keys_in, vals_in, keys_out, vals_out, start, n, lane);
+    else if (n <= 128) seg_sort_regs<2>(keys_in, vals_in, keys_out, vals_out, start, n, lane);
+    else if (n <= 256) seg_sort_regs<4>(keys_in, vals_in, keys_out, vals_out, start, n, lane);
+    else if (n <= kSegRegs) seg_sort_regs<8>(keys_in, vals_in, keys_out, vals_out, start, n, lane);
+    else if (lane == 0) long_list[atomicAdd(long_count, 1u)] = tile;
+}
+
+// Pass B: the listed long segments, one wavefront each (LDS bitonic up to
+// kSegMax pairs, else the global radix sort).  keys_in / vals_in are not
+// const: a segment beyond kSegMax uses its input range as scratch.
+__global__ __launch_bounds__(64 * kSegWaves) void k_seg_sort_long(uint64_t* keys_in, uint32_t* vals_in,
+                                                                  uint64_t* keys_out, uint32_t* vals_out,
+                                                                  const uint32_t* __restrict__ ranges,
+                                                                  uint32_t n_tiles,
+                                                                  const uint32_t* __restrict__ long_list,
+                                                                  const uint32_t* __restrict__ long_count) {
+    __shared__ uint64_t S[kSegWaves][kSegMax];
+    __shared__ uint32_t H[kSegWaves][256];
+    const uint32_t w = threadIdx.x / 64, lane = lane_id();
+    const uint32_t cnt = *long_count;
+    for (uint32_t q = blockIdx.x * kSegWaves + w; q < cnt; q += gridDim.x * kSegWaves) {
+        const uint32_t tile = long_list[q];
+        const uint32_t start = ranges[tile], n = ranges[n_tiles + tile] - start;
+        if (n > uint32_t(kSegMax)) {
+            seg_lsd_global(keys_in + start, vals_in + start, keys_out + start, vals_out + start, n, H[w], lane);
+            continue;
+        }
+        uint64_t* Sw = S[w];
+        for (uint32_t i = lane; i < n; i += 64) Sw[i] = (uint64_t(uint32_t(keys_in[start + i])) << 32) | i;
+        seg_bitonic(Sw, n, lane);
+        for (uint32_t i = lane; i < n; i += 64) {
+            const uint32_t p = uint32_t(Sw[i]);
+            keys_out[start + i] = keys_in[start + p];
+            vals_out[start + i] = vals_in[start + p];
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -581,10 +684,11 @@ struct SortWs {
     uint32_t* status[2];
     uint64_t* keys_alt;
     uint32_t* vals_alt;
+    uint32_t* long_list;
     size_t bytes;
 };
 
-static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity) {
+static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity, int64_t n_tiles) {
     Carve cv(ws);
     SortWs s;
     const int64_t nb = (n_total + kScanItems - 1) / kScanItems + 1;
@@ -598,6 +702,7 @@ static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity) {
     s.status[1] = cv.take<uint32_t>(size_t(np) * 256);
     s.keys_alt = cv.take<uint64_t>(size_t(capacity > 0 ? capacity : 1));
     s.vals_alt = cv.take<uint32_t>(size_t(capacity > 0 ? capacity : 1));
+    s.long_list = cv.take<uint32_t>(size_t(n_tiles > 0 ? n_tiles : 1));
     s.bytes = cv.used();
     return s;
 }
@@ -606,8 +711,8 @@ static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity) {
 
 using namespace gsmi;
 
-size_t ws_bin_sort(int64_t n_total, int64_t capacity, int64_t /*n_tiles*/) {
-    return carve_sort(nullptr, n_total, capacity).bytes;
+size_t ws_bin_sort(int64_t n_total, int64_t capacity, int64_t n_tiles) {
+    return carve_sort(nullptr, n_total, capacity, n_tiles).bytes;
 }
 
 extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int n_cams, int64_t n_in,
@@ -624,7 +729,7 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: null output");
     const int64_t n_total = n_in * n_cams;
     if (n_total >= (int64_t(1) << 32)) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many entries");
-    SortWs S = carve_sort(ws, n_total, capacity);
+    SortWs S = carve_sort(ws, n_total, capacity, total_tiles);
     if (!ws || ws_bytes < S.bytes || !aligned(ws, 256))
         return fail(GS_ERR_WORKSPACE, "gs_bin_sort: workspace needs %zu bytes (256-aligned)", S.bytes);
     EmitIn E;
@@ -692,9 +797,15 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream,
            static_cast<const uint64_t*>(kb[cur]), S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err, n_pairs_dev);
     if ((rc = check_launch("gs_bin_sort ranges"))) return rc;
-    launch("seg_sort", k_seg_sort, dim3(unsigned((total_tiles + kSegWaves - 1) / kSegWaves)), dim3(64 * kSegWaves), 0,
-           stream, kb[cur], vb[cur], kb[0], vb[0],
+    // counters[7] (cleared by the scan) counts the long segments
+    uint32_t* long_count = S.counters + 7;
+    launch("seg_sort", k_seg_sort, dim3(unsigned((total_tiles + 3) / 4)), dim3(256), 0, stream,
+           static_cast<const uint64_t*>(kb[cur]), static_cast<const uint32_t*>(vb[cur]), kb[0], vb[0],
            static_cast<const uint32_t*>(tile_ranges), uint32_t(total_tiles),
-           static_cast<const uint32_t*>(S.n_sorted));
+           static_cast<const uint32_t*>(S.n_sorted), S.long_list, long_count);
+    const int64_t long_grid = std::min<int64_t>((total_tiles + kSegWaves - 1) / kSegWaves, 1024);
+    launch("seg_sort_long", k_seg_sort_long, dim3(unsigned(long_grid)), dim3(64 * kSegWaves), 0, stream, kb[cur],
+           vb[cur], kb[0], vb[0], static_cast<const uint32_t*>(tile_ranges), uint32_t(total_tiles),
+           static_cast<const uint32_t*>(S.long_list), static_cast<const uint32_t*>(long_count));
     return check_launch("gs_bin_sort tile sort");
 }

@@ -190,6 +190,24 @@ def test_bin_sort_single_tile_long_segment(oracle):
     assert_same_ranges(u32(fr.ranges), ranges)
 
 
+def test_bin_sort_segment_paths(oracle):
+    """A 48x48 image of 2,500 Gaussians: tiles of ~260 pairs (register
+    network), ~750 (LDS network) and ~2,160 (global radix) in one sort."""
+    dev = device()
+    sc = S.cube_scene(2500, seed=12)
+    cam = S.cube_camera(48, 48, f=48.0)
+    _, pr, prf, K, keys, vals, ranges = _ref_sorted(oracle, sc, cam)
+    lens = ranges[1].astype(np.int64) - ranges[0].astype(np.int64)
+    assert lens.max() > 2048 and ((lens > 512) & (lens <= 2048)).any() and (lens <= 512).any()
+    fr = _frame([cam], sc.n, dev, capacity=K)
+    fr.proj[0] = upload_projection(prf, cam.width, cam.height, dev)
+    assert fr.bin_sort() == K
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(fr.keys[:K]).view(np.uint64), keys)
+    np.testing.assert_array_equal(u32(fr.vals[:K]), vals)
+    assert_same_ranges(u32(fr.ranges), ranges)
+
+
 def test_bin_sort_empty_and_overflow(oracle):
     dev = device()
     G = gsmi()
