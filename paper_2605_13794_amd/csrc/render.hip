@@ -23,6 +23,7 @@ struct TileCtx {
     int px, py0;
     float fxp;
     float fyp[4];
+    float ymid0;  // centre row of the strip of rows 0..3 (strip r: + 4r)
     bool valid[4];
     uint32_t start, end;
 };
@@ -40,6 +41,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const RenderCams& A, const uint32_t*
     t.px = tx * GS_TILE + (lane & 15);
     t.py0 = ty * GS_TILE + (lane >> 4);
     t.fxp = float(t.px) + 0.5f;
+    t.ymid0 = float(ty * GS_TILE) + 2.f;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         t.fyp[r] = float(t.py0 + 4 * r) + 0.5f;
@@ -77,6 +79,21 @@ __device__ __forceinline__ float4 scaled_b(const RawRec& R) {
     return make_float4(-0.5f * kLog2e * R.q1.x, R.q1.y, R.q1.z, R.q1.w);
 }
 
+// Reach of a record in y, plus half a strip: 1.5 + the largest |dy| at which
+// o * exp(-Q/2) can still reach 1/255 (Q = a dx^2 + 2b dx dy + c dy^2, so
+// |dy| <= sqrt(2 ln(255 o) a / (ac - b^2))), widened by 0.1% + 0.5 px against
+// rounding.  A strip of four rows whose centre row is farther than this from
+// the record's centre has no pixel with alpha >= 1/255, so it is skipped (the
+// skip changes no result).  Degenerate conics are never skipped.
+__device__ __forceinline__ float strip_reach(const RawRec& R) {
+    const float a = R.q0.z, b = R.q0.w, c = R.q1.x, o = R.q1.y;
+    const float det = a * c - b * b;
+    if (!(det > 0.f) || !(a > 0.f)) return __builtin_inff();
+    if (!(o * 255.f >= 0.999f)) return -1.f;  // o G < 1/255 everywhere (G <= 1)
+    const float t = fmaxf(logf(255.f * o), 0.f);
+    return sqrtf(2.f * t * a / det) * 1.001f + 0.5f + 1.5f;
+}
+
 // alpha of a staged record at one pixel; identical in forward and backward.
 __device__ __forceinline__ float eval_alpha(float ebase, float eb, float nc, float o, float dy, float& G,
                                             bool& pass) {
@@ -103,7 +120,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
                                                    const uint32_t* __restrict__ ranges, uint32_t n_tiles, FwdOut O) {
     __shared__ float4 sA[64];
     __shared__ float4 sB[64];
-    __shared__ float sC[64];
+    __shared__ float2 sC[64];  // (b channel, strip reach)
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
     float T[4], C0[4], C1[4], C2[4];
@@ -121,20 +138,22 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
         const uint32_t nb = min(64u, t.end - b0);
         __syncthreads();
         if (uint32_t(lane) < nb) {
-            sA[lane] = scaled_a(R); sB[lane] = scaled_b(R); sC[lane] = R.q2;
+            sA[lane] = scaled_a(R); sB[lane] = scaled_b(R); sC[lane] = make_float2(R.q2, strip_reach(R));
         }
         __syncthreads();
         fetch_record(rec, vals, b0 + 64, t.end, lane, R);  // next batch in flight during the blend
         for (uint32_t i = 0; i < nb; ++i) {
             const float4 a = sA[i];
             const float4 b = sB[i];
-            const float cb = sC[i];
+            const float2 ce = sC[i];
+            const float cb = ce.x;
             const float dx = a.x - t.fxp;
             const float ebase = a.z * dx * dx;
             const float eb = a.w * dx;
             const uint32_t pos = b0 - t.start + i + 1;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                if (fabsf(a.y - (t.ymid0 + 4.f * float(r))) > ce.y) continue;
                 float G;
                 bool pass;
                 const float alpha = eval_alpha(ebase, eb, b.x, b.y, a.y - t.fyp[r], G, pass);
@@ -331,7 +350,7 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
                                                          const uint32_t* __restrict__ ranges, uint32_t n_tiles,
                                                          float* __restrict__ w, uint32_t* __restrict__ a_cnt) {
     __shared__ float4 sA[64];
-    __shared__ float2 sB[64];
+    __shared__ float4 sB[64];  // (nc, o, strip reach, -)
     __shared__ uint32_t sJ[64];
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
@@ -349,14 +368,14 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
         if (uint32_t(lane) < nb) {
             const float4 b = scaled_b(R);
             sA[lane] = scaled_a(R);
-            sB[lane] = make_float2(b.x, b.y);
+            sB[lane] = make_float4(b.x, b.y, strip_reach(R), 0.f);
             sJ[lane] = R.j;
         }
         __syncthreads();
         fetch_record(rec, vals, b0 + 64, t.end, lane, R);
         for (uint32_t i = 0; i < nb; ++i) {
             const float4 a = sA[i];
-            const float2 b = sB[i];
+            const float4 b = sB[i];
             const float dx = a.x - t.fxp;
             const float ebase = a.z * dx * dx;
             const float eb = a.w * dx;
@@ -364,6 +383,7 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
             uint32_t sn = 0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                if (fabsf(a.y - (t.ymid0 + 4.f * float(r))) > b.z) continue;
                 float G;
                 bool pass;
                 const float alpha = eval_alpha(ebase, eb, b.x, b.y, a.y - t.fyp[r], G, pass);
