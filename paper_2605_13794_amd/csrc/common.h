@@ -117,6 +117,16 @@ __device__ __forceinline__ float wave_sum_to_last(float v) {
     return v;
 }
 
+// Sum over 8 lanes: each lane gets its quad's sum plus that of the quad 4 lanes
+// away in its row of 16.  Lanes 7 and 15 of a row (quads 1 and 3) then hold
+// complementary halves of the row whichever way the rotation runs.
+__device__ __forceinline__ float oct_sum8(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124, 0xF, 0xF, false));
+    return v;
+}
+
 // Sum over each row of 16 lanes (every lane of the row gets the row's sum).
 __device__ __forceinline__ float row_sum16(float v) {
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
     __shared__ float4 sB[64];
     __shared__ float4 sR[64];  // (raw conic a, b, c, b channel)
     __shared__ uint32_t sJ[64];
-    __shared__ float4 sRed[4][3];  // per row of 16 lanes: the nine partial sums
+    __shared__ float4 sRed[64][3];  // per lane: the nine partial sums of its group of 8
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
     const int W = A.W[t.c];
@@ -312,27 +312,28 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
                 }
             }
             if (__any(any)) {
-                // rows of 16 lanes reduce with DPP; the four row sums of each
-                // partial meet in LDS, and lanes 0..8 each add one partial
-                // (a single atomic instruction for the nine)
-                s_mx = row_sum16(s_mx);
-                s_my = row_sum16(s_my);
-                s_ca = row_sum16(s_ca);
-                s_cb = row_sum16(s_cb);
-                s_cc = row_sum16(s_cc);
-                s_op = row_sum16(s_op);
-                s_r = row_sum16(s_r);
-                s_g = row_sum16(s_g);
-                s_b = row_sum16(s_b);
-                if ((lane & 15) == 15) {
-                    sRed[lane >> 4][0] = make_float4(s_mx, s_my, s_ca, s_cb);
-                    sRed[lane >> 4][1] = make_float4(s_cc, s_op, s_r, s_g);
-                    sRed[lane >> 4][2].x = s_b;
-                }
+                // groups of 8 lanes reduce with three DPP steps; the eight group
+                // sums of each partial meet in LDS, and lanes 0..8 each add one
+                // partial (a single atomic instruction for the nine)
+                s_mx = oct_sum8(s_mx);
+                s_my = oct_sum8(s_my);
+                s_ca = oct_sum8(s_ca);
+                s_cb = oct_sum8(s_cb);
+                s_cc = oct_sum8(s_cc);
+                s_op = oct_sum8(s_op);
+                s_r = oct_sum8(s_r);
+                s_g = oct_sum8(s_g);
+                s_b = oct_sum8(s_b);
+                // every lane stores (keeps the DPP adds fused); lanes 7, 15, ..
+                // hold the group sums
+                sRed[lane][0] = make_float4(s_mx, s_my, s_ca, s_cb);
+                sRed[lane][1] = make_float4(s_cc, s_op, s_r, s_g);
+                sRed[lane][2].x = s_b;
                 __builtin_amdgcn_wave_barrier();
                 if (lane < 9) {
-                    const float* rr = reinterpret_cast<const float*>(&sRed[0][0]);
-                    const float v = (rr[lane] + rr[12 + lane]) + (rr[24 + lane] + rr[36 + lane]);
+                    const float* rr = reinterpret_cast<const float*>(&sRed[7][0]) + lane;  // lane 8g+7: rr[96 g]
+                    const float v = ((rr[0] + rr[96]) + (rr[192] + rr[288])) +
+                                    ((rr[384] + rr[480]) + (rr[576] + rr[672]));
                     atomicAdd(d2 + int64_t(sJ[i]) * kD2Stride + lane, v);
                 }
                 __builtin_amdgcn_wave_barrier();
