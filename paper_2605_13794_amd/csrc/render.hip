@@ -258,17 +258,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
             const uint32_t nbn = min(64u, b0 - t.start);
             fetch_record(rec, vals, b0 - nbn, b0, lane, R);
         }
-        // the next record's LDS reads are issued one iteration ahead
-        float4 a_n = sA[nb - 1], b_n = sB[nb - 1], rw_n = sR[nb - 1];
         for (int i = int(nb) - 1; i >= 0; --i) {
-            const float4 a = a_n;
-            const float4 b = b_n;
-            const float4 rw = rw_n;
-            if (i > 0) {
-                a_n = sA[i - 1];
-                b_n = sB[i - 1];
-                rw_n = sR[i - 1];
-            }
+            const float4 a = sA[i];
+            const float4 b = sB[i];
+            const float4 rw = sR[i];
             const uint32_t pos = b0 - t.start + uint32_t(i);  // 0-based list position
             const float dx = a.x - t.fxp;
             const float ebase = a.z * dx * dx;
