@@ -91,39 +91,48 @@ struct GateArgs {
     int l_max;
 };
 
-__global__ __launch_bounds__(256) void k_gate(GateArgs G, uint32_t* __restrict__ gate_words,
+// Pass 1: each workgroup takes `chunk` consecutive Gaussians (a multiple of
+// 256), stores the gate bits and counts gated, gated-and-kept and kept ones.
+__global__ __launch_bounds__(256) void k_gate(GateArgs G, int64_t chunk, uint32_t* __restrict__ gate_words,
                                               uint32_t* __restrict__ c_gate, uint32_t* __restrict__ c_act,
                                               uint32_t* __restrict__ c_keep) {
     __shared__ uint32_t w4[4];
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    const bool in = i < G.n;
-    bool gate = in;
-    if (in && G.mode != GS_LOD_NONE) {
-        const float dx = G.mean[i] - G.campos[0];
-        const float dy = G.mean[G.n + i] - G.campos[1];
-        const float dz = G.mean[2 * G.n + i] - G.campos[2];
-        const float d = sqrtf(dx * dx + dy * dy + dz * dz);
-        if (G.mode == GS_LOD_LEVEL) {
-            int lv;
-            if (d < 1e-6f) {
-                lv = G.l_max;
+    uint32_t ng = 0, na = 0, nk = 0;
+    for (int64_t base = int64_t(blockIdx.x) * chunk; base < min<int64_t>(G.n, int64_t(blockIdx.x + 1) * chunk);
+         base += kBlk) {
+        const int64_t i = base + threadIdx.x;
+        const bool in = i < G.n;
+        bool gate = in;
+        if (in && G.mode != GS_LOD_NONE) {
+            const float dx = G.mean[i] - G.campos[0];
+            const float dy = G.mean[G.n + i] - G.campos[1];
+            const float dz = G.mean[2 * G.n + i] - G.campos[2];
+            const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+            if (G.mode == GS_LOD_LEVEL) {
+                int lv;
+                if (d < 1e-6f) {
+                    lv = G.l_max;
+                } else {
+                    const float x = floorf(log2f(G.d0 / d) * G.inv_log2f + 0.5f);
+                    lv = int(fminf(fmaxf(x, 0.f), float(G.l_max)));
+                }
+                gate = int(G.lod[i]) <= lv;
             } else {
-                const float x = floorf(log2f(G.d0 / d) * G.inv_log2f + 0.5f);
-                lv = int(fminf(fmaxf(x, 0.f), float(G.l_max)));
+                const float smax = fmaxf(fmaxf(G.log_scale[i], G.log_scale[G.n + i]), G.log_scale[2 * G.n + i]);
+                gate = G.fx_k * __expf(smax) >= G.rmin * d;
             }
-            gate = int(G.lod[i]) <= lv;
-        } else {
-            const float smax = fmaxf(fmaxf(G.log_scale[i], G.log_scale[G.n + i]), G.log_scale[2 * G.n + i]);
-            gate = G.fx_k * __expf(smax) >= G.rmin * d;
         }
+        const bool keep = in && (G.keep ? bit_of(G.keep, i) : true);
+        const uint64_t mg = ballot(gate);
+        store_bits(gate_words, G.n, base + (threadIdx.x / 64) * 64, mg);
+        uint32_t t;
+        block_rank(gate, w4, &t);
+        ng += t;
+        block_rank(gate && keep, w4, &t);
+        na += t;
+        block_rank(keep, w4, &t);
+        nk += t;
     }
-    const bool keep = in && (G.keep ? bit_of(G.keep, i) : true);
-    const uint64_t mg = ballot(gate);
-    store_bits(gate_words, G.n, int64_t(blockIdx.x) * kBlk + (threadIdx.x / 64) * 64, mg);
-    uint32_t ng, na, nk;
-    block_rank(gate, w4, &ng);
-    block_rank(gate && keep, w4, &na);
-    block_rank(keep, w4, &nk);
     if (threadIdx.x == 0) {
         c_gate[blockIdx.x] = ng;
         c_act[blockIdx.x] = na;
@@ -131,42 +140,64 @@ __global__ __launch_bounds__(256) void k_gate(GateArgs G, uint32_t* __restrict__
     }
 }
 
-// Fallback decision and block offsets of the active set (one workgroup).
-__global__ __launch_bounds__(256) void k_gate_decide(uint32_t* __restrict__ c_gate, uint32_t* __restrict__ c_act,
-                                                     uint32_t* __restrict__ c_keep, int64_t nb, int64_t n,
-                                                     float fallback, uint32_t* __restrict__ flag) {
-    __shared__ uint64_t red[256];
-    uint64_t s = 0;
-    for (int64_t b = threadIdx.x; b < nb; b += 256) s += c_gate[b];
-    red[threadIdx.x] = s;
+// Pass 2 (same grid): every workgroup reduces the nb <= 1024 block counts
+// itself — the total gated count decides the fallback, and the counts of the
+// workgroups before it give its output offset — then writes its active
+// indices in ascending order.  Workgroup 0 stores the active count.
+__global__ __launch_bounds__(256) void k_gate_compact(GateArgs G, int64_t chunk, int64_t nb,
+                                                      const uint32_t* __restrict__ gate_words,
+                                                      const uint32_t* __restrict__ c_gate,
+                                                      const uint32_t* __restrict__ c_act,
+                                                      const uint32_t* __restrict__ c_keep,
+                                                      int32_t* __restrict__ out, int64_t* __restrict__ n_active) {
+    __shared__ uint32_t w4[4];
+    __shared__ uint64_t red[3][256];
+    uint64_t sg = 0, sa = 0, sk = 0, pa = 0, pk = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) {
+        const uint32_t g = c_gate[b], a = c_act[b], k = c_keep[b];
+        sg += g; sa += a; sk += k;
+        if (b < int64_t(blockIdx.x)) { pa += a; pk += k; }
+    }
+    red[0][threadIdx.x] = sg;
+    red[1][threadIdx.x] = sa;
+    red[2][threadIdx.x] = sk;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if (threadIdx.x < o)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
         __syncthreads();
     }
-    const bool fb = n > 0 && double(red[0]) >= double(fallback) * double(n);
-    if (threadIdx.x == 0) *flag = fb ? 1u : 0u;
-    if (fb)
-        for (int64_t b = threadIdx.x; b < nb; b += 256) c_act[b] = c_keep[b];
+    const bool fb = G.n > 0 && double(red[0][0]) >= double(G.fallback) * double(G.n);
+    const uint64_t total = fb ? red[2][0] : red[1][0];
+    __syncthreads();
+    red[0][threadIdx.x] = fb ? pk : pa;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[0][threadIdx.x] += red[0][threadIdx.x + o];
+        __syncthreads();
+    }
+    uint32_t off = uint32_t(red[0][0]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_active = int64_t(total);
+    for (int64_t base = int64_t(blockIdx.x) * chunk; base < min<int64_t>(G.n, int64_t(blockIdx.x + 1) * chunk);
+         base += kBlk) {
+        const int64_t i = base + threadIdx.x;
+        const bool in = i < G.n;
+        const bool gate = in && (fb || bit_of(gate_words, i));
+        const bool keep = in && (G.keep ? bit_of(G.keep, i) : true);
+        const bool act = gate && keep;
+        uint32_t tot;
+        const uint32_t r = block_rank(act, w4, &tot);
+        if (act) out[off + r] = int32_t(i);
+        off += tot;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_compact(GateArgs G, const uint32_t* __restrict__ gate_words,
-                                                 const uint32_t* __restrict__ offs, const uint32_t* __restrict__ flag,
-                                                 int32_t* __restrict__ out) {
-    __shared__ uint32_t w4[4];
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    const bool in = i < G.n;
-    const bool fb = *flag != 0u;
-    const bool gate = in && (fb || bit_of(gate_words, i));
-    const bool keep = in && (G.keep ? bit_of(G.keep, i) : true);
-    const bool act = gate && keep;
-    uint32_t tot;
-    const uint32_t r = block_rank(act, w4, &tot);
-    if (act) out[offs[blockIdx.x] + r] = int32_t(i);
-}
-
-__global__ void k_store_count(const uint64_t* __restrict__ total, int64_t* __restrict__ dst) {
-    if (threadIdx.x == 0) *dst = int64_t(*total);
+// Gaussians per workgroup of the gate: a multiple of 256 with at most 1,024
+// workgroups, so that each workgroup of the second pass reads all counts.
+static int64_t gate_chunk(int64_t n) {
+    int64_t c = 2048;
+    while ((n + c - 1) / c > 1024) c *= 2;
+    return c;
 }
 
 // ---------------------------------------------------------------------------
@@ -525,13 +556,11 @@ using namespace gsmi;
 
 size_t ws_lod_mask(int64_t n) {
     Carve cv(nullptr);
-    const int64_t nb = (n + kBlk - 1) / kBlk + 1;
+    const int64_t nb = (n + gate_chunk(n) - 1) / gate_chunk(n) + 1;
     cv.take<uint32_t>(size_t((n + 31) / 32 + 2));
     cv.take<uint32_t>(size_t(nb));
     cv.take<uint32_t>(size_t(nb));
     cv.take<uint32_t>(size_t(nb));
-    cv.take<uint32_t>(4);
-    cv.take<uint64_t>(1);
     return cv.used();
 }
 
@@ -579,26 +608,21 @@ extern "C" int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs
     G.fallback = params->fallback_ratio;
     G.l_max = params->l_max;
     Carve cv(ws);
-    const int64_t nb = (n + kBlk - 1) / kBlk;
+    const int64_t chunk = gate_chunk(n);
+    const int64_t nb = (n + chunk - 1) / chunk;
     uint32_t* words = cv.take<uint32_t>(size_t((n + 31) / 32 + 2));
     uint32_t* c_gate = cv.take<uint32_t>(size_t(nb + 1));
     uint32_t* c_act = cv.take<uint32_t>(size_t(nb + 1));
     uint32_t* c_keep = cv.take<uint32_t>(size_t(nb + 1));
-    uint32_t* flag = cv.take<uint32_t>(4);
-    uint64_t* tot = cv.take<uint64_t>(1);
     if (n == 0) {
-        int rc = fill_u32(tot, 0u, 2, stream);
+        int rc = fill_u32(n_active_dev, 0u, 2, stream);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_store_count, dim3(1), dim3(64), 0, stream, tot, n_active_dev);
         return check_launch("gs_lod_mask");
     }
-    launch("gate", k_gate, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_gate, c_act, c_keep);
-    hipLaunchKernelGGL(k_gate_decide, dim3(1), dim3(256), 0, stream, c_gate, c_act, c_keep, nb, n,
-                       params->fallback_ratio, flag);
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, c_act, nb, tot,
-                       static_cast<const SelState*>(nullptr));
-    launch("compact", k_compact, dim3(unsigned(nb)), dim3(256), 0, stream, G, words, c_act, flag, active_idx);
-    hipLaunchKernelGGL(k_store_count, dim3(1), dim3(64), 0, stream, tot, n_active_dev);
+    launch("gate", k_gate, dim3(unsigned(nb)), dim3(256), 0, stream, G, chunk, words, c_gate, c_act, c_keep);
+    launch("compact", k_gate_compact, dim3(unsigned(nb)), dim3(256), 0, stream, G, chunk, nb,
+           static_cast<const uint32_t*>(words), static_cast<const uint32_t*>(c_gate),
+           static_cast<const uint32_t*>(c_act), static_cast<const uint32_t*>(c_keep), active_idx, n_active_dev);
     return check_launch("gs_lod_mask");
 }
 
