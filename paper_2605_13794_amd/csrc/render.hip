@@ -123,18 +123,19 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
     __shared__ float2 sC[64];  // (b channel, strip reach)
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
+    // T > 0 while a pixel is still blending; a finished (or outside) pixel
+    // keeps its transmittance with the sign flipped
     float T[4], C0[4], C1[4], C2[4];
     uint32_t last[4];
-    bool done[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        T[r] = 1.f; C0[r] = C1[r] = C2[r] = 0.f; last[r] = 0; done[r] = !t.valid[r];
+        T[r] = t.valid[r] ? 1.f : -1.f; C0[r] = C1[r] = C2[r] = 0.f; last[r] = 0;
     }
     const int lane = threadIdx.x;
     RawRec R = {};
     fetch_record(rec, vals, t.start, t.end, lane, R);
     for (uint32_t b0 = t.start; b0 < t.end; b0 += 64) {
-        if (__all(done[0] && done[1] && done[2] && done[3])) break;
+        if (__all(T[0] < 0.f && T[1] < 0.f && T[2] < 0.f && T[3] < 0.f)) break;
         const uint32_t nb = min(64u, t.end - b0);
         __syncthreads();
         if (uint32_t(lane) < nb) {
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
                 bool pass;
                 const float alpha = eval_alpha(ebase, eb, b.x, b.y, a.y - t.fyp[r], G, pass);
                 const float Tn = T[r] * (1.f - alpha);
-                const bool ok = pass && !done[r];
+                const bool ok = pass && T[r] > 0.f;
                 const bool stop = ok && (Tn < kTMin);
                 const bool comp = ok && !stop;
                 const float wgt = comp ? alpha * T[r] : 0.f;
@@ -166,11 +167,10 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
                 C0[r] = fmaf(wgt, b.z, C0[r]);
                 C1[r] = fmaf(wgt, b.w, C1[r]);
                 C2[r] = fmaf(wgt, cb, C2[r]);
-                T[r] = comp ? Tn : T[r];
+                T[r] = comp ? Tn : (stop ? -T[r] : T[r]);
                 last[r] = comp ? pos : last[r];
-                done[r] = done[r] || stop;
             }
-            if (__all(done[0] && done[1] && done[2] && done[3])) break;
+            if (__all(T[0] < 0.f && T[1] < 0.f && T[2] < 0.f && T[3] < 0.f)) break;
         }
     }
     const int W = A.W[t.c], H = A.H[t.c];
@@ -179,10 +179,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
     for (int r = 0; r < 4; ++r) {
         if (!t.valid[r]) continue;
         const size_t p = size_t(t.py0 + 4 * r) * W + t.px;
-        O.rgb[t.c][p] = fmaf(T[r], O.bg[0], C0[r]);
-        O.rgb[t.c][plane + p] = fmaf(T[r], O.bg[1], C1[r]);
-        O.rgb[t.c][2 * plane + p] = fmaf(T[r], O.bg[2], C2[r]);
-        O.T[t.c][p] = T[r];
+        const float Tf = fabsf(T[r]);
+        O.rgb[t.c][p] = fmaf(Tf, O.bg[0], C0[r]);
+        O.rgb[t.c][plane + p] = fmaf(Tf, O.bg[1], C1[r]);
+        O.rgb[t.c][2 * plane + p] = fmaf(Tf, O.bg[2], C2[r]);
+        O.T[t.c][p] = Tf;
         O.last[t.c][p] = last[r];
     }
 }
@@ -348,15 +349,14 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
     __shared__ uint32_t sJ[64];
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
-    float T[4];
-    bool done[4];
+    float T[4];  // sign flipped once the pixel has stopped (or lies outside)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) { T[r] = 1.f; done[r] = !t.valid[r]; }
+    for (int r = 0; r < 4; ++r) T[r] = t.valid[r] ? 1.f : -1.f;
     const int lane = threadIdx.x;
     RawRec R = {};
     fetch_record(rec, vals, t.start, t.end, lane, R);
     for (uint32_t b0 = t.start; b0 < t.end; b0 += 64) {
-        if (__all(done[0] && done[1] && done[2] && done[3])) break;
+        if (__all(T[0] < 0.f && T[1] < 0.f && T[2] < 0.f && T[3] < 0.f)) break;
         const uint32_t nb = min(64u, t.end - b0);
         __syncthreads();
         if (uint32_t(lane) < nb) {
@@ -382,13 +382,12 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
                 bool pass;
                 const float alpha = eval_alpha(ebase, eb, b.x, b.y, a.y - t.fyp[r], G, pass);
                 const float Tn = T[r] * (1.f - alpha);
-                const bool ok = pass && !done[r];
+                const bool ok = pass && T[r] > 0.f;
                 const bool stop = ok && (Tn < kTMin);
                 const bool comp = ok && !stop;
                 sw += comp ? alpha * T[r] : 0.f;
                 sn += comp ? 1u : 0u;
-                T[r] = comp ? Tn : T[r];
-                done[r] = done[r] || stop;
+                T[r] = comp ? Tn : (stop ? -T[r] : T[r]);
             }
             if (__any(sn > 0)) {
                 sw = wave_sum_to_last(sw);
@@ -398,7 +397,7 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
                     atomicAdd(a_cnt + sJ[i], sn);
                 }
             }
-            if (__all(done[0] && done[1] && done[2] && done[3])) break;
+            if (__all(T[0] < 0.f && T[1] < 0.f && T[2] < 0.f && T[3] < 0.f)) break;
         }
     }
 }

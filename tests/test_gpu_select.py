@@ -120,19 +120,20 @@ def test_score_keep_bits_bitexact(oracle):
             np.testing.assert_array_equal(u32(keep), ref)
 
 
-def _gate_case():
-    sc = S.city_scene(200000, seed=12)
+def _gate_case(n=200000):
+    sc = S.city_scene(n, seed=12)
     cam = S.aerial_camera(1920, 1080, 20.0)
     return sc, cam
 
 
-@pytest.mark.parametrize("mode", ["radius", "level", "none"])
-@pytest.mark.parametrize("with_keep", [False, True])
-def test_lod_mask_matches_reference(oracle, mode, with_keep):
+@pytest.mark.parametrize("mode,with_keep,n", [(m, k, 200000) for m in ("radius", "level", "none")
+                                              for k in (False, True)] + [("radius", True, 2600000)])
+def test_lod_mask_matches_reference(oracle, mode, with_keep, n):
+    """2.6M Gaussians take the larger per-workgroup chunk of the gate."""
     dev = device()
     G = gsmi()
     from paper_2605_13794_amd.raster import DeviceScene
-    sc, cam = _gate_case()
+    sc, cam = _gate_case(n)
     n = sc.n
     ds = DeviceScene(sc, dev)
     campos = cam.position.astype(np.float32).astype(np.float64)
