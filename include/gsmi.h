@@ -139,9 +139,11 @@ size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t n_tiles, in
 const char* gs_last_error(void);
 
 /* Diagnostics: while `name` is set, every launch of that kernel (one of
- * "project", "project_bwd", "emit", "scan_reduce", "sort_hist", "sort_pass",
- * "tile_ranges", "render_fwd", "render_bwd", "importance_blend",
- * "importance_fold", "sel_hist", "gate", "compact", "adam") records `start`
+ * "project_cull", "project", "visible_list", "project_bwd", "project_bwd_sh",
+ * "export_d2", "scan_reduce", "emit", "sort_pass", "tile_ranges", "seg_sort",
+ * "seg_sort_long", "render_fwd", "render_bwd", "importance_blend",
+ * "importance_fold", "sel_hist", "gate", "compact", "adam", "fill",
+ * "ssim_fwd", "ssim_bwd") records `start`
  * and `stop` (caller-owned HIP events) immediately around the kernel on the
  * stream it is launched on; each launch overwrites the previous record.
  * name = NULL or "" turns it off.  Per calling thread. */
@@ -191,9 +193,11 @@ int gs_project(const gs_scene* scene, const int32_t* active_idx, int64_t n_in,
  * [tile_offset_c, tile_offset_c + gs_num_tiles(c)).  For every entry j with
  * radius > 0 (in order of camera, then j) and each tile of its rectangle in
  * row-major order, a pair (key = global_tile << 32 | float bits of depth,
- * value = j) is emitted; pairs are sorted stably by key (LSD radix sort on
- * 32 + ceil(log2 total_tiles) bits), so each tile's list is ordered by
- * (depth, j).  tile_ranges [2][total_tiles]: row 0 start, row 1 end.
+ * value = j) is emitted; pairs are sorted stably by key, so each tile's list
+ * is ordered by (depth, j).  (Implementation: LSD radix passes over the tile
+ * bits, then each tile's segment sorted by (depth bits, position); the result
+ * equals the stable full-key sort.)  tile_ranges [2][total_tiles]: row 0
+ * start, row 1 end.
  * *n_pairs_dev = number of pairs K.  If K > capacity nothing is sorted and
  * every tile range is empty; the caller re-runs with capacity >= K.  A
  * negative count reports an internal failure of the sort (a bounded wait
@@ -233,9 +237,10 @@ int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, int n_cams,
  *   dC/dalpha_k = T_k (c_k - S_k) - T_final bg / (1 - alpha_k)
  * with S_k the colour composited behind k normalised by T_{k+1}.  Per
  * (Gaussian, tile) the 9 screen-space partials are reduced across the
- * wavefront and added with one atomic each; a second kernel maps them to
- * mean, log_scale, quat, opacity_logit and SH (all derivatives exact, zero
- * through culls, clamps and skip/stop decisions).
+ * wavefront and added to the Gaussian's record by one atomic instruction;
+ * two more kernels map them to mean, log_scale, quat, opacity_logit and SH
+ * (all derivatives exact, zero through culls, clamps and skip/stop
+ * decisions).
  * If grads2d is non-NULL it receives the screen-space partials of camera 0
  * ([9][n_in]: d mean2d (2), d conic (3), d opacity (1), d rgb (3)).
  * chain: NULL (recompute T from the final T) or the chain the forward stored;
