@@ -294,15 +294,16 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
                     s_r = fmaf(g0[r], aT, s_r);
                     s_g = fmaf(g1[r], aT, s_g);
                     s_b = fmaf(g2[r], aT, s_b);
-                    if (o * G <= kAlphaMax) {
-                        s_op = fmaf(dLda, G, s_op);
-                        const float dP = dLda * o * G;
-                        s_mx -= dP * (rw.x * dx + rw.y * dy);
-                        s_my -= dP * (rw.y * dx + rw.z * dy);
-                        s_ca -= 0.5f * dP * dx * dx;
-                        s_cb -= dP * dx * dy;
-                        s_cc -= 0.5f * dP * dy * dy;
-                    }
+                    // a clamped alpha (o G > 0.99) passes no gradient to o or G;
+                    // a select instead of a branch (the clamp is rare)
+                    const float dLdaC = (o * G <= kAlphaMax) ? dLda : 0.f;
+                    s_op = fmaf(dLdaC, G, s_op);
+                    const float dP = dLdaC * o * G;
+                    s_mx -= dP * (rw.x * dx + rw.y * dy);
+                    s_my -= dP * (rw.y * dx + rw.z * dy);
+                    s_ca -= 0.5f * dP * dx * dx;
+                    s_cb -= dP * dx * dy;
+                    s_cc -= 0.5f * dP * dy * dy;
                 }
             }
             if (__any(any)) {
