@@ -389,9 +389,56 @@ def run_cfg3(args):
                      "plain_fwd_bwd_ms": res[("plain", "fwd_bwd_ms")],
                      "gated_fwd_bwd_ms": res[("gated", "fwd_bwd_ms")],
                      "psnr_db": 10 * math.log10(1 / mse) if mse > 0 else float("inf")})
+    # speed at equal image error: drop share x radius threshold on two views
+    sweep = []
+    ws_keep = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_SCORE_KEEP, n))
+    keep2 = torch.zeros_like(keep)
+    f = Frame([cams[0]], n, dev, capacity=int(Kmax * 1.2) + 4096)
+    plain_img, plain_ms = {}, {}
+    for v in (0, 32):
+        cam = cams[v]
+        f.cams, f.cam_arr = [cam], G.camera_array([cam])
+
+        def fb_plain():
+            f.forward(ds.struct(), check=False)
+            f.l1_loss([target])
+            f.backward(ds.struct(), gs)
+        fb_plain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            fb_plain()
+        torch.cuda.synchronize()
+        plain_ms[v] = 1e3 * (time.perf_counter() - t0) / 5
+        plain_img[v] = f.rgb[0].clone()
+    for drop in (0.0, 0.2, 0.4, 0.6):
+        G.gs_score_keep_bits(score, n, int(math.ceil(drop * n)), keep2, ws_keep)
+        for rmin in (0.0, 0.5, 1.0):
+            p2 = G.lod_params(G.GS_LOD_RADIUS, fallback_ratio=0.95, radius_min_px=rmin)
+            for v in (0, 32):
+                cam = cams[v]
+                f.cams, f.cam_arr = [cam], G.camera_array([cam])
+
+                def fb_gated():
+                    G.gs_lod_mask(ds.struct(), G.camera(cam), p2, keep2, active, n_act, ws_lod)
+                    f.forward(ds.struct(), active, n, n_act, check=False)
+                    f.l1_loss([target])
+                    f.backward(ds.struct(), gs)
+                fb_gated()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    fb_gated()
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / 5
+                mse = float(((f.rgb[0] - plain_img[v]) ** 2).mean().item())
+                sweep.append({"drop": drop, "radius_min_px": rmin, "view": v,
+                              "active_fraction": int(n_act.item()) / n, "fwd_bwd_ms": ms,
+                              "speedup": plain_ms[v] / ms,
+                              "psnr_db": 10 * math.log10(1 / mse) if mse > 0 else float("inf")})
     out = {"metric": METRIC, "config": {"workload": f"aerial city {n} Gaussians, 64 orbit views 1080p: importance "
                                                     f"sweep, drop 40% by score, 0.5 px radius gate"},
-           "importance_ms_per_view": sweep_ms, "pairs_max": Kmax,
+           "importance_ms_per_view": sweep_ms, "pairs_max": Kmax, "drop_radius_sweep": sweep,
            "active_fraction": {"mean": float(np.mean(fracs)), "min": float(np.min(fracs)),
                                "max": float(np.max(fracs))},
            "views": rows,

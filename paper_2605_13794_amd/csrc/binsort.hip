@@ -468,6 +468,7 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
 // segments of up to kSegMax pairs, else a stable 8-bit LSD radix sort of the
 // depth bits through global memory (ping-pong between the two pair buffers).
 constexpr int kSegWaves = 2;
+constexpr int64_t kSegAvgMax = 256;  // pair capacity per tile up to which the per-tile sort is used
 constexpr int kSegMax = 2048;
 
 __device__ __forceinline__ void seg_bitonic(uint64_t* S, uint32_t n, uint32_t lane) {
@@ -748,12 +749,16 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     E.n_cams = n_cams;
     E.n_in = n_in > 0 ? n_in : 1;
 
-    // radix passes over the global tile id only (bits 32 and up); the depth
-    // order inside each tile comes from the per-tile sort
+    // Two orderings with the same result.  Short tile lists (capacity per
+    // tile up to kSegAvgMax): radix passes over the global tile id only (bits
+    // 32 and up), the depth order inside each tile from the per-tile sort.
+    // Long lists: radix passes over all 32 + tile bits, no per-tile sort.
     int tile_bits = 0;
     while ((int64_t(1) << tile_bits) < total_tiles) ++tile_bits;
-    const int passes = (tile_bits + 7) / 8;
-    if (passes > 4) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
+    const bool per_tile = capacity <= kSegAvgMax * std::max<int64_t>(total_tiles, 1);
+    const int shift0 = per_tile ? 32 : 0;
+    const int passes = per_tile ? (tile_bits + 7) / 8 : (32 + tile_bits + 7) / 8;
+    if (passes > 8) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
 
     const int64_t nb = (n_total + kScanItems - 1) / kScanItems;
     if (nb > 0)
@@ -765,18 +770,18 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         rc = fill_u32(tile_ranges, 0u, size_t(2 * total_tiles), stream);
         return rc;
     }
-    // Emission target: the radix passes and then the per-tile sort each move
-    // the pairs to the other buffer; the per-tile sort reads the workspace copy
-    // and writes keys/vals.
+    // Emission target: each radix pass (and the per-tile sort) moves the pairs
+    // to the other buffer, and the last step writes keys/vals; the per-tile
+    // sort reads the workspace copy.
     uint64_t* kb[2] = {keys, S.keys_alt};
     uint32_t* vb[2] = {vals, S.vals_alt};
-    int cur = (passes + 1) & 1;
+    int cur = (passes + (per_tile ? 1 : 0)) & 1;
     const bool small = capacity <= kSmallSortCapacity;
     const int part = kSortThreads * (small ? kIptSmall : kIptLarge);
     const int64_t max_parts = (capacity + part - 1) / part;
     if (nb > 0)
         launch("emit", k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
-               S.n_sorted, kb[cur], vb[cur], passes, 32, part, S.hist, S.status[0]);
+               S.n_sorted, kb[cur], vb[cur], passes, shift0, part, S.hist, S.status[0]);
     int grid = int(std::min<int64_t>(max_parts, 256 * (small ? 6 : 3)));
     if (grid < 1) grid = 1;
     for (int p = 0; p < passes; ++p) {
@@ -785,18 +790,20 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         if (small)
             launch("sort_pass", k_sort_pass<kIptSmall>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
                    kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
-                   32 + 8 * p);
+                   shift0 + 8 * p);
         else
             launch("sort_pass", k_sort_pass<kIptLarge>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
                    kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
-                   32 + 8 * p);
+                   shift0 + 8 * p);
         cur = nxt;
     }
     if ((rc = check_launch("gs_bin_sort sort"))) return rc;
-    // cur == 1: the tile-ordered pairs are in the workspace copy
+    // per-tile path: cur == 1, the tile-ordered pairs are in the workspace
+    // copy; full-key path: cur == 0, the sorted pairs are in keys/vals
     launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream,
            static_cast<const uint64_t*>(kb[cur]), S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err, n_pairs_dev);
     if ((rc = check_launch("gs_bin_sort ranges"))) return rc;
+    if (!per_tile) return GS_OK;
     // counters[7] (cleared by the scan) counts the long segments
     uint32_t* long_count = S.counters + 7;
     launch("seg_sort", k_seg_sort, dim3(unsigned((total_tiles + 3) / 4)), dim3(256), 0, stream,

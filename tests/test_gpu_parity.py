@@ -173,9 +173,8 @@ def test_bin_sort_equal_depths(oracle):
 
 
 def test_bin_sort_single_tile_long_segment(oracle):
-    """A 16x16 image is one tile: no tile-digit pass, and its segment is longer
-    than the per-tile LDS sort takes, so the global-memory radix path orders
-    it."""
+    """A 16x16 image is one tile holding every pair: the full-key radix path
+    with no tile bits."""
     dev = device()
     sc = S.cube_scene(6000, seed=11)
     cam = S.cube_camera(16, 16, f=16.0)
@@ -191,11 +190,13 @@ def test_bin_sort_single_tile_long_segment(oracle):
 
 
 def test_bin_sort_segment_paths(oracle):
-    """A 48x48 image of 2,500 Gaussians: tiles of ~260 pairs (register
-    network), ~750 (LDS network) and ~2,160 (global radix) in one sort."""
+    """6,000 Gaussians seen small in a 256x256 image: ~57 pairs per tile on
+    average (so the per-tile path), with tiles of up to 512 pairs (register
+    network), 512-2,048 (LDS network) and over 2,048 (global radix) in one
+    sort."""
     dev = device()
-    sc = S.cube_scene(2500, seed=12)
-    cam = S.cube_camera(48, 48, f=48.0)
+    sc = S.cube_scene(6000, seed=12)
+    cam = S.cube_camera(256, 256, f=64.0)
     _, pr, prf, K, keys, vals, ranges = _ref_sorted(oracle, sc, cam)
     lens = ranges[1].astype(np.int64) - ranges[0].astype(np.int64)
     assert lens.max() > 2048 and ((lens > 512) & (lens <= 2048)).any() and (lens <= 512).any()
