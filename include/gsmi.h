@@ -140,7 +140,7 @@ const char* gs_last_error(void);
 
 /* Diagnostics: while `name` is set, every launch of that kernel (one of
  * "project_cull", "project", "visible_list", "project_bwd", "project_bwd_sh",
- * "export_d2", "scan_reduce", "emit", "sort_pass", "tile_ranges", "seg_sort",
+ * "export_d2", "scan_reduce", "emit", "sort_hist", "sort_pass", "tile_ranges", "seg_sort",
  * "seg_sort_long", "render_fwd", "render_bwd", "importance_blend",
  * "importance_fold", "sel_hist", "gate", "compact", "adam", "fill",
  * "ssim_fwd", "ssim_bwd") records `start`

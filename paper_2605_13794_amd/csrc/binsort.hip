@@ -253,6 +253,28 @@ constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 24;
 constexpr int kLookWin = 8;  // predecessors read per look-back round trip
 
+// Digit histograms of the depth passes (bits 0..31) of the full-key path in
+// one read of the keys (the emission builds the tile-digit ones): per
+// workgroup in LDS, then one global add per non-empty bin.
+__global__ __launch_bounds__(256) void k_sort_hist(const uint64_t* __restrict__ keys,
+                                                   const uint32_t* __restrict__ n_sorted, int passes,
+                                                   uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[8][256];
+    for (int k = threadIdx.x; k < 8 * 256; k += 256) (&h[0][0])[k] = 0;
+    __syncthreads();
+    const uint32_t n = *n_sorted;
+    const uint32_t span = (n + 255) / 256 * 256;  // whole wavefronts iterate together
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < span; i += gridDim.x * 256) {
+        const bool valid = i < n;
+        hist_add(h, valid ? keys[i] : 0ull, valid, passes, 0);
+    }
+    __syncthreads();
+    for (int p = 0; p < passes; ++p) {
+        const uint32_t v = h[p][threadIdx.x];
+        if (v) atomicAdd(&hist[p * 256 + threadIdx.x], v);
+    }
+}
+
 template <int IPT>
 struct SortLds {
     uint64_t keys[kSortThreads * IPT];
@@ -307,14 +329,21 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ 
     // With at least as many workgroups as partitions, the first n_parts
     // workgroups claim one partition each and the rest leave at once, so the
     // claim counter sees n_parts atomics; a smaller grid loops.
+    // A smaller grid loops; its next claim is issued when a partition starts,
+    // so the atomic's latency overlaps the partition's loads (a block holds at
+    // most one claim ahead, and the partitions it waits on were claimed
+    // earlier by running blocks).
     if (blockIdx.x >= n_parts) return;
     const bool one_each = gridDim.x >= n_parts;
+    uint32_t next = 0;
+    if (tid == 0) next = atomicAdd(counter, 1u);
     for (;;) {
-        if (tid == 0) L.part = atomicAdd(counter, 1u);
+        if (tid == 0) L.part = next;
         for (int k = tid; k < kWaves * 256; k += 256) (&L.wcnt[0][0])[k] = 0;
         __syncthreads();
         const uint32_t part = L.part;
         if (part >= n_parts) break;
+        if (tid == 0 && !one_each) next = atomicAdd(counter, 1u);
         if (status_next) status_next[part * 256 + tid] = 0;  // next pass starts clean
 
         // 1. load (wave-striped) and rank within the wavefront, stably
@@ -756,9 +785,10 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     int tile_bits = 0;
     while ((int64_t(1) << tile_bits) < total_tiles) ++tile_bits;
     const bool per_tile = capacity <= kSegAvgMax * std::max<int64_t>(total_tiles, 1);
-    const int shift0 = per_tile ? 32 : 0;
-    const int passes = per_tile ? (tile_bits + 7) / 8 : (32 + tile_bits + 7) / 8;
-    if (passes > 8) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
+    const int tile_passes = (tile_bits + 7) / 8;
+    const int depth_passes = per_tile ? 0 : 4;
+    const int passes = tile_passes + depth_passes;
+    if (tile_passes > 4) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
 
     const int64_t nb = (n_total + kScanItems - 1) / kScanItems;
     if (nb > 0)
@@ -781,7 +811,13 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     const int64_t max_parts = (capacity + part - 1) / part;
     if (nb > 0)
         launch("emit", k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
-               S.n_sorted, kb[cur], vb[cur], passes, shift0, part, S.hist, S.status[0]);
+               S.n_sorted, kb[cur], vb[cur], tile_passes, 32, part, S.hist + depth_passes * 256, S.status[0]);
+    if (depth_passes > 0) {
+        const int hb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (capacity + 4095) / 4096)));
+        launch("sort_hist", k_sort_hist, dim3(unsigned(hb)), dim3(256), 0, stream,
+               static_cast<const uint64_t*>(kb[cur]), static_cast<const uint32_t*>(S.n_sorted), depth_passes,
+               S.hist);
+    }
     int grid = int(std::min<int64_t>(max_parts, 256 * (small ? 6 : 3)));
     if (grid < 1) grid = 1;
     for (int p = 0; p < passes; ++p) {
@@ -790,11 +826,11 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         if (small)
             launch("sort_pass", k_sort_pass<kIptSmall>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
                    kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
-                   shift0 + 8 * p);
+                   8 * (p + (per_tile ? 4 : 0)));
         else
             launch("sort_pass", k_sort_pass<kIptLarge>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
                    kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
-                   shift0 + 8 * p);
+                   8 * (p + (per_tile ? 4 : 0)));
         cur = nxt;
     }
     if ((rc = check_launch("gs_bin_sort sort"))) return rc;

@@ -150,6 +150,24 @@ def test_bin_sort_large_many_passes(oracle):
     assert_same_ranges(u32(fr.ranges), ranges)
 
 
+def test_bin_sort_large_persistent_grid(oracle):
+    """2.5M Gaussians, one orbit view: over 3M pairs, long tile lists (the
+    full-key radix path) and more 3,840-key partitions than workgroups, so
+    each workgroup claims partitions in a loop."""
+    dev = device()
+    sc = S.city_scene(2500000, seed=5)
+    cam = S.orbit_cameras(64, 500.0, 300.0, 1920, 1080)[0]
+    _, pr, prf, K, keys, vals, ranges = _ref_sorted(oracle, sc, cam)
+    assert K > 768 * 3840
+    fr = _frame([cam], sc.n, dev, capacity=K)
+    fr.proj[0] = upload_projection(prf, cam.width, cam.height, dev)
+    assert fr.bin_sort() == K
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(fr.keys[:K]).view(np.uint64), keys)
+    np.testing.assert_array_equal(u32(fr.vals[:K]), vals)
+    assert_same_ranges(u32(fr.ranges), ranges)
+
+
 def test_bin_sort_equal_depths(oracle):
     """Every Gaussian at one depth: the four depth digit passes see a single
     digit each, and the order inside a tile is the index order."""
