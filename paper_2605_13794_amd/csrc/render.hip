@@ -342,12 +342,16 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
 // Importance: colour-less blend, w_j += alpha T and a_j += 1 per composited
 // (pixel, Gaussian), reduced per (Gaussian, tile) across the wavefront.
 // ---------------------------------------------------------------------------
+// w and the composited count of Gaussian j accumulate in one 8-byte record
+// wa[2j], wa[2j+1] (the count as a float, exact below 2^24), so that one
+// atomic instruction of two lanes updates both.
 __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uint32_t* __restrict__ vals,
                                                          const uint32_t* __restrict__ ranges, uint32_t n_tiles,
-                                                         float* __restrict__ w, uint32_t* __restrict__ a_cnt) {
+                                                         float* __restrict__ wa) {
     __shared__ float4 sA[64];
     __shared__ float4 sB[64];  // (nc, o, strip reach, -)
     __shared__ uint32_t sJ[64];
+    __shared__ float2 sRed[64];
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
     float T[4];  // sign flipped once the pixel has stopped (or lies outside)
@@ -391,12 +395,16 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
                 T[r] = comp ? Tn : (stop ? -T[r] : T[r]);
             }
             if (__any(sn > 0)) {
-                sw = wave_sum_to_last(sw);
-                sn = wave_sum_to_last_u32(sn);
-                if (lane == 63) {
-                    atomicAdd(w + sJ[i], sw);
-                    atomicAdd(a_cnt + sJ[i], sn);
+                // groups of 8 lanes reduce with DPP; lanes 0 and 1 add the
+                // eight group sums of w and of the count and issue one atomic
+                sRed[lane] = make_float2(oct_sum8(sw), oct_sum8(float(sn)));
+                __builtin_amdgcn_wave_barrier();
+                if (lane < 2) {
+                    const float* rr = reinterpret_cast<const float*>(&sRed[7]) + lane;  // lane 8g+7: rr[16 g]
+                    const float v = ((rr[0] + rr[16]) + (rr[32] + rr[48])) + ((rr[64] + rr[80]) + (rr[96] + rr[112]));
+                    atomicAdd(wa + 2 * int64_t(sJ[i]) + lane, v);
                 }
+                __builtin_amdgcn_wave_barrier();
             }
             if (__all(T[0] < 0.f && T[1] < 0.f && T[2] < 0.f && T[3] < 0.f)) break;
         }
@@ -425,14 +433,14 @@ int fill_render_cams(const gs_projected* proj, const gs_camera* cams, int n_cams
 }
 
 int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, const uint32_t* vals,
-                            const uint32_t* ranges, float* w, uint32_t* a, hipStream_t stream) {
+                            const uint32_t* ranges, float* wa, hipStream_t stream) {
     RenderCams A;
     int64_t tt = 0;
     int rc = fill_render_cams(proj, cam, 1, A, &tt);
     if (rc) return rc;
     if (tt == 0) return GS_OK;
-    launch("importance_blend", k_importance_blend, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, ranges, uint32_t(tt), w,
-                       a);
+    launch("importance_blend", k_importance_blend, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, ranges,
+           uint32_t(tt), wa);
     return check_launch("importance blend");
 }
 

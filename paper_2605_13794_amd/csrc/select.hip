@@ -414,6 +414,16 @@ __device__ __forceinline__ bool selected(float x, uint32_t rank_eq, const SelSta
 // ---------------------------------------------------------------------------
 // Importance fold
 // ---------------------------------------------------------------------------
+// The blend's (w, count) records to the w and a arrays.
+__global__ __launch_bounds__(256) void k_importance_split(const float2* __restrict__ wa, int64_t n,
+                                                          float* __restrict__ w, uint32_t* __restrict__ a) {
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    if (i >= n) return;
+    const float2 r = wa[i];
+    w[i] = r.x;
+    a[i] = uint32_t(r.y);
+}
+
 __global__ __launch_bounds__(256) void k_importance_fold(const float* __restrict__ w, const uint32_t* __restrict__ a,
                                                          const int32_t* __restrict__ radius, int64_t n,
                                                          const SelState* __restrict__ stp,
@@ -566,15 +576,20 @@ size_t ws_lod_mask(int64_t n) {
 
 size_t ws_importance(int64_t n) {
     Carve cv(nullptr);
+    cv.take<float>(size_t(2 * (n > 0 ? n : 1)));
     carve_sel(cv, n);
     return cv.used();
 }
 
-size_t ws_score_keep(int64_t n) { return ws_importance(n); }
+size_t ws_score_keep(int64_t n) {
+    Carve cv(nullptr);
+    carve_sel(cv, n);
+    return cv.used();
+}
 
 namespace gsmi {
 int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, const uint32_t* vals,
-                            const uint32_t* ranges, float* w, uint32_t* a, hipStream_t stream);
+                            const uint32_t* ranges, float* wa, hipStream_t stream);
 }
 
 extern "C" int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
@@ -640,10 +655,13 @@ extern "C" int gs_importance(const gs_projected* proj, const gs_camera* cam, int
         return fail(GS_ERR_WORKSPACE, "gs_importance: workspace needs %zu bytes (256-aligned)", need);
     if (n == 0) return GS_OK;
     int rc;
-    if ((rc = fill_u32(w, 0u, size_t(n), stream))) return rc;
-    if ((rc = fill_u32(a, 0u, size_t(n), stream))) return rc;
-    if ((rc = launch_importance_blend(proj, cam, vals, tile_ranges, w, a, stream))) return rc;
     Carve cv(ws);
+    float* wa = cv.take<float>(size_t(2 * n));
+    if ((rc = fill_u32(wa, 0u, size_t(2 * n), stream))) return rc;
+    if ((rc = launch_importance_blend(proj, cam, vals, tile_ranges, wa, stream))) return rc;
+    const int64_t nbs = (n + kBlk - 1) / kBlk;
+    launch("importance_split", k_importance_split, dim3(unsigned(nbs)), dim3(256), 0, stream,
+           static_cast<const float2*>(static_cast<void*>(wa)), n, w, a);
     SelWs S = carve_sel(cv, n);
     if ((rc = run_select(w, n, 0, mass_frac, 0, S, stream))) return rc;
     const int64_t nb = (n + kBlk - 1) / kBlk;
