@@ -566,7 +566,11 @@ def serving(args):
     lat = [1e3 * r.latency for r in meas]
     mpix = sum(r.pixels for r in meas) / 1e6
     span = max(r.t_done for r in meas) - min(r.arrival for r in meas)
+    by_res = {}
+    for r in meas:
+        by_res.setdefault(f"{r.cam.width}x{r.cam.height}", []).append(1e3 * r.latency)
     return {"requests": len(meas), "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "p50_p99_ms_by_resolution": {k: [percentile(v, 50), percentile(v, 99)] for k, v in sorted(by_res.items())},
             "mean_ms": sum(lat) / len(lat), "mpix_per_s": mpix / span, "offered_req_per_s": 200.0,
             "served_req_per_s": len(meas) / span, "batches": sch.n_batches, "memory_pool_gib": pool / 2**30,
             "retries": sum(r.retries for r in done), "gaussians": ds.n, "slots": 3, "max_batch": 8,

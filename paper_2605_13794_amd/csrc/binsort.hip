@@ -329,21 +329,15 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t* __restrict__ 
     // With at least as many workgroups as partitions, the first n_parts
     // workgroups claim one partition each and the rest leave at once, so the
     // claim counter sees n_parts atomics; a smaller grid loops.
-    // A smaller grid loops; its next claim is issued when a partition starts,
-    // so the atomic's latency overlaps the partition's loads (a block holds at
-    // most one claim ahead, and the partitions it waits on were claimed
-    // earlier by running blocks).
+    // A smaller grid loops, claiming one partition at a time.
     if (blockIdx.x >= n_parts) return;
     const bool one_each = gridDim.x >= n_parts;
-    uint32_t next = 0;
-    if (tid == 0) next = atomicAdd(counter, 1u);
     for (;;) {
-        if (tid == 0) L.part = next;
+        if (tid == 0) L.part = atomicAdd(counter, 1u);
         for (int k = tid; k < kWaves * 256; k += 256) (&L.wcnt[0][0])[k] = 0;
         __syncthreads();
         const uint32_t part = L.part;
         if (part >= n_parts) break;
-        if (tid == 0 && !one_each) next = atomicAdd(counter, 1u);
         if (status_next) status_next[part * 256 + tid] = 0;  // next pass starts clean
 
         // 1. load (wave-striped) and rank within the wavefront, stably
