@@ -219,7 +219,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
     const float* rec = A.rec[t.c];
     const int W = A.W[t.c];
     const size_t plane = size_t(W) * A.H[t.c];
-    float T[4], acc0[4], acc1[4], acc2[4], g0[4], g1[4], g2[4], gbg[4];
+    // S = g . (colour behind the current position, divided by the
+    // transmittance after it): the three running colour sums enter the
+    // backward only through their dot product with the pixel's dL/dC
+    float T[4], S[4], g0[4], g1[4], g2[4], gbg[4];
     uint32_t lst[4];
     uint32_t lmax = 0;
 #pragma unroll
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
         g1[r] = v ? I.grad[t.c][plane + p] : 0.f;
         g2[r] = v ? I.grad[t.c][2 * plane + p] : 0.f;
         gbg[r] = T[r] * (g0[r] * I.bg[0] + g1[r] * I.bg[1] + g2[r] * I.bg[2]);
-        acc0[r] = acc1[r] = acc2[r] = 0.f;
+        S[r] = 0.f;
         lmax = max(lmax, lst[r]);
     }
     lmax = wave_max_u32(lmax);
@@ -268,8 +271,11 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
             const float ebase = a.z * dx * dx;
             const float eb = a.w * dx;
             const float o = b.y;
-            float s_mx = 0.f, s_my = 0.f, s_ca = 0.f, s_cb = 0.f, s_cc = 0.f, s_op = 0.f;
-            float s_r = 0.f, s_g = 0.f, s_b = 0.f;
+            // per lane, over its composited rows: u = dL/dalpha * G (the
+            // opacity partial), and the moments sum(u dy), sum(u dy^2); the
+            // mean and conic partials are linear in them and are formed once
+            // per record below
+            float s_op = 0.f, q1 = 0.f, q2 = 0.f, s_r = 0.f, s_g = 0.f, s_b = 0.f;
             bool any = false;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -279,34 +285,39 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
                 const float alpha = eval_alpha(ebase, eb, b.x, o, dy, G, pass);
                 const bool ok = pass && (pos < lst[r]);
                 any |= ok;
-                const float om = 1.f - alpha;
-                const float rom = fast_rcp(om);
-                float Tk = ok ? T[r] * rom : T[r];
-                if (kChain && ok) Tk = I.chain[size_t(b0 + uint32_t(i)) * 256 + chain_slot(lane, r)];
-                const float dLda = g0[r] * (Tk * (b.z - acc0[r])) + g1[r] * (Tk * (b.w - acc1[r])) +
-                                   g2[r] * (Tk * (rw.w - acc2[r])) - gbg[r] * rom;
-                const float aT = alpha * Tk;
                 if (ok) {
-                    acc0[r] = fmaf(alpha, b.z, om * acc0[r]);
-                    acc1[r] = fmaf(alpha, b.w, om * acc1[r]);
-                    acc2[r] = fmaf(alpha, rw.w, om * acc2[r]);
+                    const float om = 1.f - alpha;
+                    const float rom = fast_rcp(om);
+                    float Tk = T[r] * rom;
+                    if (kChain) Tk = I.chain[size_t(b0 + uint32_t(i)) * 256 + chain_slot(lane, r)];
+                    const float gc = fmaf(g2[r], rw.w, fmaf(g1[r], b.w, g0[r] * b.z));
+                    const float dLda = fmaf(Tk, gc - S[r], -gbg[r] * rom);
+                    S[r] = fmaf(alpha, gc, om * S[r]);
                     T[r] = Tk;
+                    const float aT = alpha * Tk;
                     s_r = fmaf(g0[r], aT, s_r);
                     s_g = fmaf(g1[r], aT, s_g);
                     s_b = fmaf(g2[r], aT, s_b);
                     // a clamped alpha (o G > 0.99) passes no gradient to o or G;
                     // a select instead of a branch (the clamp is rare)
-                    const float dLdaC = (o * G <= kAlphaMax) ? dLda : 0.f;
-                    s_op = fmaf(dLdaC, G, s_op);
-                    const float dP = dLdaC * o * G;
-                    s_mx -= dP * (rw.x * dx + rw.y * dy);
-                    s_my -= dP * (rw.y * dx + rw.z * dy);
-                    s_ca -= 0.5f * dP * dx * dx;
-                    s_cb -= dP * dx * dy;
-                    s_cc -= 0.5f * dP * dy * dy;
+                    const float u = (o * G <= kAlphaMax) ? dLda * G : 0.f;
+                    s_op += u;
+                    const float uy = u * dy;
+                    q1 += uy;
+                    q2 = fmaf(uy, dy, q2);
                 }
             }
             if (__any(any)) {
+                // dL/dG = o dL/dalpha; dG/dmean = -G (a dx + b dy, b dx + c dy),
+                // dG/d(a, b, c) = -G (dx^2 / 2, dx dy, dy^2 / 2)
+                const float k = o * s_op;
+                const float kx = k * dx;
+                const float qy = o * q1;
+                float s_mx = -fmaf(rw.x, kx, rw.y * qy);
+                float s_my = -fmaf(rw.y, kx, rw.z * qy);
+                float s_ca = -0.5f * kx * dx;
+                float s_cb = -dx * qy;
+                float s_cc = -0.5f * o * q2;
                 // groups of 8 lanes reduce with three DPP steps; the eight group
                 // sums of each partial meet in LDS, and lanes 0..8 each add one
                 // partial (a single atomic instruction for the nine)
