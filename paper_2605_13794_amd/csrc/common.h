@@ -127,6 +127,21 @@ __device__ __forceinline__ float oct_sum8(float v) {
     return v;
 }
 
+// oct_sum8 of several values, step by step, so that the DPP adds of
+// different values interleave (no wait states between dependent DPP reads).
+template <int N>
+__device__ __forceinline__ void oct_sum8_n(float (&v)[N]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        v[k] += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[k]), 0xB1, 0xF, 0xF, false));
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        v[k] += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[k]), 0x4E, 0xF, 0xF, false));
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        v[k] += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[k]), 0x124, 0xF, 0xF, false));
+}
+
 // Sum over each row of 16 lanes (every lane of the row gets the row's sum).
 __device__ __forceinline__ float row_sum16(float v) {
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));

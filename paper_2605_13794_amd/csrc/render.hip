@@ -321,20 +321,13 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
                 // groups of 8 lanes reduce with three DPP steps; the eight group
                 // sums of each partial meet in LDS, and lanes 0..8 each add one
                 // partial (a single atomic instruction for the nine)
-                s_mx = oct_sum8(s_mx);
-                s_my = oct_sum8(s_my);
-                s_ca = oct_sum8(s_ca);
-                s_cb = oct_sum8(s_cb);
-                s_cc = oct_sum8(s_cc);
-                s_op = oct_sum8(s_op);
-                s_r = oct_sum8(s_r);
-                s_g = oct_sum8(s_g);
-                s_b = oct_sum8(s_b);
+                float red[9] = {s_mx, s_my, s_ca, s_cb, s_cc, s_op, s_r, s_g, s_b};
+                oct_sum8_n<9>(red);
                 // every lane stores (keeps the DPP adds fused); lanes 7, 15, ..
                 // hold the group sums
-                sRed[lane][0] = make_float4(s_mx, s_my, s_ca, s_cb);
-                sRed[lane][1] = make_float4(s_cc, s_op, s_r, s_g);
-                sRed[lane][2].x = s_b;
+                sRed[lane][0] = make_float4(red[0], red[1], red[2], red[3]);
+                sRed[lane][1] = make_float4(red[4], red[5], red[6], red[7]);
+                sRed[lane][2].x = red[8];
                 __builtin_amdgcn_wave_barrier();
                 if (lane < 9) {
                     const float* rr = reinterpret_cast<const float*>(&sRed[7][0]) + lane;  // lane 8g+7: rr[96 g]
