@@ -271,21 +271,28 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
             const float ebase = a.z * dx * dx;
             const float eb = a.w * dx;
             const float o = b.y;
-            // per lane, over its composited rows: u = dL/dalpha * G (the
-            // opacity partial), and the moments sum(u dy), sum(u dy^2); the
-            // mean and conic partials are linear in them and are formed once
-            // per record below
-            float s_op = 0.f, q1 = 0.f, q2 = 0.f, s_r = 0.f, s_g = 0.f, s_b = 0.f;
-            bool any = false;
+            // the four rows' alphas first (four independent exponentials in
+            // flight); a record that no pixel of the tile composites is done
+            float alv[4], Gv[4];
+            bool okv[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float dy = a.y - t.fyp[r];
-                float G;
                 bool pass;
-                const float alpha = eval_alpha(ebase, eb, b.x, o, dy, G, pass);
-                const bool ok = pass && (pos < lst[r]);
-                any |= ok;
-                if (ok) {
+                alv[r] = eval_alpha(ebase, eb, b.x, o, a.y - t.fyp[r], Gv[r], pass);
+                okv[r] = pass && (pos < lst[r]);
+            }
+            if (__any(okv[0] || okv[1] || okv[2] || okv[3])) {
+                // per lane, over its composited rows: u = dL/dalpha * G (the
+                // opacity partial), and the moments sum(u dy), sum(u dy^2); the
+                // mean and conic partials are linear in them and are formed
+                // once per record
+                float s_op = 0.f, q1 = 0.f, q2 = 0.f, s_r = 0.f, s_g = 0.f, s_b = 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (!okv[r]) continue;
+                    const float dy = a.y - t.fyp[r];
+                    const float alpha = alv[r];
+                    const float G = Gv[r];
                     const float om = 1.f - alpha;
                     const float rom = fast_rcp(om);
                     float Tk = T[r] * rom;
@@ -306,8 +313,6 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
                     q1 += uy;
                     q2 = fmaf(uy, dy, q2);
                 }
-            }
-            if (__any(any)) {
                 // dL/dG = o dL/dalpha; dG/dmean = -G (a dx + b dy, b dx + c dy),
                 // dG/d(a, b, c) = -G (dx^2 / 2, dx dy, dy^2 / 2)
                 const float k = o * s_op;
