@@ -46,6 +46,9 @@ PEAK_ALU_GOPS = 256 * 4 * 16 * 2.4
 # colour behind, colour, opacity, mean and conic partials).
 ALPHA_OPS = 13.0
 BWD_COMPOSITED_OPS = 37.0
+# Algorithmic bytes of Adam per parameter float: parameter, gradient and both
+# moments read, parameter and moments written (4 B each).
+ADAM_BYTES_PER_FLOAT = 28
 
 
 def parse():
@@ -58,8 +61,9 @@ def parse():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--drop", type=float, default=0.4, help="score-mask drop fraction")
     ap.add_argument("--rmin", type=float, default=0.5, help="projected-radius gate, px")
-    ap.add_argument("--kernel", default="render_bwd", help="kernel timed for the roofline entry "
-                                                          "(render_bwd, or any kernel for its time only)")
+    ap.add_argument("--kernel", default="adam", help="kernel of the roofline entry: adam (the step's largest "
+                                                    "kernel, HBM-bound), render_bwd (ALU-bound), or any kernel "
+                                                    "for its time only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the plain/gated side measurements")
     ap.add_argument("--graph", action="store_true", help="capture the step in a HIP graph and replay it")
@@ -77,9 +81,14 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "render_bwd_1M_city_1080p_traffic.md")
-TRAFFIC_SOURCES = ("paper_2605_13794_amd/csrc/render.hip", "paper_2605_13794_amd/csrc/common.h")
+# Committed HBM traffic per launch (profiler counters) and the sources each
+# figure was taken from.
+TRAFFIC = {
+    "render_bwd": ("render_bwd_1M_city_1080p_traffic.md",
+                   ("paper_2605_13794_amd/csrc/render.hip", "paper_2605_13794_amd/csrc/common.h")),
+    "adam": ("adam_1M_city_1080p_traffic.md",
+             ("paper_2605_13794_amd/csrc/misc.hip", "paper_2605_13794_amd/csrc/common.h")),
+}
 
 
 def recorded_traffic(kernel, args):
@@ -88,17 +97,18 @@ def recorded_traffic(kernel, args):
     kernel or workload, or kernel sources changed since the counters were
     taken (their sha256 is recorded with them)."""
     import hashlib
-    if kernel != "render_bwd" or args.config != "cfg2" or args.layout != "morton" or args.n != 1 << 20 or \
+    if kernel not in TRAFFIC or args.config != "cfg2" or args.layout != "morton" or args.n != 1 << 20 or \
             (args.width, args.height) != (1920, 1080) or args.rmin != 0.5 or args.drop != 0.4:
         return None
+    fname, sources = TRAFFIC[kernel]
+    root = os.path.dirname(os.path.abspath(__file__))
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(os.path.join(root, "profiles", fname)).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith("|"))
-    root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(root, f), "rb").read())
     if fields.get("kernel") != kernel or fields.get("source_sha256") != h.hexdigest():
         return None
@@ -589,6 +599,41 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": src.numel() * 4, "reps": 5}), flush=True)
 
 
+def roofline(b, name, reps, args):
+    """Roofline entry of kernel `name`: its average launch duration over `reps`
+    steps (HIP events around its own launches) against its algorithmic work
+    per launch."""
+    torch = b.torch
+    kms = b.kernel_time(name, b.step, reps)
+    if name == "adam":
+        floats = sum(int(p.numel()) for p in b.ds.params())
+        nbytes = ADAM_BYTES_PER_FLOAT * floats
+        achieved = nbytes / (kms * 1e-3) / 1e9
+        return dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
+                    traffic=recorded_traffic(name, args), kernel=name, ms=kms, bytes_per_launch=nbytes,
+                    floats=floats, bytes_per_float=ADAM_BYTES_PER_FLOAT)
+    if name == "render_bwd":
+        # algorithmic work of one launch on the gated frame (the step leaves
+        # the gated frame's lists and forward outputs in place)
+        G = b.G
+        last_sum = int(b.fr.last[0].to(torch.int64).sum().item())
+        a2 = torch.empty(b.n, dtype=torch.int32, device=b.dev)
+        w2, s2 = torch.empty(b.n, device=b.dev), torch.zeros(b.n, device=b.dev)
+        c2 = torch.zeros(b.n, dtype=torch.int32, device=b.dev)
+        cull2 = torch.zeros((b.n + 31) // 32, dtype=torch.int32, device=b.dev)
+        G.gs_importance(b.fr.proj[0].struct(), b.camc, b.n, b.fr.vals, b.fr.ranges, 0.99, 1e-6, w2, a2, s2, c2,
+                        c2.clone(), cull2, b.ws_imp)
+        composited = int(a2.to(torch.int64).sum().item())
+        ops = ALPHA_OPS * last_sum + BWD_COMPOSITED_OPS * composited
+        achieved = ops / (kms * 1e-3) / 1e12
+        return dict(bound="alu", achieved=achieved, peak=PEAK_ALU_GOPS / 1e3, unit="TOP/s",
+                    frac=achieved / (PEAK_ALU_GOPS / 1e3), traffic=recorded_traffic(name, args), kernel=name,
+                    ms=kms, positions=last_sum, composited=composited, ops_per_position=ALPHA_OPS,
+                    ops_per_composited=BWD_COMPOSITED_OPS)
+    return dict(bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s", frac=None, traffic=None,
+                kernel=name, ms=kms)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -620,32 +665,11 @@ def main():
             lambda: b.importance_view(b.fr_all, b.camc, b.sweep_views), args.steps, 2)
         b.check_capacity()
         extras["psnr_gated_vs_plain_db"] = b.psnr_gated_vs_plain()
-    # dominant kernel: live HIP-event timing inside the same process
-    name = args.kernel
+    # roofline entries: live HIP-event timing inside the same process
     reps = max(5, min(args.steps, 20))
-    kms = b.kernel_time(name, b.step, reps)
-    # algorithmic work of one launch of that kernel on the gated frame (the
-    # step leaves the gated frame's lists and forward outputs in place)
-    last_sum = int(b.fr.last[0].to(torch.int64).sum().item())
+    roof = roofline(b, args.kernel, reps, args)
+    roof_blend = roofline(b, "render_bwd", reps, args) if args.kernel != "render_bwd" else None
     pairs = int(b.fr.n_pairs.item())
-    if name == "render_bwd":
-        G = b.G
-        a2 = torch.empty(b.n, dtype=torch.int32, device=b.dev)
-        w2, s2 = torch.empty(b.n, device=b.dev), torch.zeros(b.n, device=b.dev)
-        c2 = torch.zeros(b.n, dtype=torch.int32, device=b.dev)
-        cull2 = torch.zeros((b.n + 31) // 32, dtype=torch.int32, device=b.dev)
-        G.gs_importance(b.fr.proj[0].struct(), b.camc, b.n, b.fr.vals, b.fr.ranges, 0.99, 1e-6, w2, a2, s2, c2,
-                        c2.clone(), cull2, b.ws_imp)
-        composited = int(a2.to(torch.int64).sum().item())
-        ops = ALPHA_OPS * last_sum + BWD_COMPOSITED_OPS * composited
-        achieved = ops / (kms * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=PEAK_ALU_GOPS / 1e3, unit="TOP/s",
-                    frac=achieved / (PEAK_ALU_GOPS / 1e3), traffic=recorded_traffic(name, args), kernel=name, ms=kms,
-                    positions=last_sum, composited=composited, ops_per_position=ALPHA_OPS,
-                    ops_per_composited=BWD_COMPOSITED_OPS)
-    else:
-        roof = dict(bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s", frac=None, traffic=None,
-                    kernel=name, ms=kms)
     px = args.width * args.height
     out = {
         "metric": METRIC,
@@ -672,6 +696,8 @@ def main():
         "pairs_plain": int(b.fr_all.n_pairs.item()),
         "roofline": roof,
     }
+    if roof_blend is not None:
+        out["roofline_blend"] = roof_blend
     out.update(extras)
     if "gated_train_ms" in extras:
         out["gated_train_it_per_s"] = 1e3 / extras["gated_train_ms"]

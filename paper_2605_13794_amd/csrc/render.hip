@@ -123,19 +123,19 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
     __shared__ float2 sC[64];  // (b channel, strip reach)
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
-    // T > 0 while a pixel is still blending; a finished (or outside) pixel
-    // keeps its transmittance with the sign flipped
-    float T[4], C0[4], C1[4], C2[4];
+    // thr: the smallest alpha a pixel still composites, 1/255 while it blends
+    // and 2 (unreachable) once it has stopped or lies outside the image
+    float T[4], thr[4], C0[4], C1[4], C2[4];
     uint32_t last[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        T[r] = t.valid[r] ? 1.f : -1.f; C0[r] = C1[r] = C2[r] = 0.f; last[r] = 0;
+        T[r] = 1.f; thr[r] = t.valid[r] ? kAlphaMin : 2.f; C0[r] = C1[r] = C2[r] = 0.f; last[r] = 0;
     }
     const int lane = threadIdx.x;
     RawRec R = {};
     fetch_record(rec, vals, t.start, t.end, lane, R);
     for (uint32_t b0 = t.start; b0 < t.end; b0 += 64) {
-        if (__all(T[0] < 0.f && T[1] < 0.f && T[2] < 0.f && T[3] < 0.f)) break;
+        if (__all(thr[0] > 1.f && thr[1] > 1.f && thr[2] > 1.f && thr[3] > 1.f)) break;
         const uint32_t nb = min(64u, t.end - b0);
         __syncthreads();
         if (uint32_t(lane) < nb) {
@@ -155,11 +155,12 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 if (fabsf(a.y - (t.ymid0 + 4.f * float(r))) > ce.y) continue;
-                float G;
-                bool pass;
-                const float alpha = eval_alpha(ebase, eb, b.x, b.y, a.y - t.fyp[r], G, pass);
+                const float e2 = gauss_e2(ebase, eb, b.x, a.y - t.fyp[r]);
+                const float alpha = fminf(kAlphaMax, b.y * fast_exp2(e2));
+                // the same decisions as eval_alpha's, with a stopped pixel's
+                // threshold out of reach
+                const bool ok = (e2 <= 0.f) && (alpha >= thr[r]);
                 const float Tn = T[r] * (1.f - alpha);
-                const bool ok = pass && T[r] > 0.f;
                 const bool stop = ok && (Tn < kTMin);
                 const bool comp = ok && !stop;
                 const float wgt = comp ? alpha * T[r] : 0.f;
@@ -167,10 +168,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
                 C0[r] = fmaf(wgt, b.z, C0[r]);
                 C1[r] = fmaf(wgt, b.w, C1[r]);
                 C2[r] = fmaf(wgt, cb, C2[r]);
-                T[r] = comp ? Tn : (stop ? -T[r] : T[r]);
+                T[r] = comp ? Tn : T[r];
+                thr[r] = stop ? 2.f : thr[r];
                 last[r] = comp ? pos : last[r];
             }
-            if (__all(T[0] < 0.f && T[1] < 0.f && T[2] < 0.f && T[3] < 0.f)) break;
+            if (__all(thr[0] > 1.f && thr[1] > 1.f && thr[2] > 1.f && thr[3] > 1.f)) break;
         }
     }
     const int W = A.W[t.c], H = A.H[t.c];
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
     for (int r = 0; r < 4; ++r) {
         if (!t.valid[r]) continue;
         const size_t p = size_t(t.py0 + 4 * r) * W + t.px;
-        const float Tf = fabsf(T[r]);
+        const float Tf = T[r];
         O.rgb[t.c][p] = fmaf(Tf, O.bg[0], C0[r]);
         O.rgb[t.c][plane + p] = fmaf(Tf, O.bg[1], C1[r]);
         O.rgb[t.c][2 * plane + p] = fmaf(Tf, O.bg[2], C2[r]);
@@ -363,14 +365,17 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
     __shared__ float2 sRed[64];
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
-    float T[4];  // sign flipped once the pixel has stopped (or lies outside)
+    float T[4], thr[4];  // thr as in the forward: 2 once the pixel has stopped (or lies outside)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) T[r] = t.valid[r] ? 1.f : -1.f;
+    for (int r = 0; r < 4; ++r) {
+        T[r] = 1.f;
+        thr[r] = t.valid[r] ? kAlphaMin : 2.f;
+    }
     const int lane = threadIdx.x;
     RawRec R = {};
     fetch_record(rec, vals, t.start, t.end, lane, R);
     for (uint32_t b0 = t.start; b0 < t.end; b0 += 64) {
-        if (__all(T[0] < 0.f && T[1] < 0.f && T[2] < 0.f && T[3] < 0.f)) break;
+        if (__all(thr[0] > 1.f && thr[1] > 1.f && thr[2] > 1.f && thr[3] > 1.f)) break;
         const uint32_t nb = min(64u, t.end - b0);
         __syncthreads();
         if (uint32_t(lane) < nb) {
@@ -387,26 +392,27 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
             const float dx = a.x - t.fxp;
             const float ebase = a.z * dx * dx;
             const float eb = a.w * dx;
-            float sw = 0.f;
-            uint32_t sn = 0;
+            float sw = 0.f, sn = 0.f;  // the count as a float (exact, at most 4)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 if (fabsf(a.y - (t.ymid0 + 4.f * float(r))) > b.z) continue;
-                float G;
-                bool pass;
-                const float alpha = eval_alpha(ebase, eb, b.x, b.y, a.y - t.fyp[r], G, pass);
+                const float e2 = gauss_e2(ebase, eb, b.x, a.y - t.fyp[r]);
+                const float alpha = fminf(kAlphaMax, b.y * fast_exp2(e2));
+                const bool ok = (e2 <= 0.f) && (alpha >= thr[r]);
                 const float Tn = T[r] * (1.f - alpha);
-                const bool ok = pass && T[r] > 0.f;
                 const bool stop = ok && (Tn < kTMin);
                 const bool comp = ok && !stop;
                 sw += comp ? alpha * T[r] : 0.f;
-                sn += comp ? 1u : 0u;
-                T[r] = comp ? Tn : (stop ? -T[r] : T[r]);
+                sn += comp ? 1.f : 0.f;
+                T[r] = comp ? Tn : T[r];
+                thr[r] = stop ? 2.f : thr[r];
             }
-            if (__any(sn > 0)) {
+            if (__any(sn > 0.f)) {
                 // groups of 8 lanes reduce with DPP; lanes 0 and 1 add the
                 // eight group sums of w and of the count and issue one atomic
-                sRed[lane] = make_float2(oct_sum8(sw), oct_sum8(float(sn)));
+                float red[2] = {sw, sn};
+                oct_sum8_n<2>(red);
+                sRed[lane] = make_float2(red[0], red[1]);
                 __builtin_amdgcn_wave_barrier();
                 if (lane < 2) {
                     const float* rr = reinterpret_cast<const float*>(&sRed[7]) + lane;  // lane 8g+7: rr[16 g]
@@ -415,7 +421,7 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-            if (__all(T[0] < 0.f && T[1] < 0.f && T[2] < 0.f && T[3] < 0.f)) break;
+            if (__all(thr[0] > 1.f && thr[1] > 1.f && thr[2] > 1.f && thr[3] > 1.f)) break;
         }
     }
 }
