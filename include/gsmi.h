@@ -222,11 +222,16 @@ int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int n_cams, int
  * pair k at pixel slot s of its tile (s = lane + 64 r for the pixel at
  * column lane % 16, row lane / 16 + 4 r), written where that pair is
  * composited.  It lets gs_render_bwd read the chain instead of recomputing.
+ * pair_live (optional, NULL = not written): [K] bytes; entry k is set to 1 if
+ * some pixel of its tile composites sorted pair k, else 0 (entries past the
+ * point where every pixel of the tile has stopped may be left unwritten:
+ * they lie beyond every pixel's `last`).  gs_render_bwd skips the pairs
+ * marked 0.
  */
 int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, int n_cams,
                   const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
                   float* const* out_rgb, float* const* out_T, uint32_t* const* out_last,
-                  float* chain, hipStream_t stream);
+                  float* chain, uint8_t* pair_live, hipStream_t stream);
 
 /*
  * Backward of gs_render_fwd and gs_project: given dL/dC (grad_rgb[c],
@@ -245,14 +250,17 @@ int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, int n_cams,
  * ([9][n_in]: d mean2d (2), d conic (3), d opacity (1), d rgb (3)).
  * chain: NULL (recompute T from the final T) or the chain the forward stored;
  * then T_k is read instead of recomputed.
+ * pair_live: NULL, or the flags the forward wrote for these lists and outputs;
+ * pairs marked 0 (composited by no pixel, hence contributing nothing) are
+ * skipped.  The result is the same either way.
  * Workspace: GS_OP_RENDER_BWD (n = n_in, n_cams).
  */
 int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in,
                   const int64_t* n_in_dev, const gs_projected* proj, const gs_camera* cams,
                   int n_cams, const uint32_t* vals, const uint32_t* tile_ranges, const float* bg,
                   float* const* out_T, uint32_t* const* out_last, float* const* grad_rgb,
-                  const float* chain, gs_grads* grads, float* grads2d, void* ws, size_t ws_bytes,
-                  hipStream_t stream);
+                  const float* chain, const uint8_t* pair_live, gs_grads* grads, float* grads2d,
+                  void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * One view of the importance-scoring sweep (Sec. 3.2 "Importance score",

@@ -108,7 +108,8 @@ struct FwdOut {
     float* rgb[GS_MAX_CAMS];
     float* T[GS_MAX_CAMS];
     uint32_t* last[GS_MAX_CAMS];
-    float* chain;  // optional: [pairs][256] transmittance before each composited position
+    float* chain;   // optional: [pairs][256] transmittance before each composited position
+    uint8_t* live;  // optional: [pairs], 1 if some pixel of the tile composites the pair
     float bg[3];
 };
 
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
         }
         __syncthreads();
         fetch_record(rec, vals, b0 + 64, t.end, lane, R);  // next batch in flight during the blend
+        uint64_t lmask = 0;  // bit i: some pixel composites record b0 + i
         for (uint32_t i = 0; i < nb; ++i) {
             const float4 a = sA[i];
             const float4 b = sB[i];
@@ -152,6 +154,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
             const float ebase = a.z * dx * dx;
             const float eb = a.w * dx;
             const uint32_t pos = b0 - t.start + i + 1;
+            bool any_comp = false;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 if (fabsf(a.y - (t.ymid0 + 4.f * float(r))) > ce.y) continue;
@@ -171,9 +174,13 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
                 T[r] = comp ? Tn : T[r];
                 thr[r] = stop ? 2.f : thr[r];
                 last[r] = comp ? pos : last[r];
+                any_comp |= comp;
             }
+            if (__any(any_comp)) lmask |= 1ull << i;
             if (__all(thr[0] > 1.f && thr[1] > 1.f && thr[2] > 1.f && thr[3] > 1.f)) break;
         }
+        // records after an early stop stay 0: they lie beyond every pixel's last
+        if (O.live && uint32_t(lane) < nb) O.live[b0 + lane] = uint8_t((lmask >> lane) & 1u);
     }
     const int W = A.W[t.c], H = A.H[t.c];
     const size_t plane = size_t(W) * H;
@@ -199,6 +206,7 @@ struct BwdImg {
     const float* grad[GS_MAX_CAMS];
     float* d2[GS_MAX_CAMS];  // [n_in][kD2Stride]
     const float* chain;      // optional stored transmittance chain
+    const uint8_t* live;     // optional: the forward's per-pair "composited in the tile" flags
     int64_t n_in;
     float bg[3];
 };
@@ -246,9 +254,11 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
     float* d2 = I.d2[t.c];
     const uint32_t stop_at = t.start + min(lmax, t.end - t.start);
     RawRec R = {};
+    uint32_t lv = 1;  // live flag of this lane's prefetched record
     if (stop_at > t.start) {
         const uint32_t nb0 = min(64u, stop_at - t.start);
         fetch_record(rec, vals, stop_at - nb0, stop_at, lane, R);
+        if (I.live && stop_at - nb0 + uint32_t(lane) < stop_at) lv = I.live[stop_at - nb0 + lane];
     }
     for (uint32_t b_end = stop_at; b_end > t.start;) {
         const uint32_t nb = min(64u, b_end - t.start);
@@ -259,12 +269,17 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
             sR[lane] = make_float4(R.q0.z, R.q0.w, R.q1.x, R.q2);
             sJ[lane] = R.j;
         }
+        // records that no pixel of the tile composites contribute nothing
+        uint64_t todo = ballot(uint32_t(lane) < nb && lv != 0);
         __syncthreads();
         if (b0 > t.start) {  // the preceding batch, fetched during this one
             const uint32_t nbn = min(64u, b0 - t.start);
             fetch_record(rec, vals, b0 - nbn, b0, lane, R);
+            if (I.live && b0 - nbn + uint32_t(lane) < b0) lv = I.live[b0 - nbn + lane];
         }
-        for (int i = int(nb) - 1; i >= 0; --i) {
+        while (todo) {  // back to front over the live records
+            const int i = 63 - __builtin_clzll(todo);
+            todo &= ~(1ull << i);
             const float4 a = sA[i];
             const float4 b = sB[i];
             const float4 rw = sR[i];
@@ -482,7 +497,8 @@ size_t ws_render_bwd(int64_t n, int n_cams) {
 
 extern "C" int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, int n_cams, const uint32_t* vals,
                              const uint32_t* tile_ranges, const float* bg, float* const* out_rgb,
-                             float* const* out_T, uint32_t* const* out_last, float* chain, hipStream_t stream) {
+                             float* const* out_T, uint32_t* const* out_last, float* chain, uint8_t* pair_live,
+                             hipStream_t stream) {
     if (!proj || !tile_ranges || !bg || !out_rgb || !out_T || !out_last)
         return fail(GS_ERR_INVALID_ARG, "gs_render_fwd: null argument");
     RenderCams A;
@@ -497,6 +513,7 @@ extern "C" int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, in
     }
     O.bg[0] = bg[0]; O.bg[1] = bg[1]; O.bg[2] = bg[2];
     O.chain = chain;
+    O.live = pair_live;
     if (tt == 0) return GS_OK;
     if (O.chain)
         launch("render_fwd", k_render_fwd<true>, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, tile_ranges,
@@ -510,7 +527,8 @@ extern "C" int gs_render_fwd(const gs_projected* proj, const gs_camera* cams, in
 extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in, const int64_t* n_in_dev,
                              const gs_projected* proj, const gs_camera* cams, int n_cams, const uint32_t* vals,
                              const uint32_t* tile_ranges, const float* bg, float* const* out_T,
-                             uint32_t* const* out_last, float* const* grad_rgb, const float* chain, gs_grads* grads,
+                             uint32_t* const* out_last, float* const* grad_rgb, const float* chain,
+                             const uint8_t* pair_live, gs_grads* grads,
                              float* grads2d, void* ws, size_t ws_bytes, hipStream_t stream) {
     int rc = check_scene(scene);
     if (rc) return rc;
@@ -542,6 +560,7 @@ extern "C" int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, i
     if ((rc = launch_visible_list(n_in, n_in_dev, n_cams, I.d2, proj, vis_list, vis_count, stream))) return rc;
     I.n_in = n_in;
     I.chain = chain;
+    I.live = pair_live;
     I.bg[0] = bg[0]; I.bg[1] = bg[1]; I.bg[2] = bg[2];
     if (tt > 0 && n_in > 0)
     {

@@ -80,8 +80,8 @@ def lib() -> ctypes.CDLL:
         L.gs_lod_mask.argtypes = [P, P, P, P, P, P, P, c_sz, P]
         L.gs_project.argtypes = [P, P, c_i64, P, P, c_int, P, P, c_sz, P]
         L.gs_bin_sort.argtypes = [P, P, c_int, c_i64, P, P, c_i64, P, P, P, c_sz, P]
-        L.gs_render_fwd.argtypes = [P, P, c_int, P, P, P, P, P, P, P, P]
-        L.gs_render_bwd.argtypes = [P, P, c_i64, P, P, P, c_int, P, P, P, P, P, P, P, P, P, P, c_sz, P]
+        L.gs_render_fwd.argtypes = [P, P, c_int, P, P, P, P, P, P, P, P, P]
+        L.gs_render_bwd.argtypes = [P, P, c_i64, P, P, P, c_int, P, P, P, P, P, P, P, P, P, P, P, c_sz, P]
         L.gs_importance.argtypes = [P, P, c_i64, P, P, c_f, c_f, P, P, P, P, P, P, P, c_sz, P]
         L.gs_score_keep_bits.argtypes = [P, c_i64, c_i64, P, P, c_sz, P]
         L.gs_l1_loss.argtypes = [P, P, c_i64, P, P, P, c_sz, P]
@@ -222,21 +222,23 @@ def gs_bin_sort(projs, cams, n_in, keys, vals, capacity, tile_ranges, n_pairs_de
            "gs_bin_sort")
 
 
-def gs_render_fwd(projs, cams, vals, tile_ranges, bg, out_rgb, out_T, out_last, chain=None, stream=None):
+def gs_render_fwd(projs, cams, vals, tile_ranges, bg, out_rgb, out_T, out_last, chain=None, live=None,
+                  stream=None):
     parr = (GsProjected * len(projs))(*projs)
     bgv = (c_f * 3)(*[float(x) for x in bg])
     _check(lib().gs_render_fwd(parr, cams, len(cams), ptr(vals), ptr(tile_ranges), bgv, _ptr_array(out_rgb),
-                               _ptr_array(out_T), _ptr_array(out_last), ptr(chain), stream_handle(stream)),
-           "gs_render_fwd")
+                               _ptr_array(out_T), _ptr_array(out_last), ptr(chain), ptr(live),
+                               stream_handle(stream)), "gs_render_fwd")
 
 
 def gs_render_bwd(scn: GsScene, active_idx, n_in, n_in_dev, projs, cams, vals, tile_ranges, bg, out_T, out_last,
-                  grad_rgb, grd: GsGrads, grads2d, ws, chain=None, stream=None):
+                  grad_rgb, grd: GsGrads, grads2d, ws, chain=None, live=None, stream=None):
     parr = (GsProjected * len(projs))(*projs)
     bgv = (c_f * 3)(*[float(x) for x in bg])
     _check(lib().gs_render_bwd(ctypes.byref(scn), ptr(active_idx), int(n_in), ptr(n_in_dev), parr, cams, len(cams),
                                ptr(vals), ptr(tile_ranges), bgv, _ptr_array(out_T), _ptr_array(out_last),
-                               _ptr_array(grad_rgb), ptr(chain), ctypes.byref(grd), ptr(grads2d), ptr(ws), ws.numel(),
+                               _ptr_array(grad_rgb), ptr(chain), ptr(live), ctypes.byref(grd), ptr(grads2d), ptr(ws),
+                               ws.numel(),
                                stream_handle(stream)), "gs_render_bwd")
 
 

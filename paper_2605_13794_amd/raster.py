@@ -107,7 +107,7 @@ class Frame:
         self.ranges = torch.empty(2 * self.total_tiles, dtype=I32, device=self.device)
         self.n_pairs = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.capacity = 0
-        self.keys = self.vals = None
+        self.keys = self.vals = self.live = None
         self.ws_sort = Workspace(self.device)
         self.ws_proj = Workspace(self.device)
         self.ws_bwd = Workspace(self.device)
@@ -135,6 +135,9 @@ class Frame:
         self.capacity = cap
         self.keys = torch.empty(cap, dtype=torch.int64, device=self.device)
         self.vals = torch.empty(cap, dtype=I32, device=self.device)
+        # per pair: composited by some pixel of its tile (written by the
+        # forward, lets the backward skip the others)
+        self.live = torch.empty(cap, dtype=torch.uint8, device=self.device)
         self.chain = None
 
     def proj_structs(self):
@@ -169,7 +172,7 @@ class Frame:
                 self.chain = torch.empty(need, dtype=F32, device=self.device)
             chain = self.chain
         G.gs_render_fwd(self.proj_structs(), self.cam_arr, self.vals, self.ranges, self.bg, self.rgb, self.T,
-                        self.last, chain, stream)
+                        self.last, chain=chain, live=self.live, stream=stream)
         return FrameOutputs(self.rgb, self.T, self.last)
 
     def forward(self, scn, active=None, n_in=None, n_in_dev=None, bg=(0.0, 0.0, 0.0), check=True, stream=None):
@@ -190,7 +193,7 @@ class Frame:
         ws = self.ws_bwd.get(G.gs_workspace_size(G.GS_OP_RENDER_BWD, self.n_in, 0, 0, len(self.cams)))
         G.gs_render_bwd(scn, self.active, self.n_in, self.n_in_dev, self.proj_structs(), self.cam_arr, self.vals,
                         self.ranges, self.bg, self.T, self.last, g, grd, grads2d, ws,
-                        self.chain if self.store_chain else None, stream)
+                        chain=self.chain if self.store_chain else None, live=self.live, stream=stream)
 
 
 class RasterizeFn(torch.autograd.Function):

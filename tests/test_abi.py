@@ -61,7 +61,7 @@ def test_host_side_errors(G):
     assert L.gs_bin_sort(None, cams, 1, 10, None, None, 0, None, None, None, 0, None) == G.GS_ERR_INVALID_ARG
     bad = G.camera_array([S.cube_camera(0, 10)])
     dummy = (G.GsProjected * 1)()
-    assert L.gs_render_fwd(dummy, bad, 1, None, None, None, None, None, None, None, None) == G.GS_ERR_INVALID_ARG
+    assert L.gs_render_fwd(dummy, bad, 1, None, None, None, None, None, None, None, None, None) == G.GS_ERR_INVALID_ARG
     assert L.gs_adam_step(None, None, None, None, None, 0, None, 0.9, 0.999, 1e-8, 1, None, 0, None) == G.GS_ERR_INVALID_ARG
     assert L.gs_score_keep_bits(None, 10, 3, None, None, 0, None) == G.GS_ERR_INVALID_ARG
     # workspace too small is reported before any launch

@@ -321,14 +321,40 @@ def test_render_bwd_matches_reference(oracle, case):
     g3 = torch.empty(9, sc.n, device=dev)
     G.gs_render_bwd(ds.struct(), None, sc.n, None, [pb.struct()], cams, v, r, bg, [T], [last], [gt],
                     G.grads(*grads), g3, ws, chain=chain)
+    # the forward's per-pair flags (composited by some pixel of the tile) let
+    # the backward skip the other pairs without changing the partials
+    live = torch.full((max(K, 1),), 7, dtype=torch.uint8, device=dev)
+    G.gs_render_fwd([pb.struct()], cams, v, r, bg, [img], [T], [last], live=live)
+    g4 = torch.empty(9, sc.n, device=dev)
+    G.gs_render_bwd(ds.struct(), None, sc.n, None, [pb.struct()], cams, v, r, bg, [T], [last], [gt],
+                    G.grads(*grads), g4, ws, live=live)
     torch.cuda.synchronize()
     got = to_np(g2)
     rows = {"mean2d": (0, 2), "conic": (2, 5), "opacity": (5, 6), "rgb": (6, 9)}
     got3 = to_np(g3)
+    got4 = to_np(g4)
     for name, (a, b) in rows.items():
         refv = d2[name].reshape(b - a, -1)
         assert _rel_inf(got[a:b], refv) <= 1e-3, (name, _rel_inf(got[a:b], refv))
         assert _rel_inf(got3[a:b], refv) <= 1e-3, ("stored chain", name, _rel_inf(got3[a:b], refv))
+        assert _rel_inf(got4[a:b], refv) <= 1e-3, ("live flags", name, _rel_inf(got4[a:b], refv))
+        # same contributions, only the order of the atomic adds may differ
+        scale = max(float(np.abs(got[a:b]).max()), 1e-30)
+        assert float(np.abs(got4[a:b] - got[a:b]).max()) <= 1e-5 * scale, ("live flags vs all pairs", name)
+    # flags are 0 or 1 below each tile's largest `last`, and the pair at every
+    # pixel's last composited position is live
+    lv = to_np(live).astype(np.int64)
+    lastn = ref["last"].astype(np.int64)
+    TXn, TYn = (W + 15) // 16, (H + 15) // 16
+    rr = np.asarray(ranges, dtype=np.int64).reshape(2, -1)
+    py, px = np.nonzero(lastn)
+    tile = (py // 16) * TXn + px // 16
+    assert np.all(lv[rr[0, tile] + lastn[py, px] - 1] == 1)
+    pad = np.zeros((TYn * 16, TXn * 16), dtype=np.int64)
+    pad[:H, :W] = lastn
+    lmax = pad.reshape(TYn, 16, TXn, 16).max(axis=(1, 3)).reshape(-1)
+    below = np.concatenate([lv[rr[0, t]:rr[0, t] + lmax[t]] for t in range(rr.shape[1])] + [np.zeros(0, np.int64)])
+    assert np.all((below == 0) | (below == 1))
 
 
 # ---------------------------------------------------------------------------
