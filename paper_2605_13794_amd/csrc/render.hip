@@ -94,6 +94,17 @@ __device__ __forceinline__ float strip_reach(const RawRec& R) {
     return sqrtf(2.f * t * a / det) * 1.001f + 0.5f + 1.5f;
 }
 
+// Strips of this tile (bit r: rows 4r..4r+3) that a record can reach,
+// computed once per record when it is staged, so the blend loop tests a bit
+// of a wavefront-uniform mask instead of comparing per strip.
+__device__ __forceinline__ uint32_t strip_mask(const RawRec& R, float ymid0) {
+    const float reach = strip_reach(R);
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m |= (fabsf(R.q0.y - (ymid0 + 4.f * float(r))) > reach) ? 0u : (1u << r);
+    return m;
+}
+
 // alpha of a staged record at one pixel; identical in forward and backward.
 __device__ __forceinline__ float eval_alpha(float ebase, float eb, float nc, float o, float dy, float& G,
                                             bool& pass) {
@@ -121,7 +132,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
                                                    const uint32_t* __restrict__ ranges, uint32_t n_tiles, FwdOut O) {
     __shared__ float4 sA[64];
     __shared__ float4 sB[64];
-    __shared__ float2 sC[64];  // (b channel, strip reach)
+    __shared__ float2 sC[64];  // (b channel, strip mask bits)
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
     const float* rec = A.rec[t.c];
     // thr: the smallest alpha a pixel still composites, 1/255 while it blends
@@ -140,7 +151,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
         const uint32_t nb = min(64u, t.end - b0);
         __syncthreads();
         if (uint32_t(lane) < nb) {
-            sA[lane] = scaled_a(R); sB[lane] = scaled_b(R); sC[lane] = make_float2(R.q2, strip_reach(R));
+            sA[lane] = scaled_a(R); sB[lane] = scaled_b(R);
+            sC[lane] = make_float2(R.q2, __uint_as_float(strip_mask(R, t.ymid0)));
         }
         __syncthreads();
         fetch_record(rec, vals, b0 + 64, t.end, lane, R);  // next batch in flight during the blend
@@ -150,6 +162,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
             const float4 b = sB[i];
             const float2 ce = sC[i];
             const float cb = ce.x;
+            const uint32_t smask = __builtin_amdgcn_readfirstlane(__float_as_uint(ce.y));
             const float dx = a.x - t.fxp;
             const float ebase = a.z * dx * dx;
             const float eb = a.w * dx;
@@ -157,7 +170,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t*
             bool any_comp = false;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                if (fabsf(a.y - (t.ymid0 + 4.f * float(r))) > ce.y) continue;
+                if (!((smask >> r) & 1u)) continue;
                 const float e2 = gauss_e2(ebase, eb, b.x, a.y - t.fyp[r]);
                 const float alpha = fminf(kAlphaMax, b.y * fast_exp2(e2));
                 // the same decisions as eval_alpha's, with a stopped pixel's
@@ -375,7 +388,7 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
                                                          const uint32_t* __restrict__ ranges, uint32_t n_tiles,
                                                          float* __restrict__ wa) {
     __shared__ float4 sA[64];
-    __shared__ float4 sB[64];  // (nc, o, strip reach, -)
+    __shared__ float4 sB[64];  // (nc, o, strip mask bits, -)
     __shared__ uint32_t sJ[64];
     __shared__ float2 sRed[64];
     const TileCtx t = tile_ctx(A, ranges, n_tiles);
@@ -396,7 +409,7 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
         if (uint32_t(lane) < nb) {
             const float4 b = scaled_b(R);
             sA[lane] = scaled_a(R);
-            sB[lane] = make_float4(b.x, b.y, strip_reach(R), 0.f);
+            sB[lane] = make_float4(b.x, b.y, __uint_as_float(strip_mask(R, t.ymid0)), 0.f);
             sJ[lane] = R.j;
         }
         __syncthreads();
@@ -404,13 +417,14 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
         for (uint32_t i = 0; i < nb; ++i) {
             const float4 a = sA[i];
             const float4 b = sB[i];
+            const uint32_t smask = __builtin_amdgcn_readfirstlane(__float_as_uint(b.z));
             const float dx = a.x - t.fxp;
             const float ebase = a.z * dx * dx;
             const float eb = a.w * dx;
             float sw = 0.f, sn = 0.f;  // the count as a float (exact, at most 4)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                if (fabsf(a.y - (t.ymid0 + 4.f * float(r))) > b.z) continue;
+                if (!((smask >> r) & 1u)) continue;
                 const float e2 = gauss_e2(ebase, eb, b.x, a.y - t.fyp[r]);
                 const float alpha = fminf(kAlphaMax, b.y * fast_exp2(e2));
                 const bool ok = (e2 <= 0.f) && (alpha >= thr[r]);
