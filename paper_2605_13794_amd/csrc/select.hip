@@ -96,8 +96,8 @@ struct GateArgs {
 __global__ __launch_bounds__(256) void k_gate(GateArgs G, int64_t chunk, uint32_t* __restrict__ gate_words,
                                               uint32_t* __restrict__ c_gate, uint32_t* __restrict__ c_act,
                                               uint32_t* __restrict__ c_keep) {
-    __shared__ uint32_t w4[4];
-    uint32_t ng = 0, na = 0, nk = 0;
+    __shared__ uint32_t w4[3][4];
+    uint32_t ng = 0, na = 0, nk = 0;  // per wavefront; summed over the workgroup at the end
     for (int64_t base = int64_t(blockIdx.x) * chunk; base < min<int64_t>(G.n, int64_t(blockIdx.x + 1) * chunk);
          base += kBlk) {
         const int64_t i = base + threadIdx.x;
@@ -125,18 +125,21 @@ __global__ __launch_bounds__(256) void k_gate(GateArgs G, int64_t chunk, uint32_
         const bool keep = in && (G.keep ? bit_of(G.keep, i) : true);
         const uint64_t mg = ballot(gate);
         store_bits(gate_words, G.n, base + (threadIdx.x / 64) * 64, mg);
-        uint32_t t;
-        block_rank(gate, w4, &t);
-        ng += t;
-        block_rank(gate && keep, w4, &t);
-        na += t;
-        block_rank(keep, w4, &t);
-        nk += t;
+        ng += popc64(mg);
+        na += popc64(ballot(gate && keep));
+        nk += popc64(ballot(keep));
     }
+    const int w = threadIdx.x / 64;
+    if (lane_id() == 0) {
+        w4[0][w] = ng;
+        w4[1][w] = na;
+        w4[2][w] = nk;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        c_gate[blockIdx.x] = ng;
-        c_act[blockIdx.x] = na;
-        c_keep[blockIdx.x] = nk;
+        c_gate[blockIdx.x] = w4[0][0] + w4[0][1] + w4[0][2] + w4[0][3];
+        c_act[blockIdx.x] = w4[1][0] + w4[1][1] + w4[1][2] + w4[1][3];
+        c_keep[blockIdx.x] = w4[2][0] + w4[2][1] + w4[2][2] + w4[2][3];
     }
 }
 
