@@ -192,9 +192,18 @@ __device__ __forceinline__ uint32_t maybe_visible(const CamSet& C, const float m
 
 // Pass 1 (low register count): entries that cannot be visible in any camera
 // get their culled outputs; the others are appended to `list` (one atomic per
-// workgroup of kCullChunk entries).
-constexpr int kCullChunk = 2048;
+// workgroup of kChunk entries).
+//
+// Chunk sizes of the list-building kernels: small inputs use 512 entries per
+// workgroup (more workgroups in flight: 15 -> 10 us for the cull and 17 -> 7 us
+// for the visible list on a 0.6M-entry view); large ones use bigger chunks so
+// that the single counter sees at most a few thousand atomics.
+constexpr int64_t kSmallListInput = 2 << 20;
+constexpr int kChunkSmall = 512;
+constexpr int kCullChunkLarge = 2048;
+constexpr int kVisChunkLarge = 4096;
 
+template <int kChunk>
 __global__ __launch_bounds__(256) void k_project_cull(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
                                                       const int64_t* __restrict__ n_in_dev, CamSet C, ProjOut O,
                                                       uint32_t* __restrict__ list, uint32_t* __restrict__ count) {
@@ -202,10 +211,10 @@ __global__ __launch_bounds__(256) void k_project_cull(SceneP P, const int32_t* _
     __shared__ uint32_t base_s;
     int64_t cnt = n_in;
     if (n_in_dev) cnt = min(cnt, *n_in_dev);
-    const int64_t j0 = int64_t(blockIdx.x) * kCullChunk;
+    const int64_t j0 = int64_t(blockIdx.x) * kChunk;
     const int w = threadIdx.x / 64;
     const int64_t N = P.n;
-    constexpr int kIt = kCullChunk / 256;
+    constexpr int kIt = kChunk / 256;
     uint32_t keep_bits = 0;  // per iteration: this thread's entry is a candidate
     uint32_t mine = 0;
 #pragma unroll
@@ -339,10 +348,9 @@ struct GradOut {
 
 // Entries visible in at least one camera, appended to `list` (order is
 // irrelevant: entries are distinct Gaussians, so their gradients are disjoint).
-// One workgroup handles kVisChunk entries: it counts them, reserves its slice
+// One workgroup handles kChunk entries: it counts them, reserves its slice
 // with a single atomic, then writes them (two reads of the radius values).
-constexpr int kVisChunk = 4096;
-
+template <int kChunk>
 __global__ __launch_bounds__(256) void k_visible_list(int64_t n_in, const int64_t* __restrict__ n_in_dev, BwdIn B,
                                                       int n_cams, uint32_t* __restrict__ list,
                                                       uint32_t* __restrict__ count) {
@@ -350,10 +358,10 @@ __global__ __launch_bounds__(256) void k_visible_list(int64_t n_in, const int64_
     __shared__ uint32_t base_s;
     int64_t cnt = n_in;
     if (n_in_dev) cnt = min(cnt, *n_in_dev);
-    const int64_t j0 = int64_t(blockIdx.x) * kVisChunk;
+    const int64_t j0 = int64_t(blockIdx.x) * kChunk;
     const int w = threadIdx.x / 64;
     uint32_t mine = 0;
-    for (int it = 0; it < kVisChunk / 256; ++it) {
+    for (int it = 0; it < kChunk / 256; ++it) {
         const int64_t j = j0 + it * 256 + threadIdx.x;
         bool vis = false;
         if (j < cnt)
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(256) void k_visible_list(int64_t n_in, const int64_
     __syncthreads();
     uint32_t off = base_s;
     for (int k = 0; k < w; ++k) off += wsum[k];
-    for (int it = 0; it < kVisChunk / 256; ++it) {
+    for (int it = 0; it < kChunk / 256; ++it) {
         const int64_t j = j0 + it * 256 + threadIdx.x;
         bool vis = false;
         if (j < cnt)
@@ -624,8 +632,13 @@ int launch_visible_list(int64_t n_in, const int64_t* n_in_dev, int n_cams, float
     int rc = fill_u32(count, 0u, 1, stream);
     if (rc) return rc;
     if (n_in == 0) return GS_OK;
-    launch("visible_list", k_visible_list, dim3(unsigned((n_in + kVisChunk - 1) / kVisChunk)), dim3(256), 0, stream,
-           n_in, n_in_dev, B, n_cams, list, count);
+    if (n_in <= kSmallListInput)
+        launch("visible_list", k_visible_list<kChunkSmall>, dim3(unsigned((n_in + kChunkSmall - 1) / kChunkSmall)),
+               dim3(256), 0, stream, n_in, n_in_dev, B, n_cams, list, count);
+    else
+        launch("visible_list", k_visible_list<kVisChunkLarge>,
+               dim3(unsigned((n_in + kVisChunkLarge - 1) / kVisChunkLarge)), dim3(256), 0, stream, n_in, n_in_dev, B,
+               n_cams, list, count);
     return check_launch("visible list");
 }
 
@@ -701,8 +714,13 @@ extern "C" int gs_project(const gs_scene* scene, const int32_t* active_idx, int6
     uint32_t* list = cv.take<uint32_t>(size_t(n_in));
     uint32_t* count = cv.take<uint32_t>(4);
     if ((rc = fill_u32(count, 0u, 1, stream))) return rc;
-    launch("project_cull", k_project_cull, dim3(unsigned((n_in + kCullChunk - 1) / kCullChunk)), dim3(256), 0, stream,
-           P, active_idx, n_in, n_in_dev, C, O, list, count);
+    if (n_in <= kSmallListInput)
+        launch("project_cull", k_project_cull<kChunkSmall>, dim3(unsigned((n_in + kChunkSmall - 1) / kChunkSmall)),
+               dim3(256), 0, stream, P, active_idx, n_in, n_in_dev, C, O, list, count);
+    else
+        launch("project_cull", k_project_cull<kCullChunkLarge>,
+               dim3(unsigned((n_in + kCullChunkLarge - 1) / kCullChunkLarge)), dim3(256), 0, stream, P, active_idx,
+               n_in, n_in_dev, C, O, list, count);
     launch("project", k_project, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx, n_in,
            static_cast<const uint32_t*>(list), static_cast<const uint32_t*>(count), C, O);
     return check_launch("gs_project");
