@@ -310,6 +310,47 @@ class Bench:
         return 10.0 * math.log10(1.0 / mse) if mse > 0 else float("inf")
 
 
+def hbm_fractions(ds, cam, n, capacity, dev, reps=5):
+    """Algorithmic HBM bytes per second of the ungated projection and of the
+    whole binning call (scan, emission, radix passes, ranges, per-tile sort)
+    on one view, timed with events on their stream, against 8 TB/s.  Bytes:
+    projection 12 N (means, read to cull) + 224 N_vis (the rest) + 49 N
+    (outputs); binning 8 N (scan) + 20 N_vis + 12 K (emission) + K (8 + 24 d)
+    (d = 8-bit passes over the 32 depth and the tile bits) + 8 K + 8 tiles
+    (ranges)."""
+    import torch
+
+    from paper_2605_13794_amd import gsmi as G
+    from paper_2605_13794_amd.raster import Frame
+    f = Frame([cam], n, dev, capacity=int(capacity * 1.2) + 4096)
+    f.project(ds.struct())
+    f.bin_sort(check=False)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_proj = t_sort = 0.0
+    for _ in range(reps):
+        e[0].record()
+        f.project(ds.struct())
+        e[1].record()
+        f.bin_sort(check=False)
+        e[2].record()
+        torch.cuda.synchronize()
+        t_proj += e[0].elapsed_time(e[1]) / reps
+        t_sort += e[1].elapsed_time(e[2]) / reps
+    n_vis = int((f.proj[0].radius[:n] > 0).sum().item())
+    K = int(f.n_pairs.item())
+    tiles = f.total_tiles
+    d = (32 + max(1, (tiles - 1).bit_length()) + 7) // 8
+    b_proj = 12 * n + 224 * n_vis + 49 * n
+    b_sort = 8 * n + 20 * n_vis + 12 * K + K * (8 + 24 * d) + 8 * K + 8 * tiles
+    res = {}
+    for name, b, t in (("project", b_proj, t_proj), ("bin_sort", b_sort, t_sort)):
+        gbs = b / (t * 1e-3) / 1e9
+        res[name] = {"ms": t, "bytes": b, "GB_per_s": gbs, "frac": gbs / PEAK_HBM_GBS}
+    res["n"], res["n_visible"], res["pairs"] = n, n_vis, K
+    return res
+
+
 def run_cfg3(args):
     """8M city: importance over 64 orbit views, score mask (drop 40%), then per
     view the 0.5 px radius gate; gated vs ungated forward and forward+backward
@@ -446,9 +487,11 @@ def run_cfg3(args):
                               "active_fraction": int(n_act.item()) / n, "fwd_bwd_ms": ms,
                               "speedup": plain_ms[v] / ms,
                               "psnr_db": 10 * math.log10(1 / mse) if mse > 0 else float("inf")})
+    hbm = hbm_fractions(ds, cams[0], n, Kmax, dev)
     out = {"metric": METRIC, "config": {"workload": f"aerial city {n} Gaussians, 64 orbit views 1080p: importance "
                                                     f"sweep, drop 40% by score, 0.5 px radius gate"},
            "importance_ms_per_view": sweep_ms, "pairs_max": Kmax, "drop_radius_sweep": sweep,
+           "hbm_fraction": hbm,
            "active_fraction": {"mean": float(np.mean(fracs)), "min": float(np.min(fracs)),
                                "max": float(np.max(fracs))},
            "views": rows,
