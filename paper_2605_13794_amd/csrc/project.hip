@@ -269,8 +269,6 @@ __global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __rest
     float s[3], qn[4], R[9], M[9], S[6], qlen;
     covariance(ls, q, s, qn, R, M, S, qlen);
     const float opa = 1.f / (1.f + __expf(-P.opacity_logit[i]));
-    bool have_sh = false;
-    float sh[48];
     for (int c = 0; c < C.n; ++c) {
         const DevCam& K = C.cam[c];
         Geo G;
@@ -293,25 +291,26 @@ __global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __rest
         const int64_t y1 = min<int64_t>(max<int64_t>(floordiv16(yi + r) + 1, 0), K.TY);
         const int64_t touched = (x1 - x0) * (y1 - y0);
         if (touched <= 0 || !(rf > 0.f)) { culled_out(O, c, j, n_in); continue; }
-        if (!have_sh) {
-#pragma unroll
-            for (int k = 0; k < 48; ++k) sh[k] = P.sh[int64_t(k) * N + i];
-            have_sh = true;
-        }
         float vx = mu[0] - K.campos[0], vy = mu[1] - K.campos[1], vz = mu[2] - K.campos[2];
         const float il = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
         float Y[16];
         sh_basis(vx * il, vy * il, vz * il, Y);
+        // the 48 coefficients are read four degrees at a time (12 loads in
+        // flight) rather than all at once: fewer registers, more wavefronts
+        float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) acc[ch] = fmaf(P.sh[int64_t(k * 3 + ch) * N + i], Y[k], acc[ch]);
+            if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
         float rgb[3];
         uint8_t cbits = 0;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            float acc = 0.f;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) acc = fmaf(sh[k * 3 + ch], Y[k], acc);
-            acc += 0.5f;
-            if (acc < 0.f) { cbits |= uint8_t(1u << ch); acc = 0.f; }
-            rgb[ch] = acc;
+            float a = acc[ch] + 0.5f;
+            if (a < 0.f) { cbits |= uint8_t(1u << ch); a = 0.f; }
+            rgb[ch] = a;
         }
         float4* rp = reinterpret_cast<float4*>(O.rec[c] + j * kRec);
         rp[0] = make_float4(mx, my, ca, cb);
