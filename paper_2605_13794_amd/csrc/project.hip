@@ -295,8 +295,8 @@ __global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __rest
         const float il = 1.f / sqrtf(vx * vx + vy * vy + vz * vz);
         float Y[16];
         sh_basis(vx * il, vy * il, vz * il, Y);
-        // the 48 coefficients are read four degrees at a time (12 loads in
-        // flight) rather than all at once: fewer registers, more wavefronts
+        // the 48 coefficients are read four SH functions (12 loads) at a time
+        // rather than all at once: fewer registers, more wavefronts
         float acc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
