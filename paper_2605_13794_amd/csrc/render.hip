@@ -127,8 +127,10 @@ struct FwdOut {
 // Slot of pixel (lane, row r) inside a tile's 256-float block of the chain.
 __device__ __forceinline__ uint32_t chain_slot(int lane, int r) { return uint32_t(lane + 64 * r); }
 
+// Eight wavefronts per SIMD (at most 64 VGPRs, no spills): 101.6 -> 94.6 us
+// on the 1M city view against the seven the compiler picks by itself.
 template <bool kChain>
-__global__ __launch_bounds__(64) void k_render_fwd(RenderCams A, const uint32_t* __restrict__ vals,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_render_fwd(RenderCams A, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges, uint32_t n_tiles, FwdOut O) {
     __shared__ float4 sA[64];
     __shared__ float4 sB[64];
