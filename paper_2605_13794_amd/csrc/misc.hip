@@ -85,7 +85,29 @@ __global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ rg
     __shared__ double red[256];
     const float inv = 1.0f / float(n);
     double acc = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    int64_t done = 0;
+    if (((reinterpret_cast<uintptr_t>(rgb) | reinterpret_cast<uintptr_t>(target) |
+          reinterpret_cast<uintptr_t>(grad)) & 15) == 0) {
+        // four values per thread and load
+        const int64_t n4 = n / 4;
+        for (int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x; q < n4; q += stride) {
+            const float4 a = reinterpret_cast<const float4*>(rgb)[q];
+            const float4 b = reinterpret_cast<const float4*>(target)[q];
+            const float d[4] = {a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w};
+            float g[4];
+            float part = 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                part += fabsf(d[e]);
+                g[e] = (d[e] > 0.f ? 1.f : (d[e] < 0.f ? -1.f : 0.f)) * inv;
+            }
+            acc += double(part);
+            reinterpret_cast<float4*>(grad)[q] = make_float4(g[0], g[1], g[2], g[3]);
+        }
+        done = n4 * 4;
+    }
+    for (int64_t i = done + int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
         float d = rgb[i] - target[i];
         acc += double(fabsf(d));
         float s = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
