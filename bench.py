@@ -307,7 +307,26 @@ class Bench:
         self.fr.forward(scn, self.active, self.n, self.n_act, check=False)
         torch.cuda.synchronize()
         mse = float(((self.fr.rgb[0] - self.fr_all.rgb[0]) ** 2).mean().item())
-        return 10.0 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+        return psnr_db(mse)
+
+
+def psnr_db(mse):
+    """PSNR in dB of an image pair with mean squared error `mse` on [0, 1]
+    colours; None for identical images (infinite PSNR, which strict JSON
+    cannot carry)."""
+    return 10.0 * math.log10(1.0 / mse) if mse > 0 else None
+
+
+def finite(x):
+    """`x` with every non-finite float replaced by None, so that the printed
+    line is strict JSON."""
+    if isinstance(x, dict):
+        return {k: finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [finite(v) for v in x]
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    return x
 
 
 def hbm_fractions(ds, cam, n, capacity, dev, reps=5):
@@ -439,7 +458,7 @@ def run_cfg3(args):
                      "plain_fwd_ms": res[("plain", "fwd_ms")], "gated_fwd_ms": res[("gated", "fwd_ms")],
                      "plain_fwd_bwd_ms": res[("plain", "fwd_bwd_ms")],
                      "gated_fwd_bwd_ms": res[("gated", "fwd_bwd_ms")],
-                     "psnr_db": 10 * math.log10(1 / mse) if mse > 0 else float("inf")})
+                     "psnr_db": psnr_db(mse)})
     # speed at equal image error: drop share x radius threshold on two views
     sweep = []
     ws_keep = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_SCORE_KEEP, n))
@@ -486,7 +505,7 @@ def run_cfg3(args):
                 sweep.append({"drop": drop, "radius_min_px": rmin, "view": v,
                               "active_fraction": int(n_act.item()) / n, "fwd_bwd_ms": ms,
                               "speedup": plain_ms[v] / ms,
-                              "psnr_db": 10 * math.log10(1 / mse) if mse > 0 else float("inf")})
+                              "psnr_db": psnr_db(mse)})
     hbm = hbm_fractions(ds, cams[0], n, Kmax, dev)
     out = {"metric": METRIC, "config": {"workload": f"aerial city {n} Gaussians, 64 orbit views 1080p: importance "
                                                     f"sweep, drop 40% by score, 0.5 px radius gate"},
@@ -496,7 +515,7 @@ def run_cfg3(args):
                                "max": float(np.max(fracs))},
            "views": rows,
            "speedup_fwd_bwd": float(np.mean([r["plain_fwd_bwd_ms"] / r["gated_fwd_bwd_ms"] for r in rows]))}
-    print(json.dumps(out), flush=True)
+    print(json.dumps(finite(out), allow_nan=False), flush=True)
 
 
 def run_cfg4(args):
@@ -541,7 +560,7 @@ def run_cfg4(args):
                                   f"RasterizeFn + L1 + Adam"},
            "peak_allocated_gib": torch.cuda.max_memory_allocated() / 2**30,
            "backward": "transmittance recomputed from the final T (no stored chain)"}
-    print(json.dumps(out), flush=True)
+    print(json.dumps(finite(out), allow_nan=False), flush=True)
 
 
 def cpu_baseline(scene, cam, min_seconds=10.0):
@@ -755,7 +774,7 @@ def main():
         from paper_2605_13794_amd import scenes as S
         out["cpu_baseline"] = cpu_baseline(layout(S.city_scene(args.n, seed=2), args),
                                            S.aerial_camera(args.width, args.height))
-    print(json.dumps(out), flush=True)
+    print(json.dumps(finite(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
