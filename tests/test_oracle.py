@@ -195,10 +195,12 @@ def test_golden_single_gaussian(oracle):
 @pytest.mark.parametrize("w,h", [(48, 40), (33, 17), (16, 16)])
 def test_binning_matches_python_sorted(oracle, w, h):
     cam = S.cube_camera(w, h, float(w))
-    _, _, pr = oracle.project(_tiny_scene(60, seed=w + h), cam)
+    _, out, pr = oracle.project(_tiny_scene(60, seed=w + h), cam)
     K, keys, vals, ranges = oracle.bin_sort(pr, w, h)
     emitted, ordered = BF.pairs(pr, w, h)
     assert K == len(emitted)
+    # the projection's per-Gaussian tile counts agree with the emitted pairs
+    assert int(out["tiles_touched"].sum()) == K
     assert keys.tolist() == [k for k, _ in ordered]
     assert vals.tolist() == [v for _, v in ordered]
     nt = oracle.n_tiles(w, h)
@@ -271,6 +273,32 @@ def test_partition_of_unity(oracle):
     assert (f["stop"] < np.diff(ranges, axis=0).max() + 1).all()
 
 
+def test_opaque_stack_stops_at_transmittance_floor(oracle):
+    """Five wide, nearly opaque Gaussians on the optical axis at distinct
+    depths: alpha clamps to 0.99 at the centre pixel, so T falls 1 -> 0.01 ->
+    1e-4 and the third would take it to 1e-6 < 1e-4, so the pixel stops before
+    compositing it: C = 0.99 c_0 + 0.99 * 0.01 c_1 + T bg, T_final = 0.01^2."""
+    cam = S.cube_camera(128, 128, 128.0)
+    n = 5
+    dcs = [(1.0, 0.0, -1.0), (-1.0, 1.0, 0.0), (0.0, -1.0, 1.0), (0.5, 0.5, 0.5), (-0.5, 0.0, 0.5)]
+    sh = np.zeros((16, 3, n))
+    for i, dc in enumerate(dcs):
+        sh[0, :, i] = dc
+    p = dict(mean=np.stack([np.zeros(n), np.zeros(n), 0.2 * np.arange(n)]), log_scale=np.full((3, n), math.log(0.8)),
+             quat=np.tile(np.array([[1.0], [0.0], [0.0], [0.0]]), (1, n)), opacity_logit=np.full(n, 10.0), sh=sh)
+    bg = (0.2, 0.4, 0.6)
+    r = oracle.forward_backward(p, cam, bg=bg)
+    pr = r["projected"]
+    g = pr.opacity * np.exp(-0.5 * (pr.conic[0] * 0.25 + pr.conic[2] * 0.25) - pr.conic[1] * 0.25)
+    assert (g > 0.99).all()                      # every alpha at pixel (64, 64) clamps
+    a = 0.99
+    T1 = 1.0 * (1.0 - a)
+    T2 = T1 * (1.0 - a)
+    assert r["T"][64, 64] == pytest.approx(T2, rel=1e-12)
+    expect = a * pr.rgb[:, 0] + a * T1 * pr.rgb[:, 1] + T2 * np.array(bg)
+    np.testing.assert_allclose(r["rgb"][:, 64, 64], expect, rtol=1e-12)
+
+
 def test_matches_bruteforce_depth_order(oracle):
     """Tile lists + sorted keys give the same image as sorting every pixel's
     candidates by depth with Python's sorted()."""
@@ -318,20 +346,46 @@ def test_integral_of_wide_gaussian(oracle):
 # --------------------------------------------------------------------------
 # Gradients (central finite differences of the float64 pipeline)
 # --------------------------------------------------------------------------
-def _signature(oracle, p, cam, target):
-    r = oracle.forward_backward(p, cam)
+def _clamped_evaluations(pr, w, h):
+    """(Gaussian, pixel) pairs inside the Gaussian's tile rectangle where
+    o G exceeds 0.99 (alpha clamped), counted by brute force."""
+    u = np.arange(w) + 0.5
+    v = np.arange(h) + 0.5
+    count = 0
+    for i in np.nonzero(pr.radius > 0)[0]:
+        x0, x1, y0, y1 = BF.rect(pr.mean2d[0, i], pr.mean2d[1, i], int(pr.radius[i]), w, h)
+        dx = pr.mean2d[0, i] - u[None, 16 * x0:16 * x1]
+        dy = pr.mean2d[1, i] - v[16 * y0:16 * y1, None]
+        a, b, c = pr.conic[:, i]
+        power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+        count += int((pr.opacity[i] * np.exp(np.minimum(power, 0.0)) > 0.99).sum())
+    return count
+
+
+def _signature(oracle, p, cam, target, bg):
+    r = oracle.forward_backward(p, cam, bg=bg)
     sig = (r["sig"].tobytes(), r["projected"].radius.tobytes(),
            r["out"]["rect"].numpy().tobytes(), r["out"]["clamp_bits"].numpy().tobytes())
     return oracle.l1_loss(r["rgb"], target)[0], sig
 
 
-def test_gradients_match_finite_differences(oracle):
+@pytest.mark.parametrize("bg,logit_shift,log_mu", [((0.0, 0.0, 0.0), 0.0, -1.8), ((0.3, 0.6, 0.9), 0.0, -1.8),
+                                                    ((0.3, 0.6, 0.9), 7.0, -0.6)])
+def test_gradients_match_finite_differences(oracle, bg, logit_shift, log_mu):
+    """Every parameter group against central differences of the loss, on a
+    black and on a coloured background (the background enters dC/dalpha), and
+    with opacities high enough that alpha = min(0.99, o G) clamps on many
+    pixels (zero derivative there)."""
     w, h = 32, 32
     cam = S.cube_camera(w, h, 32.0)
-    sc = S.cube_scene(24, seed=4, log_scale_mu=-1.8, log_scale_sigma=0.3)
+    sc = S.cube_scene(24, seed=4, log_scale_mu=log_mu, log_scale_sigma=0.3)
     p = {k: v.astype(np.float64) for k, v in sc.arrays().items() if k != "lod"}
+    p["opacity_logit"] = p["opacity_logit"] + logit_shift
     target = S.target_image(w, h, seed=4)
-    r = oracle.forward_backward(p, cam, target=target)
+    r = oracle.forward_backward(p, cam, target=target, bg=bg)
+    if logit_shift > 0:
+        pr = r["projected"]
+        assert _clamped_evaluations(pr, w, h) > 20
     grads = r["grads"]
     vis = np.nonzero(r["projected"].radius > 0)[0]
     rng = np.random.default_rng(1)
@@ -347,8 +401,8 @@ def test_gradients_match_finite_differences(oracle):
             pm = {k: v.copy() for k, v in p.items()}
             pp[name][idx] = x + hstep
             pm[name][idx] = x - hstep
-            lp, sp = _signature(oracle, pp, cam, target)
-            lm, sm = _signature(oracle, pm, cam, target)
+            lp, sp = _signature(oracle, pp, cam, target, bg)
+            lm, sm = _signature(oracle, pm, cam, target, bg)
             if sp != sm:
                 continue
             fd = (lp - lm) / (2 * hstep)

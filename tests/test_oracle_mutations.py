@@ -1,0 +1,142 @@
+"""The CPU reference's pins catch plausible mistakes.
+
+Each case plants one mistake in the CPU reference (a dropped term, a flipped
+sign, a transposed operand, an off-by-one, a missing clamp rule) — in a
+patched Python helper or in a recompiled copy of the C compositing code, on
+the CPU only — and checks that at least one of the pins in `test_oracle.py`
+then fails.  Nothing here touches the HIP library.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+from tests import test_oracle as P
+
+
+def _mutant_lib(oracle, tmp_path, replacements):
+    """Compile a copy of the reference's C code with `replacements`
+    (old, new, expected count) applied; returns the path of the library."""
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "raster.c")).read()
+    for old, new, count in replacements:
+        assert src.count(old) >= count, old
+        src = src.replace(old, new, count)
+    c = tmp_path / "raster_mutant.c"
+    c.write_text(src)
+    so = tmp_path / "raster_mutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+                           str(c), "-o", str(so), "-lm"])
+    return str(so)
+
+
+@pytest.fixture
+def with_c_mutation(oracle, tmp_path, monkeypatch):
+    def apply(replacements):
+        path = _mutant_lib(oracle, tmp_path, replacements)
+        monkeypatch.setattr(oracle, "_LIB_PATH", path)
+        monkeypatch.setattr(oracle, "_lib", None)
+    return apply
+
+
+def _fails(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+# -- compositing (C) ---------------------------------------------------------
+FWD_POWER = "const double power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy;"
+
+
+def test_flipped_cross_term_in_forward_power_is_caught(oracle, with_c_mutation):
+    # the first occurrence of the exponent is the forward's
+    with_c_mutation([(FWD_POWER, FWD_POWER.replace("- b * dx", "+ b * dx"), 1)])
+    _fails(P.test_single_gaussian_closed_form, oracle)
+
+
+def test_dropped_background_term_in_backward_is_caught(oracle, with_c_mutation):
+    with_c_mutation([("(suffix[c3] + Tfin * bg[c3])", "(suffix[c3])", 1)])
+    P.test_gradients_match_finite_differences(oracle, (0.0, 0.0, 0.0), 0.0, -1.8)  # black: invisible
+    _fails(P.test_gradients_match_finite_differences, oracle, (0.3, 0.6, 0.9), 0.0, -1.8)
+
+
+def test_derivative_through_the_opacity_clamp_is_caught(oracle, with_c_mutation):
+    with_c_mutation([("if (e->g > ALPHA_MAX) continue;", "", 1)])
+    _fails(P.test_gradients_match_finite_differences, oracle, (0.3, 0.6, 0.9), 7.0, -0.6)
+
+
+def test_back_to_front_order_is_caught(oracle, with_c_mutation):
+    # sort keys descending: every tile list (and its depth order) reversed
+    with_c_mutation([("return a->key < b->key ? -1 : 1;", "return a->key < b->key ? 1 : -1;", 1)])
+    _fails(P.test_matches_bruteforce_depth_order, oracle)
+
+
+def test_wrong_stop_level_is_caught(oracle, with_c_mutation):
+    # a lower stop level lets the pixel composite one more Gaussian
+    with_c_mutation([("#define T_MIN 1e-4", "#define T_MIN 1e-6", 1)])
+    _fails(P.test_opaque_stack_stops_at_transmittance_floor, oracle)
+
+
+def test_emitted_rectangle_off_by_one_is_caught(oracle, with_c_mutation):
+    tx1 = "*tx1 = clampi(floordiv(xi + r, TILE) + 1, 0, TX);"
+    with_c_mutation([(tx1, tx1.replace(" + 1,", ","), 1)])
+    _fails(P.test_binning_covers_radius_box, oracle)
+
+
+# -- projection (Python) -----------------------------------------------------
+def test_missing_screen_space_dilation_is_caught(oracle, monkeypatch):
+    monkeypatch.setattr(oracle._proj, "DILATION", 0.0)
+    _fails(P.test_isotropic_on_axis_closed_form, oracle, 1.0, 0.1)
+
+
+def test_transposed_rotation_is_caught(oracle, monkeypatch):
+    orig = oracle._proj.quat_to_rotmat
+    monkeypatch.setattr(oracle._proj, "quat_to_rotmat", lambda q: orig(q).transpose(1, 2))
+    _fails(P.test_screen_covariance_matches_numeric_jacobian, oracle)
+
+
+def test_sh_sign_flip_is_caught(oracle, monkeypatch):
+    orig = oracle.sh_basis
+
+    def flipped(d, *a, **k):
+        Y = orig(d, *a, **k).clone()
+        Y[:, 1] = -Y[:, 1]
+        return Y
+    monkeypatch.setattr(oracle, "sh_basis", flipped)
+    _fails(P.test_sh_matches_scipy_complex_harmonics, oracle)
+
+
+def test_tile_count_off_by_one_is_caught(oracle, monkeypatch):
+    orig = oracle._proj.tile_rect
+
+    def short(*a):
+        tx0, tx1, ty0, ty1 = orig(*a)
+        return tx0, torch.maximum(tx0, tx1 - 1), ty0, ty1
+    monkeypatch.setattr(oracle._proj, "tile_rect", short)
+    _fails(P.test_binning_matches_python_sorted, oracle, 48, 40)
+
+
+# -- importance, optimizer ---------------------------------------------------
+def test_top_mass_without_the_crossing_weight_is_caught(oracle, monkeypatch):
+    orig = oracle.top_mass
+
+    def exclusive(w, frac=0.99):
+        sel = orig(w, frac)
+        if sel.any():
+            w = np.asarray(w)
+            smallest = np.flatnonzero(sel)[np.argmin(w[sel])]
+            sel = sel.copy()
+            sel[smallest] = False
+        return sel
+    monkeypatch.setattr(oracle, "top_mass", exclusive)
+    _fails(P.test_top_mass_hand_cases, oracle)
+
+
+def test_adam_without_bias_correction_is_caught(oracle, monkeypatch):
+    orig = oracle.adam_step
+    monkeypatch.setattr(oracle, "adam_step",
+                        lambda p, g, m, v, lr, step, **k: orig(p, g, m, v, lr, 10 ** 9, **k))
+    _fails(P.test_adam_first_step_and_torch, oracle)
