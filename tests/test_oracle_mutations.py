@@ -8,6 +8,7 @@ then fails.  Nothing here touches the HIP library.
 """
 from __future__ import annotations
 
+import math
 import os
 import subprocess
 
@@ -80,6 +81,24 @@ def test_wrong_stop_level_is_caught(oracle, with_c_mutation):
     _fails(P.test_opaque_stack_stops_at_transmittance_floor, oracle)
 
 
+def test_flipped_mean_gradient_in_backward_is_caught(oracle, with_c_mutation):
+    line = "d_mean2d[j] += dl_dpower * (-(a * e->dx + b * e->dy));"
+    with_c_mutation([(line, line.replace("(-(a", "((a"), 1)])
+    _fails(P.test_gradients_match_finite_differences, oracle, (0.0, 0.0, 0.0), 0.0, -1.8)
+
+
+def test_halved_cross_term_of_conic_gradient_is_caught(oracle, with_c_mutation):
+    line = "d_conic[n + j] += dl_dpower * (-e->dx * e->dy);"
+    with_c_mutation([(line, line.replace("(-e->dx", "(-0.5 * e->dx"), 1)])
+    _fails(P.test_gradients_match_finite_differences, oracle, (0.0, 0.0, 0.0), 0.0, -1.8)
+
+
+def test_importance_weight_without_transmittance_is_caught(oracle, with_c_mutation):
+    with_c_mutation([("w[j] += alpha * T;", "w[j] += alpha;", 1)])
+    _fails(P.test_importance_sum_identity, oracle)
+    _fails(P.test_matches_bruteforce_depth_order, oracle)
+
+
 def test_emitted_rectangle_off_by_one_is_caught(oracle, with_c_mutation):
     tx1 = "*tx1 = clampi(floordiv(xi + r, TILE) + 1, 0, TX);"
     with_c_mutation([(tx1, tx1.replace(" + 1,", ","), 1)])
@@ -133,6 +152,20 @@ def test_top_mass_without_the_crossing_weight_is_caught(oracle, monkeypatch):
         return sel
     monkeypatch.setattr(oracle, "top_mass", exclusive)
     _fails(P.test_top_mass_hand_cases, oracle)
+
+
+def test_score_without_eps_is_caught(oracle, monkeypatch):
+    orig = oracle.importance_fold
+    monkeypatch.setattr(oracle, "importance_fold",
+                        lambda st, view, w, a, radius, frac=0.99, eps=1e-6: orig(st, view, w, a, radius, frac, 0.0))
+    _fails(P.test_importance_fold_and_phi, oracle)
+
+
+def test_level_gate_in_the_wrong_log_base_is_caught(oracle, monkeypatch):
+    orig = oracle.lod_gate_level
+    monkeypatch.setattr(oracle, "lod_gate_level",
+                        lambda mean, lod, cam_pos, d0, l_max, f=2.0: orig(mean, lod, cam_pos, d0, l_max, math.e))
+    _fails(P.test_lod_level_equation_values, oracle)
 
 
 def test_adam_without_bias_correction_is_caught(oracle, monkeypatch):
