@@ -425,22 +425,45 @@ def test_l1_loss_matches_reference(oracle):
         torch.cuda.synchronize()
         assert abs(loss.item() - L) <= 1e-6 * max(L, 1)
         np.testing.assert_allclose(to_np(grad), g, rtol=1e-6, atol=0)
+        # the same values at addresses one float past a 16-byte boundary
+        # (the kernel's one-value-per-load path)
+        n = at.numel()
+        ab = torch.empty(n + 1, device=dev)
+        bb = torch.empty(n + 1, device=dev)
+        gb = torch.full((n + 2,), 7.0, device=dev)
+        ab[1:] = at.reshape(-1)
+        bb[1:] = bt.reshape(-1)
+        loss.zero_()
+        G.gs_l1_loss(ab[1:], bb[1:], n, loss, gb[1:n + 1], ws)
+        torch.cuda.synchronize()
+        assert abs(loss.item() - L) <= 1e-6 * max(L, 1)
+        gh = to_np(gb)
+        np.testing.assert_allclose(gh[1:n + 1].reshape(shape), g, rtol=1e-6, atol=0)
+        assert gh[0] == 7.0 and gh[n + 1] == 7.0          # nothing written outside
 
 
 def test_adam_matches_reference(oracle):
     dev = device()
     G = gsmi()
     rng = np.random.default_rng(1)
-    sizes = [12288, 4096, 7, 1 << 16]
-    lrs = [1e-3, 2e-2, 5e-2, 3e-4]
+    sizes = [12288, 4096, 7, 1 << 16, 1001]
+    lrs = [1e-3, 2e-2, 5e-2, 3e-4, 1e-2]
+    # the last group sits one float past a 16-byte boundary (the kernel's
+    # one-value-per-load path)
+    offs = [0, 0, 0, 0, 1]
+
+    def on_dev(x, off):
+        buf = torch.zeros(x.size + off, device=dev)
+        buf[off:] = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+        return buf[off:]
     p0 = [rng.standard_normal(n).astype(np.float32) for n in sizes]
-    ps = [torch.from_numpy(x.copy()).to(dev) for x in p0]
-    ms = [torch.zeros_like(x) for x in ps]
-    vs = [torch.zeros_like(x) for x in ps]
+    ps = [on_dev(x, o) for x, o in zip(p0, offs)]
+    ms = [on_dev(np.zeros(n), o) for n, o in zip(sizes, offs)]
+    vs = [on_dev(np.zeros(n), o) for n, o in zip(sizes, offs)]
     ref = [(x.astype(np.float64), np.zeros(n), np.zeros(n)) for x, n in zip(p0, sizes)]
     for step in range(1, 5):
         gs = [rng.standard_normal(n).astype(np.float32) for n in sizes]
-        G.gs_adam_step(ps, [torch.from_numpy(g).to(dev) for g in gs], ms, vs, lrs, 0.9, 0.999, 1e-15, step)
+        G.gs_adam_step(ps, [on_dev(g, o) for g, o in zip(gs, offs)], ms, vs, lrs, 0.9, 0.999, 1e-15, step)
         ref = [oracle.adam_step(p, g, m, v, lr, step) for (p, m, v), g, lr in zip(ref, gs, lrs)]
     torch.cuda.synchronize()
     for t, (p, _, _) in zip(ps, ref):
