@@ -181,8 +181,12 @@ __global__ __launch_bounds__(256) void k_adam(AdamGroups G, float b1, float b2, 
     const int64_t stride = int64_t(gridDim.x) * 256;
     int64_t done = 0;
     if (vec) {
+        // each workgroup streams one contiguous chunk of whole 256-float4 rows
         const int64_t n4 = cnt / 4;
-        for (int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x; q < n4; q += stride) {
+        const int64_t chunk = ((n4 + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+        const int64_t q0 = int64_t(blockIdx.x) * chunk;
+        const int64_t q1 = min(q0 + chunk, n4);
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
             // streamed once per step: non-temporal loads and stores keep the
             // 2 GB pass from evicting the caches the other kernels use
             typedef float f4 __attribute__((ext_vector_type(4)));
@@ -312,11 +316,11 @@ extern "C" int gs_adam_step(float* const* params, float* const* grads, float* co
     if (total == 0) return GS_OK;
     int64_t maxc = 0;
     for (int k = 0; k < n_groups; ++k) maxc = std::max<int64_t>(maxc, counts[k]);
-    // grid-stride over float4s; caps measured on the 1M-Gaussian step (62M
-    // floats): 512 -> 331 us, 1,024 -> 382, 1,536 -> 350, 2,048 -> 330,
-    // 4,096 -> 344, 16,384 -> 394
+    // contiguous float4 chunks per workgroup; caps measured on the 1M-Gaussian
+    // step (62M floats): 1,024 -> 380 us, 2,048 -> 324, 4,096 -> 318,
+    // 6,144 -> 312, 8,192 -> 329 (a grid-stride loop was best at 2,048: 330)
     int64_t blocks = (maxc / 4 + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 6144) blocks = 6144;
     if (blocks < 1) blocks = 1;
     launch("adam", k_adam, dim3(unsigned(blocks), unsigned(n_groups)), dim3(256), 0, stream, G, b1, b2, eps,
            float(1.0 / bc1),
