@@ -189,6 +189,41 @@ def test_golden_single_gaussian(oracle):
     assert r["rgb"][:, 64, 100] == pytest.approx(g["pixel_64_100"], rel=1e-10)
 
 
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    g = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, v = line.split("=")
+            g[k.strip()] = [float(x) for x in v.split()]
+    return g
+
+
+def test_golden_tile_rect_edge(oracle):
+    """Hand-derived support-rule case, tests/golden/tile_rect_edge.txt: the
+    pixel just across the edge of the Gaussian's tile rectangle keeps the
+    background although its alpha passes 1/255."""
+    g = _golden("tile_rect_edge.txt")
+    cam = S.camera_from_rt(128, 128, 128.0, 128.0, np.eye(3), np.array([0.0, 0.0, 4.0]), cx=70.5, cy=64.0)
+    p = _one_gaussian((0.0, 0.0, 0.0), [math.log(0.25)] * 3, logit=math.log(9.0))
+    p["sh"] = np.zeros((16, 3, 1), dtype=np.float64)
+    p["sh"][0, :, 0] = (0.8, 0.2, -0.3)
+    r = oracle.forward_backward(p, cam)
+    pr = r["projected"]
+    assert pr.mean2d[:, 0] == pytest.approx([70.5, 64.0], abs=1e-12)
+    assert int(pr.radius[0]) == int(g["radius"][0])
+    assert r["K"] == int(g["pairs"][0])
+    assert pr.rgb[:, 0] == pytest.approx(g["rgb"], rel=1e-12)
+    assert r["rgb"][:, 64, 95] == pytest.approx(g["pixel_64_95"], rel=1e-9)
+    assert r["T"][64, 95] == pytest.approx(g["T_64_95"][0], rel=1e-12)
+    assert g["alpha_64_96"][0] > 1.0 / 255.0
+    assert r["rgb"][:, 64, 96].tolist() == g["pixel_64_96"]
+    assert r["T"][64, 96] == g["T_64_96"][0]
+    assert int(r["last"][64, 96]) == 0
+
+
 # --------------------------------------------------------------------------
 # Binning
 # --------------------------------------------------------------------------
@@ -481,6 +516,27 @@ def test_lod_level_equation_values(oracle):
                         (3, [0, 0, 0, 0, 0, 0])]:
         keep = oracle.lod_gate_level(mean, np.full(6, lvl), np.zeros(3), d0=100.0, l_max=2)
         assert keep.astype(int).tolist() == expect
+
+
+def test_lod_radius_gate_boundary_values(oracle):
+    """Radius gate r = k fx max_j s_j / d at hand-chosen values: fx = 50 and
+    s = 1 (log-scale 0) at d = 100 (a 60-80-0 offset) give r = 0.5 px
+    exactly, kept; d one part in 1e9 farther gives r below 0.5, dropped; the
+    largest of the three axes decides (the third axis here); k = 3 triples
+    r; a Gaussian at the camera centre has infinite r and is kept."""
+    cam_pos = np.array([10.0, -20.0, 5.0])
+    off = np.array([[60.0, 80.0, 0.0], [60.0 * (1 + 1e-9), 80.0 * (1 + 1e-9), 0.0], [0.0, 0.0, 100.0],
+                    [0.0, 0.0, 0.0], [0.0, 0.0, 300.0], [0.0, 0.0, 301.0]])
+    mean = (cam_pos[None, :] + off).T
+    log_scale = np.array([[0.0, -1.0, -2.0], [0.0, 0.0, 0.0], [-3.0, -2.0, 0.0], [-5.0, -5.0, -5.0],
+                          [0.0, -1.0, -1.0], [0.0, -1.0, -1.0]]).T
+    keep, r = oracle.lod_gate_radius(mean, log_scale, cam_pos, fx=50.0, r_min=0.5)
+    assert r[0] == 0.5 and r[2] == 0.5
+    assert r[1] < 0.5
+    assert keep.tolist() == [True, False, True, True, False, False]
+    keep3, r3 = oracle.lod_gate_radius(mean, log_scale, cam_pos, fx=50.0, r_min=0.5, k_sigma=3.0)
+    assert r3[4] == 0.5 and r3[5] < 0.5
+    assert keep3.tolist() == [True, True, True, True, True, False]
 
 
 def test_gates_bruteforce_and_compaction(oracle):
