@@ -320,11 +320,14 @@ int gs_compact(const void* const* src, void* const* dst, const int32_t* rows, co
 
 /*
  * L1 photometric term (Eq. 4 with lambda = 0): *loss_dev = mean |C - target|
- * over n_vals values, grad = sign(C - target) / n_vals (sign(0) = 0).
- * Deterministic two-stage reduction.  Workspace: GS_OP_L1_LOSS.
+ * over n_vals values, grad = s * sign(C - target) / n_vals (sign(0) = 0)
+ * with s = *grad_scale (a device float, e.g. the upstream derivative of an
+ * autograd graph) or 1 when grad_scale is NULL.  Either output may be NULL
+ * (not computed), not both.  Deterministic two-stage reduction.  Workspace:
+ * GS_OP_L1_LOSS (only used when loss_dev is non-NULL).
  */
 int gs_l1_loss(const float* rgb, const float* target, int64_t n_vals, float* loss_dev,
-               float* grad, void* ws, size_t ws_bytes, hipStream_t stream);
+               float* grad, const float* grad_scale, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Photometric term of the paper's objective (Sec. 3.4, Eq. 4) for one view:

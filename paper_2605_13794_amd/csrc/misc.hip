@@ -75,15 +75,21 @@ int fill_u32(void* dst, uint32_t value, size_t count, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // L1 loss: per-block partial sums in double, then one block sums them in a
-// fixed order (deterministic).
+// fixed order (deterministic).  Either output may be skipped: `part` NULL
+// (no loss) or `grad` NULL (no gradient); the gradient is multiplied by
+// *scale when `scale` is non-NULL (the upstream derivative of an autograd
+// graph, read on the device).
 // ---------------------------------------------------------------------------
 constexpr int kL1Blocks = 1024;
 
+__device__ __forceinline__ float l1_sign(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
+
 __global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ rgb,
                                                     const float* __restrict__ target, int64_t n,
-                                                    float* __restrict__ grad, double* __restrict__ part) {
+                                                    float* __restrict__ grad, const float* __restrict__ scale,
+                                                    double* __restrict__ part) {
     __shared__ double red[256];
-    const float inv = 1.0f / float(n);
+    const float inv = (scale ? *scale : 1.0f) / float(n);
     double acc = 0.0;
     const int64_t stride = int64_t(gridDim.x) * 256;
     int64_t done = 0;
@@ -95,24 +101,19 @@ __global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ rg
             const float4 a = reinterpret_cast<const float4*>(rgb)[q];
             const float4 b = reinterpret_cast<const float4*>(target)[q];
             const float d[4] = {a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w};
-            float g[4];
-            float part = 0.f;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                part += fabsf(d[e]);
-                g[e] = (d[e] > 0.f ? 1.f : (d[e] < 0.f ? -1.f : 0.f)) * inv;
-            }
-            acc += double(part);
-            reinterpret_cast<float4*>(grad)[q] = make_float4(g[0], g[1], g[2], g[3]);
+            acc += double(fabsf(d[0]) + fabsf(d[1]) + fabsf(d[2]) + fabsf(d[3]));
+            if (grad)
+                reinterpret_cast<float4*>(grad)[q] =
+                    make_float4(l1_sign(d[0]) * inv, l1_sign(d[1]) * inv, l1_sign(d[2]) * inv, l1_sign(d[3]) * inv);
         }
         done = n4 * 4;
     }
     for (int64_t i = done + int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
-        float d = rgb[i] - target[i];
+        const float d = rgb[i] - target[i];
         acc += double(fabsf(d));
-        float s = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-        grad[i] = s * inv;
+        if (grad) grad[i] = l1_sign(d) * inv;
     }
+    if (!part) return;
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -279,16 +280,19 @@ extern "C" size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t 
 }
 
 extern "C" int gs_l1_loss(const float* rgb, const float* target, int64_t n_vals, float* loss_dev,
-                          float* grad, void* ws, size_t ws_bytes, hipStream_t stream) {
-    if (n_vals <= 0 || !rgb || !target || !loss_dev || !grad)
+                          float* grad, const float* grad_scale, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n_vals <= 0 || !rgb || !target || (!loss_dev && !grad))
         return fail(GS_ERR_INVALID_ARG, "gs_l1_loss: null pointer or empty input");
-    if (!ws || ws_bytes < size_t(kL1Blocks) * sizeof(double) || !aligned(ws, 8))
+    if (loss_dev && (!ws || ws_bytes < size_t(kL1Blocks) * sizeof(double) || !aligned(ws, 8)))
         return fail(GS_ERR_WORKSPACE, "gs_l1_loss: workspace too small");
     int blocks = int((n_vals + 255) / 256);
     if (blocks > kL1Blocks) blocks = kL1Blocks;
-    double* part = static_cast<double*>(ws);
-    hipLaunchKernelGGL(k_l1_partial, dim3(blocks), dim3(256), 0, stream, rgb, target, n_vals, grad, part);
-    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, stream, part, blocks, n_vals, loss_dev);
+    double* part = loss_dev ? static_cast<double*>(ws) : nullptr;
+    launch("l1_partial", k_l1_partial, dim3(blocks), dim3(256), 0, stream, rgb, target, n_vals, grad, grad_scale,
+           part);
+    if (loss_dev)
+        launch("l1_final", k_l1_final, dim3(1), dim3(256), 0, stream, static_cast<const double*>(part), blocks,
+               n_vals, loss_dev);
     return check_launch("gs_l1_loss");
 }
 

@@ -265,7 +265,6 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
     }
     lmax = wave_max_u32(lmax);
     const int lane = threadIdx.x;
-    const int64_t n_in = I.n_in;
     float* d2 = I.d2[t.c];
     const uint32_t stop_at = t.start + min(lmax, t.end - t.start);
     RawRec R = {};

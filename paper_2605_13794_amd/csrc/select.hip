@@ -195,8 +195,6 @@ __global__ __launch_bounds__(256) void k_gate_compact(GateArgs G, int64_t chunk,
     }
 }
 
-// Gaussians per workgroup of the gate: a multiple of 256 with at most 1,024
-// workgroups, so that each workgroup of the second pass reads all counts.
 // Gaussians per gate workgroup: 512 (many workgroups in flight; on the 1M view
 // the step runs 5 % faster than with 2,048), doubled until there are at most
 // 2,048 workgroups, since every compaction workgroup reduces all their counts.

@@ -84,7 +84,7 @@ def lib() -> ctypes.CDLL:
         L.gs_render_bwd.argtypes = [P, P, c_i64, P, P, P, c_int, P, P, P, P, P, P, P, P, P, P, P, c_sz, P]
         L.gs_importance.argtypes = [P, P, c_i64, P, P, c_f, c_f, P, P, P, P, P, P, P, c_sz, P]
         L.gs_score_keep_bits.argtypes = [P, c_i64, c_i64, P, P, c_sz, P]
-        L.gs_l1_loss.argtypes = [P, P, c_i64, P, P, P, c_sz, P]
+        L.gs_l1_loss.argtypes = [P, P, c_i64, P, P, P, P, c_sz, P]
         L.gs_adam_step.argtypes = [P, P, P, P, P, c_int, P, c_f, c_f, c_f, c_int, P, c_int, P]
         L.gs_profile_kernel.argtypes = [ctypes.c_char_p, P, P]
         L.gs_mass_keep_bits.argtypes = [P, c_i64, c_f, P, P, P, c_sz, P]
@@ -284,9 +284,9 @@ def gs_scale_reg(scn: GsScene, active_idx, n_in, n_in_dev, radius, beta, loss_de
            "gs_scale_reg")
 
 
-def gs_l1_loss(rgb, target, n_vals, loss_dev, grad, ws, stream=None):
-    _check(lib().gs_l1_loss(ptr(rgb), ptr(target), int(n_vals), ptr(loss_dev), ptr(grad), ptr(ws), ws.numel(),
-                            stream_handle(stream)), "gs_l1_loss")
+def gs_l1_loss(rgb, target, n_vals, loss_dev, grad, ws, stream=None, grad_scale=None):
+    _check(lib().gs_l1_loss(ptr(rgb), ptr(target), int(n_vals), ptr(loss_dev), ptr(grad), ptr(grad_scale), ptr(ws),
+                            ws.numel() if ws is not None else 0, stream_handle(stream)), "gs_l1_loss")
 
 
 def gs_adam_step(params, grads_, m, v, lrs, b1, b2, eps, step, clear_grads=False, step_dev=None, stream=None):

@@ -121,6 +121,9 @@ class Frame:
         self.n_in = self.n_max
         self.active = None
         self.n_in_dev = None
+        # incremented by every forward: the buffers a backward reads (lists,
+        # final transmittance, `last`, projections) belong to one forward
+        self.generation = 0
 
     def ensure_capacity(self, cap: int):
         cap = int(min(max(cap, 1), G.GS_MAX_PAIRS - 1))
@@ -163,7 +166,12 @@ class Frame:
             return K
         return None
 
-    def render_fwd(self, bg=(0.0, 0.0, 0.0), stream=None):
+    def render_fwd(self, bg=(0.0, 0.0, 0.0), stream=None, out_rgb=None):
+        """Composites every camera; out_rgb (optional) replaces the frame's
+        own image buffers (one [3][H][W] tensor per camera)."""
+        self.generation += 1
+        if out_rgb is not None:
+            self.rgb = list(out_rgb)
         self.bg = tuple(float(x) for x in bg)
         chain = None
         if self.store_chain:
@@ -175,10 +183,11 @@ class Frame:
                         self.last, chain=chain, live=self.live, stream=stream)
         return FrameOutputs(self.rgb, self.T, self.last)
 
-    def forward(self, scn, active=None, n_in=None, n_in_dev=None, bg=(0.0, 0.0, 0.0), check=True, stream=None):
+    def forward(self, scn, active=None, n_in=None, n_in_dev=None, bg=(0.0, 0.0, 0.0), check=True, stream=None,
+                out_rgb=None):
         self.project(scn, active, n_in, n_in_dev, stream)
         K = self.bin_sort(check=check, stream=stream)
-        out = self.render_fwd(bg, stream)
+        out = self.render_fwd(bg, stream, out_rgb=out_rgb)
         return out, K
 
     # -- loss and backward ----------------------------------------------------
@@ -200,9 +209,14 @@ class RasterizeFn(torch.autograd.Function):
     """Differentiable rasterization of a batch of cameras.
 
     forward(frame, scene, mean, log_scale, quat, opacity_logit, sh) -> images
-    [B, 3, H, W] (all cameras of the frame must share one resolution).  The
-    backward calls gs_render_bwd, which recomputes every pixel's
-    transmittance chain from the final T instead of storing it.
+    [B, 3, H, W] (all cameras of the frame must share one resolution),
+    composited straight into a new tensor.  The backward calls gs_render_bwd,
+    which recomputes every pixel's transmittance chain from the final T
+    instead of storing it (or reads the chain when the frame stores it).
+
+    A frame holds the buffers of its latest forward only: a second forward
+    through the same frame before this graph's backward makes the backward
+    raise instead of differentiating the wrong frame.
     """
 
     @staticmethod
@@ -211,21 +225,58 @@ class RasterizeFn(torch.autograd.Function):
         params = [mean, log_scale, quat, opacity_logit, sh]
         scn = G.scene(*[p.detach() for p in params], lod=dscene.lod)
         n_in = None if active is None else int(active.numel())
-        out, _ = frame.forward(scn, active, n_in, n_in_dev)
+        h, w = frame.cams[0].height, frame.cams[0].width
+        if any((c.height, c.width) != (h, w) for c in frame.cams):
+            raise ValueError("RasterizeFn: every camera of the frame must share one resolution")
+        images = torch.empty(len(frame.cams), 3, h, w, dtype=F32, device=frame.device)
+        frame.forward(scn, active, n_in, n_in_dev, out_rgb=list(images.unbind(0)))
         ctx.frame, ctx.scn, ctx.params = frame, scn, [p.detach() for p in params]
-        return torch.stack([x.clone() for x in out.rgb])
+        ctx.generation = frame.generation
+        return images
 
     @staticmethod
     def backward(ctx, grad_out):
         frame = ctx.frame
+        if frame.generation != ctx.generation:
+            raise RuntimeError("RasterizeFn.backward: the frame ran another forward after this one; its lists and "
+                               "transmittance no longer belong to this graph (use one frame per graph)")
         gr = [torch.zeros_like(p) for p in ctx.params]
-        grad_rgb = [grad_out[c].contiguous() for c in range(len(frame.cams))]
-        frame.backward(ctx.scn, G.grads(*gr), grad_rgb=grad_rgb)
+        grad_out = grad_out.contiguous()
+        frame.backward(ctx.scn, G.grads(*gr), grad_rgb=list(grad_out.unbind(0)))
         return (None, None, *gr, None, None)
 
 
 def rasterize(frame: Frame, dscene: DeviceScene, active=None, n_in_dev=None):
     return RasterizeFn.apply(frame, dscene, *dscene.params(), active, n_in_dev)
+
+
+class L1LossFn(torch.autograd.Function):
+    """L = mean |C - target| over all values of C (any shape, float32,
+    contiguous) through gs_l1_loss; the backward writes
+    dL/dC = g * sign(C - target) / numel with the upstream derivative g read
+    on the device (no host synchronisation, no tensor arithmetic)."""
+
+    @staticmethod
+    def forward(ctx, img, target):
+        img_c, tgt_c = img.detach().contiguous(), target.detach().contiguous()
+        if img_c.shape != tgt_c.shape or img_c.dtype != F32 or tgt_c.dtype != F32:
+            raise ValueError("l1_loss: image and target must be float32 tensors of one shape")
+        loss = torch.empty((), dtype=F32, device=img_c.device)
+        ws = torch.empty(G.gs_workspace_size(G.GS_OP_L1_LOSS), dtype=U8, device=img_c.device)
+        G.gs_l1_loss(img_c, tgt_c, img_c.numel(), loss, None, ws)
+        ctx.save_for_backward(img_c, tgt_c)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        img_c, tgt_c = ctx.saved_tensors
+        grad = torch.empty_like(img_c)
+        G.gs_l1_loss(img_c, tgt_c, img_c.numel(), None, grad, None, grad_scale=grad_loss.detach().contiguous())
+        return grad, None
+
+
+def l1_loss(img, target):
+    return L1LossFn.apply(img, target)
 
 
 class Adam:

@@ -194,6 +194,20 @@ class GpuExecutor:
     def images(self, slot: int):
         return self.slots[slot]["out"]
 
+    def copy_images(self, slot: int):
+        """Copies of the slot's finished images, made on the slot's own stream
+        (so they are ordered before the slot's next batch, which may reuse
+        the memory of these outputs); the current stream then waits for them."""
+        torch = self.torch
+        s = self.slots[slot]
+        with torch.cuda.stream(s["stream"]):
+            copies = [o[0].clone() for o in s["out"]]
+        cur = torch.cuda.current_stream()
+        cur.wait_stream(s["stream"])
+        for c in copies:
+            c.record_stream(cur)
+        return copies
+
 
 def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, keep_images=False, idle_sleep=0.0):
     """Runs the arrival trace (request.arrival in seconds from the start)
@@ -218,13 +232,13 @@ def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, kee
                     continue
                 t = clock() - t0
                 batch = scheduler.finish(slot, K)
-                imgs = executor.images(slot)
+                imgs = executor.copy_images(slot) if keep_images else None
                 for k, r in enumerate(batch):
                     r.t_done = t
                     r.pairs = K
                     done.append(r)
                     if keep_images:
-                        images[r.rid] = imgs[k][0].clone()
+                        images[r.rid] = imgs[k]
         # admissions
         while True:
             nb = scheduler.next_batch()

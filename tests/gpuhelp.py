@@ -132,3 +132,27 @@ def assert_same_ranges(got, ref):
     np.testing.assert_array_equal(got[1] - got[0], ref[1] - ref[0])
     ne = ref[1] > ref[0]
     np.testing.assert_array_equal(got[0][ne], ref[0][ne])
+
+
+def comparable_pixels(ref, rad_gpu, width, height, margin=1e-3):
+    """[H][W] mask of the pixels where an end-to-end comparison (float32
+    projection against the float64 one) is meaningful: every threshold test
+    of the pixel clears its threshold by `margin` (relative), no Gaussian of
+    the pixel's tile has a different integer radius on the two sides, and the
+    pixel's colour does not depend on the order of two near-equal depths.
+    `ref` is the reference's forward_backward result for the same entries
+    that the device projected; rad_gpu the device radii of those entries."""
+    pr = ref["projected"]
+    bad = set(np.nonzero(np.asarray(rad_gpu)[:pr.n] != pr.radius)[0].tolist())
+    tiles = set()
+    if bad:
+        for key, val in zip(ref["keys"].tolist(), ref["vals"].tolist()):
+            if val in bad:
+                tiles.add(key >> 32)
+    ties = tie_pixel_mask(pr, ref["keys"], ref["vals"], ref["out"]["depth"].detach().numpy(), width, height)
+    return (ref["margin"] >= margin) & tile_mask(tiles, width, height) & ties, len(bad)
+
+
+def rel_inf(g, ref):
+    """max|g - ref| / max|ref| (per tensor)."""
+    return float(np.abs(g - ref).max() / max(np.abs(ref).max(), 1e-30))
