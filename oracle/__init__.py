@@ -11,6 +11,9 @@ Parts and the passages they follow:
                `alpha_compositing`), its backward with the stored float64
                transmittance chain, and the colour-less instrumented blend of
                the importance sweep (Sec. 3.2, Fig. 3).
+  levels.py    LOD labels from multi-resolution voxelisation, the L_max(t)
+               schedule, the clone/split level inheritance and the spawn
+               gate's rank veto (Sec. 3.3; Sec. 3.2 and Appendix E).
   this file    loss, importance aggregation (s_i, c^rad, c^vis, Cull; Sec. 3.2),
                the view-level LOD gate and active set (Sec. 3.3, Eqs. 1-3),
                the score mask, Adam, and the end-to-end pipeline.

@@ -173,3 +173,63 @@ def test_adam_without_bias_correction_is_caught(oracle, monkeypatch):
     monkeypatch.setattr(oracle, "adam_step",
                         lambda p, g, m, v, lr, step, **k: orig(p, g, m, v, lr, 10 ** 9, **k))
     _fails(P.test_adam_first_step_and_torch, oracle)
+
+
+# ---------------------------------------------------------------------------
+# LOD levels, L_max(t) and the spawn-gate veto (oracle/levels.py)
+# ---------------------------------------------------------------------------
+def _levels_mutant(old, new):
+    import types
+
+    from oracle import levels
+    src = open(levels.__file__).read()
+    assert src.count(old) == 1, old
+    mod = types.ModuleType("levels_mutant")
+    exec(compile(src.replace(old, new), "levels_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+LEVEL_MUTATIONS = {
+    "representative is the last point of its cube": (
+        "order = np.lexsort((idx, code, key))", "order = np.lexsort((-idx, -code, key))"),
+    "ties inside a finest cell by descending index": (
+        "order = np.lexsort((idx, code, key))", "order = np.lexsort((-idx, code, key))"),
+    "label is the finest level represented": (
+        "for lvl in range(K - 1, -1, -1):", "for lvl in range(K):"),
+    "cube shift off by one": ("sh = K - 1 - lvl", "sh = K - lvl"),
+    "x and y swapped in the Z-order code": (
+        "code |= ((cells[axis] >> b) & 1) << (3 * b + axis)",
+        "code |= ((cells[(1, 0, 2)[axis]] >> b) & 1) << (3 * b + axis)"),
+    "cell decision in float64": (
+        "q = np.floor((m - o) * s)", "q = np.floor((m.astype(np.float64) - o) / float(delta0) * 2 ** (n_levels - 1))"),
+    "unlock times spaced linearly": (
+        "u = t0 * (t1 / t0) ** (k / (K - 1))", "u = t0 + (t1 - t0) * k / (K - 1)"),
+    "veto count rounded down": (
+        "return min(n, max(0, int(math.ceil(float(rho) * n))))", "return min(n, max(0, int(float(rho) * n)))"),
+    "veto keeps the lowest survival": (
+        "keep[order[:veto_count(n, rho)]] = False", "keep[order[n - veto_count(n, rho):]] = False"),
+    "veto ties by descending index": (
+        "order = np.lexsort((np.arange(n), p))", "order = np.lexsort((-np.arange(n), p))"),
+    "split keeps the parent's level": (
+        "lv = np.asarray(parent_level, dtype=np.int64) + (1 if split else 0)",
+        "lv = np.asarray(parent_level, dtype=np.int64)"),
+    "split level not clamped": (
+        "return np.minimum(lv, n_levels - 1).astype(np.uint8)", "return lv.astype(np.uint8)"),
+    "stub scorer uses the child's index": (
+        "z = np.asarray(opacity_logit, dtype=np.float32)[np.asarray(parents, dtype=np.int64)]",
+        "z = np.asarray(opacity_logit, dtype=np.float32)[np.arange(len(parents)) % len(opacity_logit)]"),
+    "reference distance by mean instead of median": ("return float(np.median(d))", "return float(np.mean(d))"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LEVEL_MUTATIONS))
+def test_level_mutation_is_caught(name):
+    from tests import test_oracle_levels as PL
+    mod = _levels_mutant(*LEVEL_MUTATIONS[name])
+    failed = []
+    for pin in PL.PINS:
+        try:
+            pin(mod)
+        except (AssertionError, IndexError, ValueError):
+            failed.append(pin.__name__)
+    assert failed, f"no pin catches: {name}"
