@@ -47,7 +47,7 @@ def build(force: bool = False) -> str:
     src = os.path.join(_HERE, "raster.c")
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
                                "-fno-fast-math", src, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -69,6 +69,8 @@ def lib():
         L.gso_render_bwd.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P]
         L.gso_importance_blend.restype = None
         L.gso_importance_blend.argtypes = [i32, i32, i64, P, P, P, P, P, P, P]
+        L.gso_num_threads.restype = ctypes.c_int
+        L.gso_num_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -76,6 +78,11 @@ def lib():
 def _p(a: np.ndarray):
     assert a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    """Threads the compiled compositing loops use (OpenMP)."""
+    return int(lib().gso_num_threads())
 
 
 def n_tiles(width: int, height: int) -> int:

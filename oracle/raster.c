@@ -15,11 +15,18 @@
  *    instrumented blend without colour records w_{i,v} = sum_p alpha_p T_p and
  *    the count a_{i,v} of pixels at which g_i is composited.
  *
+ * Threads (OpenMP, OMP_NUM_THREADS): pixels are independent in the forward;
+ * the backward and the importance blend accumulate per Gaussian, so each
+ * thread sums into its own arrays, over an interleaved static share of the
+ * image rows, and the per-thread arrays are added in thread order (the same
+ * per-term arithmetic; the summation order depends only on the thread count).
+ *
  * Layouts: component-major arrays ([2][n] mean2d, [3][n] conic and rgb),
  * images [3][H][W], per-pixel maps [H][W].  Gaussians are visited in list
  * order; the list of a tile is sorted by (tile, float32 depth bits, index).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -118,6 +125,8 @@ int64_t gso_bin_sort(int64_t n, const double* mean2d, const int32_t* radius,
 
 static double rel_gap(double v, double thr) { return fabs(v - thr) / thr; }
 
+int gso_num_threads(void) { return omp_get_max_threads(); }
+
 /*
  * Forward compositing of every pixel.  Outputs the colour [3][H][W] (with
  * T_final * bg added), the final transmittance, `last` = 1 + list position of
@@ -134,6 +143,7 @@ void gso_render_fwd(int32_t width, int32_t height, int64_t n, const double* mean
     const int64_t TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     const int64_t n_tiles = TX * TY;
     const int64_t npx = (int64_t)width * height;
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t v = 0; v < height; ++v)
         for (int64_t u = 0; u < width; ++u) {
             const int64_t t = (v / TILE) * TX + (u / TILE);
@@ -213,7 +223,19 @@ void gso_render_bwd(int32_t width, int32_t height, int64_t n, const double* mean
         int64_t l = (int64_t)ranges[n_tiles + t] - (int64_t)ranges[t];
         if (l > max_len) max_len = l;
     }
+    const int nt = omp_get_max_threads();
+    /* per-thread accumulators: 9 rows of n (mean2d 2, conic 3, opacity 1, rgb 3) */
+    double* priv = nt > 1 ? (double*)calloc((size_t)nt * 9 * (size_t)n, sizeof(double)) : NULL;
+#pragma omp parallel num_threads(nt)
+    {
+    const int tid = omp_get_thread_num();
+    double* acc = priv ? priv + (size_t)tid * 9 * (size_t)n : NULL;
+    double* d_mean2d_t = acc ? acc : d_mean2d;
+    double* d_conic_t = acc ? acc + 2 * n : d_conic;
+    double* d_opacity_t = acc ? acc + 5 * n : d_opacity;
+    double* d_rgb_t = acc ? acc + 6 * n : d_rgb;
     chain_t* ch = (chain_t*)malloc((size_t)(max_len + 1) * sizeof(chain_t));
+#pragma omp for schedule(static, 1)
     for (int64_t v = 0; v < height; ++v)
         for (int64_t u = 0; u < width; ++u) {
             const int64_t t = (v / TILE) * TX + (u / TILE);
@@ -250,22 +272,32 @@ void gso_render_bwd(int32_t width, int32_t height, int64_t n, const double* mean
                     const double cj = rgb[c3 * n + j];
                     const double dc = cj * e->T - (suffix[c3] + Tfin * bg[c3]) / (1.0 - e->alpha);
                     dl_dalpha += gi[c3] * dc;
-                    d_rgb[c3 * n + j] += gi[c3] * e->alpha * e->T;
+                    d_rgb_t[c3 * n + j] += gi[c3] * e->alpha * e->T;
                 }
                 for (int c3 = 0; c3 < 3; ++c3) suffix[c3] += rgb[c3 * n + j] * e->alpha * e->T;
                 if (e->g > ALPHA_MAX) continue;  /* clamped: alpha is constant */
                 const double dl_dG = dl_dalpha * opacity[j];
-                d_opacity[j] += dl_dalpha * e->G;
+                d_opacity_t[j] += dl_dalpha * e->G;
                 const double dl_dpower = dl_dG * e->G;
                 const double a = conic[j], b = conic[n + j], c = conic[2 * n + j];
-                d_mean2d[j] += dl_dpower * (-(a * e->dx + b * e->dy));
-                d_mean2d[n + j] += dl_dpower * (-(b * e->dx + c * e->dy));
-                d_conic[j] += dl_dpower * (-0.5 * e->dx * e->dx);
-                d_conic[n + j] += dl_dpower * (-e->dx * e->dy);
-                d_conic[2 * n + j] += dl_dpower * (-0.5 * e->dy * e->dy);
+                d_mean2d_t[j] += dl_dpower * (-(a * e->dx + b * e->dy));
+                d_mean2d_t[n + j] += dl_dpower * (-(b * e->dx + c * e->dy));
+                d_conic_t[j] += dl_dpower * (-0.5 * e->dx * e->dx);
+                d_conic_t[n + j] += dl_dpower * (-e->dx * e->dy);
+                d_conic_t[2 * n + j] += dl_dpower * (-0.5 * e->dy * e->dy);
             }
         }
     free(ch);
+    }
+    if (priv) {
+        double* outs[9] = {d_mean2d, d_mean2d + n, d_conic, d_conic + n, d_conic + 2 * n, d_opacity,
+                           d_rgb, d_rgb + n, d_rgb + 2 * n};
+#pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < n; ++j)
+            for (int r = 0; r < 9; ++r)
+                for (int t = 0; t < nt; ++t) outs[r][j] += priv[((size_t)t * 9 + r) * (size_t)n + j];
+        free(priv);
+    }
     (void)TY;
 }
 
@@ -279,6 +311,15 @@ void gso_importance_blend(int32_t width, int32_t height, int64_t n, const double
                           const uint32_t* ranges, double* w, int64_t* a) {
     const int64_t TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     const int64_t n_tiles = TX * TY;
+    const int nt = omp_get_max_threads();
+    double* wp = nt > 1 ? (double*)calloc((size_t)nt * (size_t)n, sizeof(double)) : NULL;
+    int64_t* ap = nt > 1 ? (int64_t*)calloc((size_t)nt * (size_t)n, sizeof(int64_t)) : NULL;
+#pragma omp parallel num_threads(nt)
+    {
+    const int tid = omp_get_thread_num();
+    double* w_t = wp ? wp + (size_t)tid * (size_t)n : w;
+    int64_t* a_t = ap ? ap + (size_t)tid * (size_t)n : a;
+#pragma omp for schedule(static, 1)
     for (int64_t v = 0; v < height; ++v)
         for (int64_t u = 0; u < width; ++u) {
             const int64_t t = (v / TILE) * TX + (u / TILE);
@@ -296,10 +337,21 @@ void gso_importance_blend(int32_t width, int32_t height, int64_t n, const double
                 if (alpha < ALPHA_MIN) continue;
                 const double Tn = T * (1.0 - alpha);
                 if (Tn < T_MIN) break;
-                w[j] += alpha * T;
-                a[j] += 1;
+                w_t[j] += alpha * T;
+                a_t[j] += 1;
                 T = Tn;
             }
         }
+    }
+    if (wp) {
+#pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < n; ++j)
+            for (int t = 0; t < nt; ++t) {
+                w[j] += wp[(size_t)t * (size_t)n + j];
+                a[j] += ap[(size_t)t * (size_t)n + j];
+            }
+        free(wp);
+        free(ap);
+    }
     (void)TY;
 }

@@ -29,7 +29,7 @@ def _mutant_lib(oracle, tmp_path, replacements):
     c = tmp_path / "raster_mutant.c"
     c.write_text(src)
     so = tmp_path / "raster_mutant.so"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
                            str(c), "-o", str(so), "-lm"])
     return str(so)
 
@@ -82,19 +82,19 @@ def test_wrong_stop_level_is_caught(oracle, with_c_mutation):
 
 
 def test_flipped_mean_gradient_in_backward_is_caught(oracle, with_c_mutation):
-    line = "d_mean2d[j] += dl_dpower * (-(a * e->dx + b * e->dy));"
+    line = "d_mean2d_t[j] += dl_dpower * (-(a * e->dx + b * e->dy));"
     with_c_mutation([(line, line.replace("(-(a", "((a"), 1)])
     _fails(P.test_gradients_match_finite_differences, oracle, (0.0, 0.0, 0.0), 0.0, -1.8)
 
 
 def test_halved_cross_term_of_conic_gradient_is_caught(oracle, with_c_mutation):
-    line = "d_conic[n + j] += dl_dpower * (-e->dx * e->dy);"
+    line = "d_conic_t[n + j] += dl_dpower * (-e->dx * e->dy);"
     with_c_mutation([(line, line.replace("(-e->dx", "(-0.5 * e->dx"), 1)])
     _fails(P.test_gradients_match_finite_differences, oracle, (0.0, 0.0, 0.0), 0.0, -1.8)
 
 
 def test_importance_weight_without_transmittance_is_caught(oracle, with_c_mutation):
-    with_c_mutation([("w[j] += alpha * T;", "w[j] += alpha;", 1)])
+    with_c_mutation([("w_t[j] += alpha * T;", "w_t[j] += alpha;", 1)])
     _fails(P.test_importance_sum_identity, oracle)
     _fails(P.test_matches_bruteforce_depth_order, oracle)
 
