@@ -171,6 +171,23 @@ int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs_lod_params
                 void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * gs_lod_mask without a workspace, for callers that cannot allocate device
+ * memory or pass a workspace (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as gs_lod_mask.  Its scratch (gate bitmap and per-workgroup counts,
+ * 2,162,688 bytes) is a fixed array inside the library, one per GPU, held
+ * until the process ends; it allows n <= 16,777,216 (2^24) Gaussians and
+ * returns GS_ERR_INVALID_ARG above that.  The first call on a device looks up
+ * that device's copy (GS_ERR_HIP if the lookup fails).  The call allocates
+ * nothing.  Every call on one GPU shares its array: calls that overlap on one
+ * GPU (concurrent streams or host threads) race and must be serialised by the
+ * caller.
+ */
+int gs_lod_mask_noalloc(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
+                        const uint32_t* keep_bits, int32_t* active_idx, int64_t* n_active_dev,
+                        hipStream_t stream);
+
+/*
  * Projection (Appendix A: Gaussians projected to screen-space ellipses) of
  * the input list into n_cams cameras at once, reading the scene once.
  * Entry j < n_in is Gaussian active_idx[j] (active_idx NULL: Gaussian j).

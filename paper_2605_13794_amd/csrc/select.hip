@@ -2,6 +2,8 @@
 // per-view top-mass cut, and the score mask.  Order statistics use an
 // MSD radix select over float bits (4 passes of 8 bits, histograms in LDS);
 // ties at the threshold are resolved by index with a block-count scan.
+#include <mutex>
+
 #include "common.h"
 
 namespace gsmi {
@@ -596,9 +598,8 @@ int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, cons
                             const uint32_t* ranges, float* wa, hipStream_t stream);
 }
 
-extern "C" int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
-                           const uint32_t* keep_bits, int32_t* active_idx, int64_t* n_active_dev, void* ws,
-                           size_t ws_bytes, hipStream_t stream) {
+static int lod_mask_checks(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
+                           const int32_t* active_idx, const int64_t* n_active_dev) {
     if (!scene || !cam || !params || !active_idx || !n_active_dev)
         return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: null argument");
     if (scene->n < 0 || scene->n >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: bad n");
@@ -611,9 +612,14 @@ extern "C" int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs
         return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: level mode needs lod labels, d0 > 0 and f > 1");
     if (n > 0 && params->mode == GS_LOD_RADIUS && !scene->log_scale)
         return fail(GS_ERR_INVALID_ARG, "gs_lod_mask: radius mode needs log-scales");
-    const size_t need = ws_lod_mask(n);
-    if (!ws || ws_bytes < need || !aligned(ws, 256))
-        return fail(GS_ERR_WORKSPACE, "gs_lod_mask: workspace needs %zu bytes (256-aligned)", need);
+    return GS_OK;
+}
+
+// Gate and compaction with the scratch at `ws` (checked by the caller).
+static int lod_mask_launch(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
+                           const uint32_t* keep_bits, int32_t* active_idx, int64_t* n_active_dev, void* ws,
+                           hipStream_t stream) {
+    const int64_t n = scene->n;
     DevCam dc = make_devcam(*cam, 0);
     GateArgs G;
     memset(&G, 0, sizeof(G));
@@ -643,6 +649,63 @@ extern "C" int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs
            static_cast<const uint32_t*>(words), static_cast<const uint32_t*>(c_gate),
            static_cast<const uint32_t*>(c_act), static_cast<const uint32_t*>(c_keep), active_idx, n_active_dev);
     return check_launch("gs_lod_mask");
+}
+
+extern "C" int gs_lod_mask(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
+                           const uint32_t* keep_bits, int32_t* active_idx, int64_t* n_active_dev, void* ws,
+                           size_t ws_bytes, hipStream_t stream) {
+    int rc = lod_mask_checks(scene, cam, params, active_idx, n_active_dev);
+    if (rc) return rc;
+    const size_t need = ws_lod_mask(scene->n);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_lod_mask: workspace needs %zu bytes (256-aligned)", need);
+    return lod_mask_launch(scene, cam, params, keep_bits, active_idx, n_active_dev, ws, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free gate: the scratch of gs_lod_mask (gate bitmap and
+// per-workgroup counts, fully rewritten by every call, so nothing needs
+// clearing) lives in a fixed device array.  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address is looked up once
+// per device with hipGetSymbolAddress and only that address is handed to
+// kernels.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 24;
+constexpr size_t kNoAllocScratchBytes = (size_t(2) << 20) + (size_t(64) << 10);
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_on_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(GS_ERR_HIP, "gs_lod_mask_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_HIP, "gs_lod_mask_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GS_ERR_HIP, "gs_lod_mask_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GS_OK;
+}
+
+extern "C" int gs_lod_mask_noalloc(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
+                                   const uint32_t* keep_bits, int32_t* active_idx, int64_t* n_active_dev,
+                                   hipStream_t stream) {
+    int rc = lod_mask_checks(scene, cam, params, active_idx, n_active_dev);
+    if (rc) return rc;
+    if (scene->n > kNoAllocMaxN || ws_lod_mask(scene->n) > kNoAllocScratchBytes)
+        return fail(GS_ERR_INVALID_ARG, "gs_lod_mask_noalloc: n = %lld exceeds the fixed scratch (at most %lld)",
+                    (long long)scene->n, (long long)kNoAllocMaxN);
+    void* ws = nullptr;
+    if ((rc = scratch_on_current_device(&ws))) return rc;
+    return lod_mask_launch(scene, cam, params, keep_bits, active_idx, n_active_dev, ws, stream);
 }
 
 extern "C" int gs_importance(const gs_projected* proj, const gs_camera* cam, int64_t n, const uint32_t* vals,

@@ -30,7 +30,7 @@ REC_FLOATS = 12
 EXPORTED = ("gs_workspace_size", "gs_last_error", "gs_num_tiles", "gs_lod_mask", "gs_project", "gs_bin_sort",
             "gs_render_fwd", "gs_render_bwd", "gs_importance", "gs_score_keep_bits", "gs_l1_loss",
             "gs_adam_step", "gs_profile_kernel", "gs_mass_keep_bits", "gs_sample_keep_bits", "gs_compact",
-            "gs_photo_loss", "gs_scale_reg")
+            "gs_photo_loss", "gs_scale_reg", "gs_lod_mask_noalloc")
 
 c_int, c_i32, c_i64, c_f, c_p, c_sz = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                        ctypes.c_void_p, ctypes.c_size_t)
@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
         L.gs_num_tiles.restype = c_i64
         L.gs_num_tiles.argtypes = [c_i32, c_i32]
         L.gs_lod_mask.argtypes = [P, P, P, P, P, P, P, c_sz, P]
+        L.gs_lod_mask_noalloc.argtypes = [P, P, P, P, P, P, P]
         L.gs_project.argtypes = [P, P, c_i64, P, P, c_int, P, P, c_sz, P]
         L.gs_bin_sort.argtypes = [P, P, c_int, c_i64, P, P, c_i64, P, P, P, c_sz, P]
         L.gs_render_fwd.argtypes = [P, P, c_int, P, P, P, P, P, P, P, P, P]
@@ -207,6 +208,13 @@ def gs_lod_mask(scn: GsScene, cam: GsCamera, params: GsLodParams, keep_bits, act
     _check(lib().gs_lod_mask(ctypes.byref(scn), ctypes.byref(cam), ctypes.byref(params), ptr(keep_bits),
                              ptr(active_idx), ptr(n_active_dev), ptr(ws), ws.numel() if ws is not None else 0,
                              stream_handle(stream)), "gs_lod_mask")
+
+
+def gs_lod_mask_noalloc(scn: GsScene, cam: GsCamera, params: GsLodParams, keep_bits, active_idx, n_active_dev,
+                        stream=None):
+    _check(lib().gs_lod_mask_noalloc(ctypes.byref(scn), ctypes.byref(cam), ctypes.byref(params), ptr(keep_bits),
+                                     ptr(active_idx), ptr(n_active_dev), stream_handle(stream)),
+           "gs_lod_mask_noalloc")
 
 
 def gs_project(scn: GsScene, active_idx, n_in, n_in_dev, cams, outs, ws, stream=None):

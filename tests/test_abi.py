@@ -73,3 +73,18 @@ def test_host_side_errors(G):
     out = ctypes.c_void_p(256)
     rc = L.gs_lod_mask(ctypes.byref(sc), ctypes.byref(cams[0]), ctypes.byref(p), None, out, out, out, 16, None)
     assert rc == G.GS_ERR_WORKSPACE
+
+
+def test_noalloc_gate_refuses_oversized_input_on_the_host(G):
+    """The allocation-free gate rejects more Gaussians than its fixed scratch
+    holds before touching the device."""
+    from paper_2605_13794_amd import scenes as S
+    scn = G.GsScene()
+    scn.n = (1 << 24) + 1
+    cam = G.camera(S.cube_camera())
+    prm = G.lod_params(G.GS_LOD_NONE)
+    dummy = ctypes.c_void_p(256)
+    rc = G.lib().gs_lod_mask_noalloc(ctypes.byref(scn), ctypes.byref(cam), ctypes.byref(prm), None, dummy, dummy,
+                                     None)
+    assert rc == G.GS_ERR_INVALID_ARG
+    assert "exceeds the fixed scratch" in G.lib().gs_last_error().decode()
