@@ -128,7 +128,9 @@ enum {
     GS_OP_SIMPLIFY = 6,
     GS_OP_PHOTO_LOSS = 7, /* n = width * 65536 + height */
     GS_OP_SCALE_REG = 8,
-    GS_OP_PROJECT = 9
+    GS_OP_PROJECT = 9,
+    GS_OP_VOXEL_LEVELS = 10,
+    GS_OP_SPAWN_GATE = 11 /* n = max(n_clone, n_split) */
 };
 
 /* Bytes of workspace `op` needs for n Gaussians (per camera), n_pairs pair
@@ -385,6 +387,52 @@ int gs_adam_step(float* const* params, float* const* grads, float* const* m,
                  float* const* v, const int64_t* counts, int n_groups, const float* lr,
                  float b1, float b2, float eps, int step, int32_t* step_dev, int clear_grads,
                  hipStream_t stream);
+
+/*
+ * LOD labels by multi-resolution voxelisation (Sec. 3.3, "Distance-based LOD
+ * gate": labels attached at multi-resolution voxelisation).  Level l
+ * partitions space into cubes of edge delta0 / 2^l anchored at origin[3]
+ * (host floats, e.g. the per-axis minimum of the means); every occupied
+ * level-l cube is represented by one Gaussian, its first in the order
+ * (Z-order code of the point's finest cell, index), and lod[i] is the
+ * coarsest level l in [0, n_levels) at which Gaussian i represents its cube,
+ * n_levels - 1 if none.  Keeping lod <= L therefore keeps exactly one
+ * Gaussian per occupied cube of edge delta0 / 2^L.  The finest cell of a point
+ * is floor((mean - origin) * s) per axis in float32 with s = 2^(n_levels-1) /
+ * delta0 (NaN -> 0, clamped to [0, 2^21)).  mean [3][n]; lod [n] (written).
+ * n_levels in [1, 22].  If the internal sort fails (a bounded wait timed out)
+ * every label is 255.  Workspace: GS_OP_VOXEL_LEVELS.
+ */
+int gs_voxel_levels(const float* mean, int64_t n, const float* origin, float delta0, int32_t n_levels,
+                    uint8_t* lod, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Spawn gate of one densification event (Sec. 3.2 "Spawn gate"; the veto
+ * equation of Appendix E).  Clones (clone_parent[n_clone], predicted
+ * survival p_clone) and splits (split_parent[n_split], p_split) are separate
+ * candidate sets; in each, the ceil(rho * |C|) candidates of lowest survival
+ * (rho * |C| evaluated in double) are vetoed, ties by candidate index (the
+ * lower index vetoed first).  Survival scores must be non-negative and not
+ * NaN (probabilities).  The instantiated candidates are written in order -
+ * surviving clones in candidate order, then surviving splits - as
+ * child_parent (the parent's index), child_lod (the inherited level: a clone
+ * keeps lod[parent], a split gets lod[parent] + 1, clamped at n_levels - 1)
+ * and child_split (0 clone, 1 split).  *n_children (HOST int64) receives
+ * their number, known before any launch; outputs hold n_clone + n_split
+ * entries.  rho in [0, 1] (0.6 in the paper).  Workspace: GS_OP_SPAWN_GATE.
+ */
+int gs_spawn_gate(const uint8_t* lod, const int32_t* clone_parent, const float* p_clone, int64_t n_clone,
+                  const int32_t* split_parent, const float* p_split, int64_t n_split, double rho,
+                  int32_t n_levels, int32_t* child_parent, uint8_t* child_lod, uint8_t* child_split,
+                  int64_t* n_children, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Stand-in for the offline survival predictor of the spawn gate (Sec. 3.2;
+ * the gradient-boosted tree is fit on lineage logs of real scenes): p[i] =
+ * the opacity of Gaussian parent[i], sigmoid(opacity_logit), one of the
+ * spawn-time features the paper lists.  No workspace.
+ */
+int gs_spawn_stub_score(const gs_scene* scene, const int32_t* parent, int64_t n, float* p, hipStream_t stream);
 
 #ifdef __cplusplus
 }

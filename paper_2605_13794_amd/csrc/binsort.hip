@@ -9,6 +9,13 @@ namespace gsmi {
 // Emission
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = 256;
+// Look-back status words: 2 flag bits (aggregate / inclusive prefix) over a
+// 30-bit count; a bounded number of polls before a wait reports failure.
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1u;
+constexpr uint32_t kSpinLimit = 1u << 24;
+
 constexpr int kScanIters = 1;
 constexpr int kScanItems = kScanThreads * kScanIters;  // entries per block
 
@@ -43,6 +50,7 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 
 // Block-wide exclusive scan of one value per thread (256 threads), returns
 // the exclusive prefix and writes the block total to *total.
+template <int W = 4>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds4, uint32_t* total) {
     const uint32_t inc = wave_incl_scan(v);
     const int w = threadIdx.x / 64;
@@ -50,7 +58,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds4, 
     __syncthreads();
     uint32_t before = 0, tot = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < W; ++k) {
         const uint32_t s = lds4[k];
         if (k < w) before += s;
         tot += s;
@@ -60,63 +68,130 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds4, 
     return before + inc - v;
 }
 
-__global__ __launch_bounds__(256) void k_scan_reduce(EmitIn E, int64_t n_total, uint32_t* __restrict__ block_sums) {
+// Per block of 256 entries: the number of pairs and, if vis_sums is set, the
+// number of visible entries (tile count > 0).
+__global__ __launch_bounds__(256) void k_scan_reduce(EmitIn E, int64_t n_total, uint32_t* __restrict__ block_sums,
+                                                     uint32_t* __restrict__ vis_sums) {
     __shared__ uint32_t lds4[4];
     const int64_t base = int64_t(blockIdx.x) * kScanItems;
-    uint32_t acc = 0;
+    uint32_t acc = 0, vis = 0;
 #pragma unroll 4
     for (int it = 0; it < kScanIters; ++it) {
         const int64_t e = base + int64_t(it) * kScanThreads + threadIdx.x;
-        if (e < n_total) acc += tiles_of(E, e);
+        if (e < n_total) {
+            const uint32_t c = tiles_of(E, e);
+            acc += c;
+            vis += c > 0u;
+        }
     }
     uint32_t tot;
     block_excl_scan(acc, lds4, &tot);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+    if (vis_sums) {
+        uint32_t tv;
+        block_excl_scan(vis, lds4, &tv);
+        if (threadIdx.x == 0) vis_sums[blockIdx.x] = tv;
+    }
 }
 
-// One workgroup: exclusive scan of the block sums, total pair count; also
-// clears the sort's histograms, partition counters and error flag.
-__global__ __launch_bounds__(256) void k_scan_blocks(uint32_t* __restrict__ block_sums, int64_t n_blocks,
-                                                     int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                     uint32_t* __restrict__ n_sorted, uint32_t* __restrict__ hist,
-                                                     uint32_t* __restrict__ counters, uint32_t* __restrict__ err) {
-    __shared__ uint32_t lds4[4];
-    __shared__ uint64_t carry_s;
-    for (int k = threadIdx.x; k < 8 * 256; k += 256) hist[k] = 0;
-    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
-    if (threadIdx.x == 0) *err = 0;
-    if (threadIdx.x == 0) carry_s = 0;
+// Exclusive scan in place of nb per-block sums by one workgroup of
+// kScanWgThreads threads, kScanPer consecutive sums per thread per round: the
+// sums are staged through LDS (coalesced loads and stores; one pad word per
+// 32 keeps the per-thread runs free of bank conflicts); returns the total.
+constexpr int kScanWgThreads = 1024;
+constexpr int kScanPer = 8;
+constexpr int kScanRound = kScanWgThreads * kScanPer;
+constexpr int kScanStage = kScanRound + kScanRound / 32;
+
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
+
+__device__ uint64_t scan_sums_1wg(uint32_t* __restrict__ sums, int64_t nb, uint32_t* lds_w, uint64_t* carry_s,
+                                  uint32_t* stage) {
+    const int tid = threadIdx.x;
+    if (tid == 0) *carry_s = 0;
     __syncthreads();
-    // 16 consecutive sums per thread, 4,096 per round
-    for (int64_t b0 = 0; b0 < n_blocks; b0 += 256 * 16) {
-        const int64_t bt = b0 + int64_t(threadIdx.x) * 16;
-        uint32_t v[16], sum = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanRound) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            v[q] = (bt + q < n_blocks) ? block_sums[bt + q] : 0u;
+        for (int q = 0; q < kScanPer; ++q) {
+            const int idx = q * kScanWgThreads + tid;
+            stage[scan_pad(idx)] = (b0 + idx < nb) ? sums[b0 + idx] : 0u;
+        }
+        __syncthreads();
+        uint32_t v[kScanPer], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            v[q] = stage[scan_pad(tid * kScanPer + q)];
             sum += v[q];
         }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(sum, lds4, &tot);
-        const uint64_t carry = carry_s;
+        const uint32_t ex = block_excl_scan<kScanWgThreads / 64>(sum, lds_w, &tot);
+        const uint64_t carry = *carry_s;
         uint64_t run = carry + ex;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if (bt + q < n_blocks) block_sums[bt + q] = uint32_t(run);  // fits: K < 2^32 checked below
+        for (int q = 0; q < kScanPer; ++q) {
+            stage[scan_pad(tid * kScanPer + q)] = uint32_t(run);  // totals below 2^32 are checked by the caller
             run += v[q];
         }
         __syncthreads();
-        if (threadIdx.x == 0) carry_s = carry + tot;
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const int idx = q * kScanWgThreads + tid;
+            if (b0 + idx < nb) sums[b0 + idx] = stage[scan_pad(idx)];
+        }
+        if (tid == 0) *carry_s = carry + tot;
         __syncthreads();
     }
+    return *carry_s;
+}
+
+// Partition-claim counters of the sort: one per radix pass.
+constexpr int kCounters = 8;
+
+// One workgroup: exclusive scan of the block sums, total pair count; also
+// clears the sort's histograms, partition counters and error flag.  With
+// vis_sums (depth-first path) it also scans the visible-entry counts and
+// writes their total to n_sorted[1] (0 if the pairs do not fit).
+__global__ __launch_bounds__(kScanWgThreads) void k_scan_blocks(uint32_t* __restrict__ block_sums, int64_t n_blocks,
+                                                     int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                     uint32_t* __restrict__ n_sorted, uint32_t* __restrict__ hist,
+                                                     uint32_t* __restrict__ counters, uint32_t* __restrict__ err,
+                                                     uint32_t* __restrict__ vis_sums) {
+    __shared__ uint32_t lds4[kScanWgThreads / 64];
+    __shared__ uint64_t carry_s;
+    __shared__ uint32_t stage[kScanStage];
+    for (int k = threadIdx.x; k < 8 * 256; k += kScanWgThreads) hist[k] = 0;
+    if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *err = 0;
+    const uint64_t K = scan_sums_1wg(block_sums, n_blocks, lds4, &carry_s, stage);
+    const bool fits = int64_t(K) <= capacity;
+    uint64_t nv = 0;
+    if (vis_sums) nv = scan_sums_1wg(vis_sums, n_blocks, lds4, &carry_s, stage);
     if (threadIdx.x == 0) {
-        const int64_t K = int64_t(carry_s);
-        *n_pairs = K;
-        *n_sorted = (K <= capacity) ? uint32_t(K) : 0u;
+        *n_pairs = int64_t(K);
+        n_sorted[0] = fits ? uint32_t(K) : 0u;
+        n_sorted[1] = fits ? uint32_t(nv) : 0u;
     }
 }
 
 __device__ __forceinline__ int64_t fdiv16(int64_t a) { return a >= 0 ? a / 16 : -((-a + 15) / 16); }
+
+// Integer tile rectangle of a visible entry: first global tile, width in
+// tiles, and the camera's tiles per row.
+__device__ __forceinline__ void vis_rect(const EmitIn& E, int c, int64_t j, uint32_t* bt, uint32_t* wd,
+                                         uint32_t* tx) {
+    const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
+    const int64_t r = E.radius[c][j];
+    const int64_t xi = int64_t(floorf(fminf(fmaxf(q0.x, -1073741824.f), 1073741824.f)));
+    const int64_t yi = int64_t(floorf(fminf(fmaxf(q0.y, -1073741824.f), 1073741824.f)));
+    const int64_t TX = E.TX[c], TY = E.TY[c];
+    const int64_t x0 = min<int64_t>(max<int64_t>(fdiv16(xi - r), 0), TX);
+    const int64_t x1 = min<int64_t>(max<int64_t>(fdiv16(xi + r) + 1, 0), TX);
+    const int64_t y0 = min<int64_t>(max<int64_t>(fdiv16(yi - r), 0), TY);
+    *bt = uint32_t(E.tile_off[c]) + uint32_t(y0 * TX + x0);
+    *wd = uint32_t(max<int64_t>(x1 - x0, 1));
+    *tx = uint32_t(TX);
+}
+
 
 // Emission: per 256 entries a block-wide scan of the tile counts gives the
 // block a contiguous run of output pairs; all 256 threads then write
@@ -135,6 +210,7 @@ struct EmitLds {
 // Adds one key's digits to the per-pass LDS histograms; a digit shared by the
 // whole wavefront is added once.
 __device__ __forceinline__ void hist_add(uint32_t (*h)[256], uint64_t key, bool valid, int passes, int shift0) {
+    if (passes == 0) return;
     const uint64_t vm = ballot(valid);
     if (!vm) return;
     const int first = __ffsll((unsigned long long)vm) - 1;
@@ -146,6 +222,36 @@ __device__ __forceinline__ void hist_add(uint32_t (*h)[256], uint64_t key, bool 
         } else if (valid) {
             atomicAdd(&h[p][d], 1u);
         }
+    }
+}
+
+// Writes a block's `tot` pairs at keys/vals[run ...]: output o belongs to the
+// last entry l with start[l] <= o (zero-count entries share the next start);
+// its tile is the (o - start[l])-th of the entry's rectangle in row-major
+// order.  The whole block iterates together (the histogram ballots).
+__device__ __forceinline__ void emit_block_pairs(const EmitLds& L, uint32_t (*h)[256], uint32_t tot, uint32_t run,
+                                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, int passes,
+                                                 int shift0) {
+    const uint32_t span = (tot + kScanThreads - 1) / kScanThreads * kScanThreads;
+    for (uint32_t o = threadIdx.x; o < span; o += kScanThreads) {
+        const bool valid = o < tot;
+        uint64_t key = 0;
+        if (valid) {
+            uint32_t lo = 0, hi = kScanThreads;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (L.start[mid] <= o) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t local = o - L.start[lo];
+            const uint32_t ww = L.w[lo];
+            const uint32_t dy = local / ww, dx = local - dy * ww;
+            const uint64_t tile = uint64_t(L.base_tile[lo] + dy * L.tx[lo] + dx);
+            key = (tile << 32) | uint64_t(L.dbits[lo]);
+            keys[run + o] = key;
+            vals[run + o] = L.j[lo];
+        }
+        hist_add(h, key, valid, passes, shift0);
     }
 }
 
@@ -184,17 +290,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
         const uint32_t ex = block_excl_scan(cnt, lds4, &tot);
         uint32_t bt = 0, wd = 1, tx = 0, db = 0;
         if (cnt > 0) {
-            const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
-            const int64_t r = E.radius[c][j];
-            const int64_t xi = int64_t(floorf(fminf(fmaxf(q0.x, -1073741824.f), 1073741824.f)));
-            const int64_t yi = int64_t(floorf(fminf(fmaxf(q0.y, -1073741824.f), 1073741824.f)));
-            const int64_t TX = E.TX[c], TY = E.TY[c];
-            const int64_t x0 = min<int64_t>(max<int64_t>(fdiv16(xi - r), 0), TX);
-            const int64_t x1 = min<int64_t>(max<int64_t>(fdiv16(xi + r) + 1, 0), TX);
-            const int64_t y0 = min<int64_t>(max<int64_t>(fdiv16(yi - r), 0), TY);
-            bt = uint32_t(E.tile_off[c]) + uint32_t(y0 * TX + x0);
-            wd = uint32_t(max<int64_t>(x1 - x0, 1));
-            tx = uint32_t(TX);
+            vis_rect(E, c, j, &bt, &wd, &tx);
             db = __float_as_uint(E.depth[c][j]);
         }
         L.start[tid] = ex;
@@ -205,28 +301,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
         L.j[tid] = uint32_t(j);
         if (tid == 0) L.start[kScanThreads] = tot;
         __syncthreads();
-        const uint32_t span = (tot + kScanThreads - 1) / kScanThreads * kScanThreads;
-        for (uint32_t o = tid; o < span; o += kScanThreads) {  // whole block iterates together
-            const bool valid = o < tot;
-            uint64_t key = 0;
-            if (valid) {
-                // last entry l with start[l] <= o (zero-count entries share the next start)
-                uint32_t lo = 0, hi = kScanThreads;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (L.start[mid] <= o) lo = mid;
-                    else hi = mid;
-                }
-                const uint32_t local = o - L.start[lo];
-                const uint32_t ww = L.w[lo];
-                const uint32_t dy = local / ww, dx = local - dy * ww;
-                const uint64_t tile = uint64_t(L.base_tile[lo] + dy * L.tx[lo] + dx);
-                key = (tile << 32) | uint64_t(L.dbits[lo]);
-                keys[run + o] = key;
-                vals[run + o] = L.j[lo];
-            }
-            hist_add(h, key, valid, passes, shift0);
-        }
+        emit_block_pairs(L, h, tot, run, keys, vals, passes, shift0);
         __syncthreads();
         run += tot;
     }
@@ -234,6 +309,213 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
         const uint32_t v = h[p][tid];
         if (v) atomicAdd(&hist[p * 256 + tid], v);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Depth-first binning (long tile lists): the visible entries are compacted
+// and sorted by depth once (four 8-bit passes over 32-bit keys), the pairs are
+// then emitted in that order, so that stable passes over the tile bits alone
+// leave every tile's list in (depth, entry) order - the order of the stable
+// sort by the full (tile | depth) key.  Per pair this moves the 12-byte pairs
+// through the tile passes only; the depth passes move 8 bytes per visible
+// entry.
+// ---------------------------------------------------------------------------
+// Visible-entry record: entry index within its camera, first global tile of
+// the rectangle, rectangle width | camera tiles-per-row << 16, tile count.
+// Compaction of the visible entries (ascending entry order): depth bits and
+// rank for the depth sort, and the entry's record; clears the first depth
+// pass's look-back status.
+__global__ __launch_bounds__(256) void k_vis_compact(EmitIn E, int64_t n_total, const uint32_t* __restrict__ vis_offs,
+                                                     const uint32_t* __restrict__ n_sorted,
+                                                     uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
+                                                     uint4* __restrict__ vrec, int part,
+                                                     uint32_t* __restrict__ status0) {
+    __shared__ uint32_t lds4[4];
+    const uint32_t n_v = n_sorted[1];
+    if (n_v == 0) return;  // nothing visible, or the pairs do not fit
+    const uint32_t tid = threadIdx.x;
+    {
+        const uint32_t n_parts = (n_v + uint32_t(part) - 1) / uint32_t(part);
+        for (uint32_t k = blockIdx.x * 256 + tid; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
+    }
+    const int64_t e = int64_t(blockIdx.x) * kScanItems + tid;
+    int c = 0;
+    int64_t j = 0;
+    uint32_t cnt = 0;
+    if (e < n_total) {
+        c = int(e / E.n_in);
+        j = e - int64_t(c) * E.n_in;
+        cnt = E.tiles[c][j];
+    }
+    const bool vis = cnt > 0;
+    uint32_t tot;
+    const uint32_t o = vis_offs[blockIdx.x] + block_excl_scan(vis ? 1u : 0u, lds4, &tot);
+    if (vis) {
+        uint32_t bt, wd, tx;
+        vis_rect(E, c, j, &bt, &wd, &tx);
+        dkey[o] = __float_as_uint(E.depth[c][j]);
+        dval[o] = o;
+        vrec[o] = make_uint4(uint32_t(j), bt, wd | (tx << 16), cnt);
+    }
+}
+
+// Digit histograms of the depth-first path in one read of the compacted
+// visible entries (ascending entry order, so a workgroup's rectangles are
+// close together on screen): the four depth-digit histograms, and for every
+// tile pass q the histogram of digit q of the tiles of every rectangle.  A
+// rectangle row is a run of at most 255 consecutive tile ids, so digit 0 of
+// the run is a (cyclic) range of digits, added through a difference array,
+// and every higher digit takes at most two values along the run.  Few
+// workgroups, so that few global atomics meet the same addresses.
+constexpr int kBinHistGroups = 1024;
+
+__global__ __launch_bounds__(256) void k_bin_hist(const uint32_t* __restrict__ dkey, const uint4* __restrict__ vrec,
+                                                  const uint32_t* __restrict__ n_sorted, int tile_passes,
+                                                  uint32_t* __restrict__ hist) {
+    __shared__ uint32_t hd[4][256];
+    __shared__ int32_t dlo[257];
+    __shared__ uint32_t ht[4][256];
+    __shared__ uint32_t uni;
+    const uint32_t tid = threadIdx.x;
+    for (int k = tid; k < 4 * 256; k += 256) {
+        (&hd[0][0])[k] = 0;
+        (&ht[0][0])[k] = 0;
+    }
+    for (int k = tid; k < 257; k += 256) dlo[k] = 0;
+    if (tid == 0) uni = 0;
+    __syncthreads();
+    const uint32_t n_v = n_sorted[1];
+    constexpr int kU = 4;  // items per thread per round, loaded before use
+    const uint32_t stride = gridDim.x * 256;
+    const uint32_t span = (n_v + 255) / 256 * 256;  // whole wavefronts iterate together
+    for (uint32_t i0 = blockIdx.x * 256 + tid; i0 < span; i0 += kU * stride) {
+    uint32_t dbs[kU];
+    uint4 rs[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const uint32_t i = i0 + u * stride;
+        dbs[u] = i < n_v ? dkey[i] : 0u;
+        rs[u] = i < n_v ? vrec[i] : make_uint4(0u, 0u, 1u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const uint32_t i = i0 + u * stride;
+        const bool valid = i < n_v;
+        const uint32_t db = dbs[u];
+        const uint4 r = rs[u];
+        hist_add(hd, uint64_t(db), valid, 4, 0);
+        if (!valid || tile_passes == 0) continue;
+        const uint32_t w = r.z & 0xffffu, tx = r.z >> 16;
+        const uint32_t rows = r.w / w;
+        for (uint32_t dy = 0; dy < rows; ++dy) {
+            const uint32_t s0 = r.y + dy * tx;  // first tile of the row
+            const uint32_t a = s0 & 255u;
+            // digit 0: every digit w / 256 times, then the cyclic range
+            // [a, a + w % 256)
+            const uint32_t rem = w & 255u;
+            if (w >= 256u) atomicAdd(&uni, w >> 8);
+            if (rem) {
+                atomicAdd(&dlo[a], 1);
+                if (a + rem <= 256u) {
+                    atomicAdd(&dlo[a + rem], -1);
+                } else {
+                    atomicAdd(&dlo[256], -1);
+                    atomicAdd(&dlo[0], 1);
+                    atomicAdd(&dlo[a + rem - 256u], -1);
+                }
+            }
+            // digit q >= 1: constant over runs of 256^q consecutive tiles
+            for (int q = 1; q < tile_passes; ++q) {
+                const uint32_t end = s0 + w;
+                for (uint32_t t = s0; t < end;) {
+                    const uint32_t next = min(end, ((t >> (8 * q)) + 1u) << (8 * q));
+                    atomicAdd(&ht[q][(t >> (8 * q)) & 255u], next - t);
+                    t = next;
+                }
+            }
+        }
+    }
+    }
+    __syncthreads();
+    if (tile_passes > 0 && tid == 0) {
+        int32_t run = 0;
+        for (int d = 0; d < 256; ++d) {
+            run += dlo[d];
+            ht[0][d] = uint32_t(run) + uni;
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t v = hd[p][tid];
+        if (v) atomicAdd(&hist[p * 256 + tid], v);
+    }
+    for (int q = 0; q < tile_passes; ++q) {
+        const uint32_t v = ht[q][tid];
+        if (v) atomicAdd(&hist[(4 + q) * 256 + tid], v);
+    }
+}
+
+// Per block of 256 depth-sorted visible entries: their pair count.
+__global__ __launch_bounds__(256) void k_emit_reduce(const uint4* __restrict__ vrec, const uint32_t* __restrict__ dval,
+                                                     const uint32_t* __restrict__ n_sorted,
+                                                     uint32_t* __restrict__ sums) {
+    __shared__ uint32_t lds4[4];
+    const uint32_t n_v = n_sorted[1];
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x * 256u >= n_v) return;  // uniform per block
+    const uint32_t cnt = i < n_v ? vrec[dval[i]].w : 0u;
+    uint32_t tot;
+    block_excl_scan(cnt, lds4, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanWgThreads) void k_scan_sums(uint32_t* __restrict__ sums,
+                                                              const uint32_t* __restrict__ n_sorted) {
+    __shared__ uint32_t lds_w[kScanWgThreads / 64];
+    __shared__ uint64_t carry_s;
+    __shared__ uint32_t stage[kScanStage];
+    const int64_t nb = (int64_t(n_sorted[1]) + 255) / 256;
+    scan_sums_1wg(sums, nb, lds_w, &carry_s, stage);
+}
+
+// Emission in depth order: per block of 256 depth-sorted visible entries, the
+// block's pairs are written as one contiguous run, spread over all threads;
+// clears the first tile pass's status.  (The tile-digit histograms come from
+// k_bin_hist.)
+__global__ __launch_bounds__(256) void k_emit_sorted(const uint4* __restrict__ vrec, const uint32_t* __restrict__ dkey,
+                                                     const uint32_t* __restrict__ dval,
+                                                     const uint32_t* __restrict__ n_sorted,
+                                                     const uint32_t* __restrict__ offs, uint64_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals, int part,
+                                                     uint32_t* __restrict__ status0) {
+    __shared__ uint32_t lds4[4];
+    __shared__ EmitLds L;
+    const uint32_t n_s = n_sorted[0], n_v = n_sorted[1];
+    if (n_v == 0) return;
+    const uint32_t tid = threadIdx.x;
+    {
+        const uint32_t n_parts = (n_s + uint32_t(part) - 1) / uint32_t(part);
+        for (uint32_t k = blockIdx.x * 256 + tid; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
+    }
+    if (blockIdx.x * 256u >= n_v) return;  // uniform per block
+    const uint32_t i = blockIdx.x * 256 + tid;
+    uint4 r = make_uint4(0u, 0u, 1u, 0u);
+    uint32_t db = 0;
+    if (i < n_v) {
+        r = vrec[dval[i]];
+        db = dkey[i];
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(r.w, lds4, &tot);
+    L.start[tid] = ex;
+    L.base_tile[tid] = r.y;
+    L.w[tid] = r.z & 0xffffu;
+    L.tx[tid] = r.z >> 16;
+    L.dbits[tid] = db;
+    L.j[tid] = r.x;
+    if (tid == 0) L.start[kScanThreads] = tot;
+    __syncthreads();
+    emit_block_pairs(L, nullptr, tot, offs[blockIdx.x], keys, vals, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -247,37 +529,11 @@ constexpr int kIptLarge = 15;
 constexpr int kIptSmall = 5;
 constexpr int64_t kSmallSortCapacity = 2 << 20;
 constexpr int kPartMin = kSortThreads * kIptSmall;
-constexpr uint32_t kFlagAgg = 1u << 30;
-constexpr uint32_t kFlagInc = 2u << 30;
-constexpr uint32_t kValMask = (1u << 30) - 1u;
-constexpr uint32_t kSpinLimit = 1u << 24;
 constexpr int kLookWin = 8;  // predecessors read per look-back round trip
 
-// Digit histograms of the depth passes (bits 0..31) of the full-key path in
-// one read of the keys (the emission builds the tile-digit ones): per
-// workgroup in LDS, then one global add per non-empty bin.
-__global__ __launch_bounds__(256) void k_sort_hist(const uint64_t* __restrict__ keys,
-                                                   const uint32_t* __restrict__ n_sorted, int passes,
-                                                   uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[8][256];
-    for (int k = threadIdx.x; k < 8 * 256; k += 256) (&h[0][0])[k] = 0;
-    __syncthreads();
-    const uint32_t n = *n_sorted;
-    const uint32_t span = (n + 255) / 256 * 256;  // whole wavefronts iterate together
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < span; i += gridDim.x * 256) {
-        const bool valid = i < n;
-        hist_add(h, valid ? keys[i] : 0ull, valid, passes, 0);
-    }
-    __syncthreads();
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t v = h[p][threadIdx.x];
-        if (v) atomicAdd(&hist[p * 256 + threadIdx.x], v);
-    }
-}
-
-template <int IPT>
+template <int IPT, typename KeyT>
 struct SortLds {
-    uint64_t keys[kSortThreads * IPT];
+    KeyT keys[kSortThreads * IPT];
     uint32_t vals[kSortThreads * IPT];
     uint32_t wcnt[kWaves][256];
     uint32_t bin_start[256];
@@ -290,10 +546,11 @@ struct SortLds {
 // At least three wavefronts per SIMD (the 3,840-key instance would take
 // 170 VGPRs, two wavefronts; 168 and three match its LDS limit of three
 // workgroups per compute unit): 142 -> 121 us per pass at 13.5M pairs.
-template <int IPT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_sort_pass(const uint64_t* __restrict__ keys_in,
+// KeyT: uint64_t (pairs) or uint32_t (depth keys of the depth-first path).
+template <int IPT, typename KeyT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_sort_pass(const KeyT* __restrict__ keys_in,
                                                    const uint32_t* __restrict__ vals_in,
-                                                   uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                   KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                    const uint32_t* __restrict__ n_sorted,
                                                    const uint32_t* __restrict__ hist_pass,
                                                    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
@@ -301,7 +558,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                                    int shift) {
     constexpr int kSortPerThread = IPT;
     constexpr int kPart = kSortThreads * IPT;
-    __shared__ SortLds<IPT> L;
+    __shared__ SortLds<IPT, KeyT> L;
     const uint32_t n = *n_sorted;
     const uint32_t n_parts = (n + kPart - 1) / kPart;
     const int tid = threadIdx.x;
@@ -345,14 +602,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 
         // 1. load (wave-striped) and rank within the wavefront, stably
         const uint32_t wbase = part * kPart + uint32_t(w) * (kSortPerThread * 64);
-        uint64_t k_[kSortPerThread];
+        KeyT k_[kSortPerThread];
         uint32_t v_[kSortPerThread];
         uint32_t rank_[kSortPerThread];
 #pragma unroll
         for (int it = 0; it < kSortPerThread; ++it) {
             const uint32_t idx = wbase + uint32_t(it) * 64 + lane;
             const bool valid = idx < n;
-            k_[it] = valid ? keys_in[idx] : ~0ull;
+            k_[it] = valid ? keys_in[idx] : ~KeyT(0);
             v_[it] = valid ? vals_in[idx] : 0u;
             const uint32_t d = uint32_t(k_[it] >> shift) & 255u;
             uint64_t peers = ballot(valid);
@@ -448,7 +705,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         // 5. coalesced write-out
         const uint32_t cnt = min<uint32_t>(kPart, n - part * kPart);
         for (uint32_t i = tid; i < cnt; i += 256) {
-            const uint64_t key = L.keys[i];
+            const KeyT key = L.keys[i];
             const uint32_t d = uint32_t(key >> shift) & 255u;
             const uint32_t g = L.gbase[d] + i;
             if (g < n) {  // always true unless a look-back wait timed out
@@ -704,6 +961,9 @@ __global__ __launch_bounds__(64 * kSegWaves) void k_seg_sort_long(uint64_t* keys
 
 struct SortWs {
     uint32_t* block_sums;
+    uint32_t* vis_sums;   // depth-first path only
+    uint32_t* emit_sums;  // depth-first path only
+    uint4* vrec;          // depth-first path only
     uint32_t* n_sorted;
     uint32_t* hist;
     uint32_t* counters;
@@ -715,12 +975,23 @@ struct SortWs {
     size_t bytes;
 };
 
+// Short tile lists (pair capacity per tile up to kSegAvgMax): radix passes
+// over the tile bits, then a per-tile depth sort.  Longer lists: the
+// depth-first path.
+static bool per_tile_path(int64_t capacity, int64_t n_tiles) {
+    return capacity <= kSegAvgMax * std::max<int64_t>(n_tiles, 1);
+}
+
 static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity, int64_t n_tiles) {
     Carve cv(ws);
     SortWs s;
     const int64_t nb = (n_total + kScanItems - 1) / kScanItems + 1;
     const int64_t np = (capacity + kPartMin - 1) / kPartMin + 1;
+    const bool depth_first = !per_tile_path(capacity, n_tiles);
     s.block_sums = cv.take<uint32_t>(size_t(nb));
+    s.vis_sums = depth_first ? cv.take<uint32_t>(size_t(nb)) : nullptr;
+    s.emit_sums = depth_first ? cv.take<uint32_t>(size_t(nb)) : nullptr;
+    s.vrec = depth_first ? cv.take<uint4>(size_t(n_total > 0 ? n_total : 1)) : nullptr;
     s.n_sorted = cv.take<uint32_t>(4);
     s.hist = cv.take<uint32_t>(8 * 256);
     s.counters = cv.take<uint32_t>(8);
@@ -734,12 +1005,181 @@ static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity, int64_t n_
     return s;
 }
 
+// ---------------------------------------------------------------------------
+// LOD labels by multi-resolution voxelisation (Sec. 3.3): cubes of edge
+// delta0 / 2^l, one representative per occupied cube - its first point in
+// (Z-order code of the finest cell, index).  One stable radix sort of the
+// 63-bit Z-order codes puts every cube's points in one run at every level
+// (the level-l cube of a point is its code shifted right by 3 (K-1-l)), so
+// a point's label follows from its predecessor alone: the highest bit in
+// which the two codes differ names the coarsest level at which a new cube
+// starts.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// Finest cell coordinate of one axis: floor((m - o) * s) in float32 (a
+// subtraction and a product, each rounded once), NaN -> 0, clamped to
+// [0, 2^21 - 1].
+__device__ __forceinline__ uint32_t fine_cell(float m, float o, float sc) {
+    const float d = __fsub_rn(m, o);
+    const float q = floorf(__fmul_rn(d, sc));
+    if (q != q) return 0u;
+    return uint32_t(fminf(fmaxf(q, 0.f), 2097151.f));
+}
+
+__global__ void k_voxel_init(uint32_t* __restrict__ hist, uint32_t* __restrict__ counters,
+                             uint32_t* __restrict__ err, uint32_t* __restrict__ n_sorted, uint32_t n) {
+    for (int k = threadIdx.x; k < 8 * 256; k += blockDim.x) hist[k] = 0;
+    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        *err = 0;
+        n_sorted[0] = n;
+        n_sorted[1] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_voxel_codes(const float* __restrict__ mean, int64_t n, float o0, float o1,
+                                                     float o2, float sc, uint64_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals, int part,
+                                                     uint32_t* __restrict__ hist, uint32_t* __restrict__ status0) {
+    __shared__ uint32_t h[8][256];
+    const uint32_t tid = threadIdx.x;
+    {
+        const uint32_t n_parts = uint32_t((n + part - 1) / part);
+        for (uint32_t k = blockIdx.x * 256 + tid; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
+    }
+    for (int k = tid; k < 8 * 256; k += 256) (&h[0][0])[k] = 0;
+    __syncthreads();
+    const int64_t span = (n + 255) / 256 * 256;  // whole wavefronts iterate together
+    for (int64_t i = int64_t(blockIdx.x) * 256 + tid; i < span; i += int64_t(gridDim.x) * 256) {
+        const bool valid = i < n;
+        uint64_t code = 0;
+        if (valid) {
+            const uint32_t cx = fine_cell(mean[i], o0, sc);
+            const uint32_t cy = fine_cell(mean[n + i], o1, sc);
+            const uint32_t cz = fine_cell(mean[2 * n + i], o2, sc);
+            code = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+            keys[i] = code;
+            vals[i] = uint32_t(i);
+        }
+        hist_add(h, code, valid, 8, 0);
+    }
+    __syncthreads();
+    for (int p = 0; p < 8; ++p) {
+        const uint32_t v = h[p][tid];
+        if (v) atomicAdd(&hist[p * 256 + tid], v);
+    }
+}
+
+// Label of the point at sorted position p from its predecessor's code; a
+// timed-out look-back wait of the sort writes 255 (no valid level).
+__global__ __launch_bounds__(256) void k_voxel_label(const uint64_t* __restrict__ keys,
+                                                     const uint32_t* __restrict__ vals, int64_t n, int n_levels,
+                                                     const uint32_t* __restrict__ err, uint8_t* __restrict__ lod) {
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= n) return;
+    int label = 0;
+    if (p > 0) {
+        const uint64_t x = keys[p] ^ keys[p - 1];
+        if (x == 0) {
+            label = n_levels - 1;
+        } else {
+            const int h = 63 - __clzll((long long)x);
+            label = max(0, n_levels - 1 - h / 3);
+        }
+    }
+    lod[vals[p]] = *err ? uint8_t(255) : uint8_t(label);
+}
+
+struct VoxWs {
+    uint64_t* keys[2];
+    uint32_t* vals[2];
+    uint32_t* status[2];
+    uint32_t* hist;
+    uint32_t* counters;
+    uint32_t* err;
+    uint32_t* n_sorted;
+    size_t bytes;
+};
+
+static VoxWs carve_vox(void* ws, int64_t n) {
+    Carve cv(ws);
+    VoxWs s;
+    const size_t m = size_t(n > 0 ? n : 1);
+    const int64_t np = (n + kPartMin - 1) / kPartMin + 1;
+    for (int b = 0; b < 2; ++b) {
+        s.keys[b] = cv.take<uint64_t>(m);
+        s.vals[b] = cv.take<uint32_t>(m);
+        s.status[b] = cv.take<uint32_t>(size_t(np) * 256);
+    }
+    s.hist = cv.take<uint32_t>(8 * 256);
+    s.counters = cv.take<uint32_t>(8);
+    s.err = cv.take<uint32_t>(4);
+    s.n_sorted = cv.take<uint32_t>(4);
+    s.bytes = cv.used();
+    return s;
+}
+
 }  // namespace gsmi
 
 using namespace gsmi;
 
 size_t ws_bin_sort(int64_t n_total, int64_t capacity, int64_t n_tiles) {
     return carve_sort(nullptr, n_total, capacity, n_tiles).bytes;
+}
+
+size_t ws_voxel_levels(int64_t n) { return carve_vox(nullptr, n).bytes; }
+
+extern "C" int gs_voxel_levels(const float* mean, int64_t n, const float* origin, float delta0, int32_t n_levels,
+                               uint8_t* lod, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_voxel_levels: need 0 <= n < 2^31");
+    if (n_levels < 1 || n_levels > 22) return fail(GS_ERR_INVALID_ARG, "gs_voxel_levels: n_levels in [1, 22]");
+    if (!origin || !std::isfinite(origin[0]) || !std::isfinite(origin[1]) || !std::isfinite(origin[2]))
+        return fail(GS_ERR_INVALID_ARG, "gs_voxel_levels: origin must be three finite floats");
+    if (!(delta0 > 0.f) || !std::isfinite(delta0))
+        return fail(GS_ERR_INVALID_ARG, "gs_voxel_levels: delta0 must be positive and finite");
+    if (n > 0 && (!mean || !lod)) return fail(GS_ERR_INVALID_ARG, "gs_voxel_levels: null mean or lod");
+    VoxWs V = carve_vox(ws, n);
+    if (!ws || ws_bytes < V.bytes || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_voxel_levels: workspace needs %zu bytes (256-aligned)", V.bytes);
+    if (n == 0) return GS_OK;
+    // cell scale 2^(K-1) / delta0, one float32 division (correctly rounded)
+    const float sc = float(1u << (n_levels - 1)) / delta0;
+    const bool small = n <= kSmallSortCapacity;
+    const int part = kSortThreads * (small ? kIptSmall : kIptLarge);
+    int grid = int(std::min<int64_t>((n + part - 1) / part, 256 * (small ? 6 : 3)));
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_voxel_init, dim3(1), dim3(256), 0, stream, V.hist, V.counters, V.err, V.n_sorted,
+                       uint32_t(n));
+    // few workgroups, so that the LDS histograms reach the global ones with
+    // few atomics
+    const int cb = int(std::min<int64_t>((n + 255) / 256, 256));
+    launch("voxel_codes", k_voxel_codes, dim3(cb), dim3(256), 0, stream, mean, n, origin[0], origin[1], origin[2], sc,
+           V.keys[0], V.vals[0], part, V.hist, V.status[0]);
+    for (int p = 0; p < 8; ++p) {
+        const int a = p & 1, b = a ^ 1;
+        uint32_t* st_next = p < 7 ? V.status[b] : nullptr;
+        if (small)
+            launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
+                   V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
+                   static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p);
+        else
+            launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
+                   V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
+                   static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p);
+    }
+    launch("voxel_label", k_voxel_label, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream,
+           static_cast<const uint64_t*>(V.keys[0]), static_cast<const uint32_t*>(V.vals[0]), n, int(n_levels),
+           static_cast<const uint32_t*>(V.err), lod);
+    return check_launch("gs_voxel_levels");
 }
 
 extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int n_cams, int64_t n_in,
@@ -775,68 +1215,118 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     E.n_cams = n_cams;
     E.n_in = n_in > 0 ? n_in : 1;
 
-    // Two orderings with the same result.  Short tile lists (capacity per
-    // tile up to kSegAvgMax): radix passes over the global tile id only (bits
-    // 32 and up), the depth order inside each tile from the per-tile sort.
-    // Long lists: radix passes over all 32 + tile bits, no per-tile sort.
+    // Two orderings with the same result (the stable sort by the full key).
+    // Short tile lists: radix passes over the global tile id only (bits 32
+    // and up), the depth order inside each tile from the per-tile sort.  Long
+    // lists: the depth-first path (visible entries sorted by depth, pairs
+    // emitted in that order, then the tile passes).
     int tile_bits = 0;
     while ((int64_t(1) << tile_bits) < total_tiles) ++tile_bits;
-    const bool per_tile = capacity <= kSegAvgMax * std::max<int64_t>(total_tiles, 1);
+    const bool per_tile = per_tile_path(capacity, total_tiles);
     const int tile_passes = (tile_bits + 7) / 8;
-    const int depth_passes = per_tile ? 0 : 4;
-    const int passes = tile_passes + depth_passes;
     if (tile_passes > 4) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
 
     const int64_t nb = (n_total + kScanItems - 1) / kScanItems;
     if (nb > 0)
-        launch("scan_reduce", k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, stream, S.block_sums, nb, n_pairs_dev, capacity,
-                       S.n_sorted, S.hist, S.counters, S.err);
+        launch("scan_reduce", k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total,
+               S.block_sums, per_tile ? nullptr : S.vis_sums);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanWgThreads), 0, stream, S.block_sums, nb, n_pairs_dev, capacity,
+                       S.n_sorted, S.hist, S.counters, S.err, per_tile ? nullptr : S.vis_sums);
     if ((rc = check_launch("gs_bin_sort scan"))) return rc;
     if (capacity == 0) {
         rc = fill_u32(tile_ranges, 0u, size_t(2 * total_tiles), stream);
         return rc;
     }
-    // Emission target: each radix pass (and the per-tile sort) moves the pairs
-    // to the other buffer, and the last step writes keys/vals; the per-tile
-    // sort reads the workspace copy.
     uint64_t* kb[2] = {keys, S.keys_alt};
     uint32_t* vb[2] = {vals, S.vals_alt};
-    int cur = (passes + (per_tile ? 1 : 0)) & 1;
     const bool small = capacity <= kSmallSortCapacity;
     const int part = kSortThreads * (small ? kIptSmall : kIptLarge);
     const int64_t max_parts = (capacity + part - 1) / part;
-    if (nb > 0)
-        launch("emit", k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
-               S.n_sorted, kb[cur], vb[cur], tile_passes, 32, part, S.hist + depth_passes * 256, S.status[0]);
-    if (depth_passes > 0) {
-        const int hb = int(std::min<int64_t>(1024, std::max<int64_t>(1, (capacity + 4095) / 4096)));
-        launch("sort_hist", k_sort_hist, dim3(unsigned(hb)), dim3(256), 0, stream,
-               static_cast<const uint64_t*>(kb[cur]), static_cast<const uint32_t*>(S.n_sorted), depth_passes,
-               S.hist);
-    }
     int grid = int(std::min<int64_t>(max_parts, 256 * (small ? 6 : 3)));
     if (grid < 1) grid = 1;
-    for (int p = 0; p < passes; ++p) {
-        const int nxt = cur ^ 1;
-        uint32_t* st_next = (p + 1 < passes) ? S.status[(p + 1) & 1] : nullptr;
+    auto tile_pass = [&](int q, int cur, int hist_slot, int counter, bool last) {
+        uint32_t* st_next = last ? nullptr : S.status[(q + 1) & 1];
         if (small)
-            launch("sort_pass", k_sort_pass<kIptSmall>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
-                   kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
-                   8 * (p + (per_tile ? 4 : 0)));
+            launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
+                   vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
+                   S.counters + counter, S.err, 32 + 8 * q);
         else
-            launch("sort_pass", k_sort_pass<kIptLarge>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur], vb[cur],
-                   kb[nxt], vb[nxt], S.n_sorted, S.hist + p * 256, S.status[p & 1], st_next, S.counters + p, S.err,
-                   8 * (p + (per_tile ? 4 : 0)));
-        cur = nxt;
+            launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
+                   vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
+                   S.counters + counter, S.err, 32 + 8 * q);
+    };
+
+    if (!per_tile) {
+        // Depth-first path.  The emission writes into buffer z and the tile
+        // passes ping-pong from there, ending in the caller's keys/vals; the
+        // depth sort runs in the other buffer x (its 32-bit keys in the
+        // first half of the key array), ending where it started.
+        const int z = tile_passes & 1, x = z ^ 1;
+        uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(kb[x]), reinterpret_cast<uint32_t*>(kb[z])};
+        uint32_t* dv[2] = {vb[x], vb[z]};
+        const bool small_d = n_total <= kSmallSortCapacity;
+        const int part_d = kSortThreads * (small_d ? kIptSmall : kIptLarge);
+        int grid_d = int(std::min<int64_t>((n_total + part_d - 1) / part_d, 256 * (small_d ? 6 : 3)));
+        if (grid_d < 1) grid_d = 1;
+        if (nb > 0) {
+            launch("vis_compact", k_vis_compact, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total,
+                   static_cast<const uint32_t*>(S.vis_sums), static_cast<const uint32_t*>(S.n_sorted), dk[0], dv[0],
+                   S.vrec, part_d, S.status[0]);
+            const int64_t hg = std::min<int64_t>(kBinHistGroups, nb);
+            launch("bin_hist", k_bin_hist, dim3(unsigned(hg)), dim3(256), 0, stream,
+                   static_cast<const uint32_t*>(dk[0]), static_cast<const uint4*>(S.vrec),
+                   static_cast<const uint32_t*>(S.n_sorted), tile_passes, S.hist);
+        }
+        for (int p = 0; p < 4; ++p) {
+            uint32_t* st_next = p < 3 ? S.status[(p + 1) & 1] : nullptr;
+            const int a = p & 1, b = a ^ 1;
+            if (small_d)
+                launch("sort_pass", k_sort_pass<kIptSmall, uint32_t>, dim3(grid_d), dim3(kSortThreads), 0, stream,
+                       dk[a], dv[a], dk[b], dv[b], S.n_sorted + 1, S.hist + p * 256, S.status[p & 1], st_next,
+                       S.counters + p, S.err, 8 * p);
+            else
+                launch("sort_pass", k_sort_pass<kIptLarge, uint32_t>, dim3(grid_d), dim3(kSortThreads), 0, stream,
+                       dk[a], dv[a], dk[b], dv[b], S.n_sorted + 1, S.hist + p * 256, S.status[p & 1], st_next,
+                       S.counters + p, S.err, 8 * p);
+        }
+        if (nb > 0) {
+            launch("emit_reduce", k_emit_reduce, dim3(unsigned(nb)), dim3(256), 0, stream,
+                   static_cast<const uint4*>(S.vrec), static_cast<const uint32_t*>(dv[0]),
+                   static_cast<const uint32_t*>(S.n_sorted), S.emit_sums);
+            hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanWgThreads), 0, stream, S.emit_sums,
+                               static_cast<const uint32_t*>(S.n_sorted));
+            launch("emit", k_emit_sorted, dim3(unsigned(nb)), dim3(256), 0, stream, static_cast<const uint4*>(S.vrec),
+                   static_cast<const uint32_t*>(dk[0]), static_cast<const uint32_t*>(dv[0]),
+                   static_cast<const uint32_t*>(S.n_sorted), static_cast<const uint32_t*>(S.emit_sums), kb[z], vb[z],
+                   part, S.status[0]);
+        }
+        int cur = z;
+        for (int q = 0; q < tile_passes; ++q) {
+            tile_pass(q, cur, 4 + q, 4 + q, q + 1 == tile_passes);
+            cur ^= 1;
+        }
+        if ((rc = check_launch("gs_bin_sort sort"))) return rc;
+        launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream,
+               static_cast<const uint64_t*>(kb[0]), S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err,
+               n_pairs_dev);
+        return check_launch("gs_bin_sort ranges");
+    }
+
+    // Per-tile path: each tile pass moves the pairs to the other buffer and
+    // the per-tile sort writes the caller's keys/vals from the workspace copy.
+    int cur = (tile_passes + 1) & 1;
+    if (nb > 0)
+        launch("emit", k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
+               S.n_sorted, kb[cur], vb[cur], tile_passes, 32, part, S.hist, S.status[0]);
+    for (int q = 0; q < tile_passes; ++q) {
+        tile_pass(q, cur, q, q, q + 1 == tile_passes);
+        cur ^= 1;
     }
     if ((rc = check_launch("gs_bin_sort sort"))) return rc;
-    // per-tile path: cur == 1, the tile-ordered pairs are in the workspace
-    // copy; full-key path: cur == 0, the sorted pairs are in keys/vals
+    // cur == 1: the tile-ordered pairs are in the workspace copy
     launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream,
            static_cast<const uint64_t*>(kb[cur]), S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err, n_pairs_dev);
     if ((rc = check_launch("gs_bin_sort ranges"))) return rc;
-    if (!per_tile) return GS_OK;
     // counters[7] (cleared by the scan) counts the long segments
     uint32_t* long_count = S.counters + 7;
     launch("seg_sort", k_seg_sort, dim3(unsigned((total_tiles + 3) / 4)), dim3(256), 0, stream,

@@ -260,6 +260,8 @@ size_t ws_simplify(int64_t n);
 size_t ws_photo(int32_t W, int32_t H);
 size_t ws_scale_reg();
 size_t ws_project(int64_t n_in);
+size_t ws_voxel_levels(int64_t n);
+size_t ws_spawn_gate(int64_t n);
 
 extern "C" size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t n_tiles, int n_cams) {
     if (n < 0) n = 0;
@@ -275,6 +277,8 @@ extern "C" size_t gs_workspace_size(int op, int64_t n, int64_t n_pairs, int64_t 
         case GS_OP_PHOTO_LOSS: return ws_photo(int32_t(n / 65536), int32_t(n % 65536));
         case GS_OP_SCALE_REG: return ws_scale_reg();
         case GS_OP_PROJECT: return ws_project(n);
+        case GS_OP_VOXEL_LEVELS: return ws_voxel_levels(n);
+        case GS_OP_SPAWN_GATE: return ws_spawn_gate(n);
         default: return 0;
     }
 }

@@ -836,3 +836,114 @@ extern "C" int gs_compact(const void* const* src, void* const* dst, const int32_
     hipLaunchKernelGGL(k_compact_arrays, dim3(unsigned(nb)), dim3(256), 0, stream, A, keep_bits, n, n_keep, cnt);
     return check_launch("gs_compact");
 }
+
+// ---------------------------------------------------------------------------
+// Spawn gate (Sec. 3.2 "Spawn gate"; veto equation of Appendix E): within
+// each candidate set the ceil(rho |C|) candidates of lowest predicted
+// survival are vetoed (ties by index, the lower vetoed first), the survivors
+// are instantiated with the inherited level (clone: the parent's, split: one
+// finer, clamped at K-1).
+// ---------------------------------------------------------------------------
+namespace gsmi {
+
+__global__ __launch_bounds__(256) void k_spawn_emit(const int32_t* __restrict__ parent, const uint32_t* __restrict__ keep,
+                                                    int64_t n, const uint8_t* __restrict__ lod, int split, int n_levels,
+                                                    const uint32_t* __restrict__ offs, int64_t out_base,
+                                                    int32_t* __restrict__ child_parent, uint8_t* __restrict__ child_lod,
+                                                    uint8_t* __restrict__ child_split) {
+    __shared__ uint32_t w4[4];
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    const bool k = i < n && bit_of(keep, i);
+    uint32_t tot;
+    const uint32_t r = block_rank(k, w4, &tot);
+    if (!k) return;
+    const int64_t o = out_base + offs[blockIdx.x] + r;
+    const int32_t pj = parent[i];
+    child_parent[o] = pj;
+    child_lod[o] = uint8_t(min(int(lod[pj]) + split, n_levels - 1));
+    child_split[o] = uint8_t(split);
+}
+
+// Stand-in survival score: the parent's opacity.
+__global__ __launch_bounds__(256) void k_spawn_stub(const float* __restrict__ opacity_logit,
+                                                    const int32_t* __restrict__ parent, int64_t n,
+                                                    float* __restrict__ p) {
+    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    if (i >= n) return;
+    p[i] = 1.f / (1.f + expf(-opacity_logit[parent[i]]));
+}
+
+}  // namespace gsmi
+
+static int64_t veto_count(int64_t n, double rho) {
+    const double v = std::ceil(rho * double(n));
+    return std::min<int64_t>(n, std::max<int64_t>(0, int64_t(v)));
+}
+
+size_t ws_spawn_gate(int64_t n) {
+    Carve cv(nullptr);
+    carve_sel(cv, n);
+    cv.take<uint32_t>(size_t((n + 31) / 32 + 1));
+    cv.take<uint32_t>(size_t((n + kBlk - 1) / kBlk + 1));
+    return cv.used();
+}
+
+extern "C" int gs_spawn_gate(const uint8_t* lod, const int32_t* clone_parent, const float* p_clone, int64_t n_clone,
+                             const int32_t* split_parent, const float* p_split, int64_t n_split, double rho,
+                             int32_t n_levels, int32_t* child_parent, uint8_t* child_lod, uint8_t* child_split,
+                             int64_t* n_children, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n_clone < 0 || n_split < 0 || n_clone >= (int64_t(1) << 31) || n_split >= (int64_t(1) << 31))
+        return fail(GS_ERR_INVALID_ARG, "gs_spawn_gate: candidate counts must be in [0, 2^31)");
+    if (!(rho >= 0.0 && rho <= 1.0)) return fail(GS_ERR_INVALID_ARG, "gs_spawn_gate: rho must be in [0, 1]");
+    if (n_levels < 1 || n_levels > 255) return fail(GS_ERR_INVALID_ARG, "gs_spawn_gate: n_levels in [1, 255]");
+    if (!n_children) return fail(GS_ERR_INVALID_ARG, "gs_spawn_gate: null n_children");
+    if ((n_clone > 0 && (!clone_parent || !p_clone)) || (n_split > 0 && (!split_parent || !p_split)))
+        return fail(GS_ERR_INVALID_ARG, "gs_spawn_gate: null candidate array");
+    const int64_t v_c = veto_count(n_clone, rho), v_s = veto_count(n_split, rho);
+    const int64_t total = (n_clone - v_c) + (n_split - v_s);
+    if (total > 0 && (!lod || !child_parent || !child_lod || !child_split))
+        return fail(GS_ERR_INVALID_ARG, "gs_spawn_gate: null level or output array");
+    const int64_t nmax = std::max(n_clone, n_split);
+    const size_t need = ws_spawn_gate(nmax);
+    if (!ws || ws_bytes < need || !aligned(ws, 256))
+        return fail(GS_ERR_WORKSPACE, "gs_spawn_gate: workspace needs %zu bytes (256-aligned)", need);
+    *n_children = total;
+    Carve cv(ws);
+    SelWs S = carve_sel(cv, nmax);
+    uint32_t* keep = cv.take<uint32_t>(size_t((nmax + 31) / 32 + 1));
+    uint32_t* cnt = cv.take<uint32_t>(size_t((nmax + kBlk - 1) / kBlk + 1));
+    int rc;
+    int64_t base = 0;
+    const int32_t* parents[2] = {clone_parent, split_parent};
+    const float* scores[2] = {p_clone, p_split};
+    const int64_t counts[2] = {n_clone, n_split}, vetoes[2] = {v_c, v_s};
+    for (int set = 0; set < 2; ++set) {
+        const int64_t n = counts[set];
+        if (n == 0) continue;
+        if ((rc = run_select(scores[set], n, 1, 0.f, uint64_t(vetoes[set]), S, stream))) return rc;
+        const int64_t nb = (n + kBlk - 1) / kBlk;
+        hipLaunchKernelGGL(k_keep_bits, dim3(unsigned(nb)), dim3(256), 0, stream, scores[set], n,
+                           static_cast<const SelState*>(S.st), static_cast<const uint32_t*>(S.eq_cnt), keep, 1, 0,
+                           static_cast<unsigned long long*>(nullptr));
+        hipLaunchKernelGGL(k_keep_count, dim3(unsigned(nb)), dim3(256), 0, stream, static_cast<const uint32_t*>(keep),
+                           n, cnt);
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, cnt, nb, static_cast<uint64_t*>(nullptr),
+                           static_cast<const SelState*>(nullptr));
+        launch("spawn_emit", k_spawn_emit, dim3(unsigned(nb)), dim3(256), 0, stream, parents[set],
+               static_cast<const uint32_t*>(keep), n, lod, set, int(n_levels), static_cast<const uint32_t*>(cnt), base,
+               child_parent, child_lod, child_split);
+        base += n - vetoes[set];
+    }
+    return check_launch("gs_spawn_gate");
+}
+
+extern "C" int gs_spawn_stub_score(const gs_scene* scene, const int32_t* parent, int64_t n, float* p,
+                                   hipStream_t stream) {
+    if (!scene || n < 0 || n >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_spawn_stub_score: bad arguments");
+    if (n > 0 && (!scene->opacity_logit || !parent || !p))
+        return fail(GS_ERR_INVALID_ARG, "gs_spawn_stub_score: null argument");
+    if (n == 0) return GS_OK;
+    launch("spawn_stub", k_spawn_stub, dim3(unsigned((n + kBlk - 1) / kBlk)), dim3(256), 0, stream,
+           scene->opacity_logit, parent, n, p);
+    return check_launch("gs_spawn_stub_score");
+}

@@ -22,7 +22,7 @@ GS_ERR_HIP = -4
 
 GS_LOD_NONE, GS_LOD_LEVEL, GS_LOD_RADIUS = 0, 1, 2
 (GS_OP_LOD_MASK, GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_IMPORTANCE, GS_OP_SCORE_KEEP, GS_OP_L1_LOSS,
- GS_OP_SIMPLIFY, GS_OP_PHOTO_LOSS, GS_OP_SCALE_REG, GS_OP_PROJECT) = range(10)
+ GS_OP_SIMPLIFY, GS_OP_PHOTO_LOSS, GS_OP_SCALE_REG, GS_OP_PROJECT, GS_OP_VOXEL_LEVELS, GS_OP_SPAWN_GATE) = range(12)
 GS_MAX_CAMS = 8
 GS_MAX_PAIRS = 1 << 30
 REC_FLOATS = 12
@@ -30,7 +30,8 @@ REC_FLOATS = 12
 EXPORTED = ("gs_workspace_size", "gs_last_error", "gs_num_tiles", "gs_lod_mask", "gs_project", "gs_bin_sort",
             "gs_render_fwd", "gs_render_bwd", "gs_importance", "gs_score_keep_bits", "gs_l1_loss",
             "gs_adam_step", "gs_profile_kernel", "gs_mass_keep_bits", "gs_sample_keep_bits", "gs_compact",
-            "gs_photo_loss", "gs_scale_reg", "gs_lod_mask_noalloc")
+            "gs_photo_loss", "gs_scale_reg", "gs_lod_mask_noalloc", "gs_voxel_levels", "gs_spawn_gate",
+            "gs_spawn_stub_score")
 
 c_int, c_i32, c_i64, c_f, c_p, c_sz = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                        ctypes.c_void_p, ctypes.c_size_t)
@@ -79,6 +80,9 @@ def lib() -> ctypes.CDLL:
         L.gs_num_tiles.argtypes = [c_i32, c_i32]
         L.gs_lod_mask.argtypes = [P, P, P, P, P, P, P, c_sz, P]
         L.gs_lod_mask_noalloc.argtypes = [P, P, P, P, P, P, P]
+        L.gs_voxel_levels.argtypes = [P, c_i64, P, c_f, c_i32, P, P, c_sz, P]
+        L.gs_spawn_gate.argtypes = [P, P, P, c_i64, P, P, c_i64, ctypes.c_double, c_i32, P, P, P, P, P, c_sz, P]
+        L.gs_spawn_stub_score.argtypes = [P, P, c_i64, P, P]
         L.gs_project.argtypes = [P, P, c_i64, P, P, c_int, P, P, c_sz, P]
         L.gs_bin_sort.argtypes = [P, P, c_int, c_i64, P, P, c_i64, P, P, P, c_sz, P]
         L.gs_render_fwd.argtypes = [P, P, c_int, P, P, P, P, P, P, P, P, P]
@@ -260,6 +264,28 @@ def gs_importance(proj: GsProjected, cam: GsCamera, n, vals, tile_ranges, mass_f
 def gs_score_keep_bits(score, n, n_drop, keep_bits, ws, stream=None):
     _check(lib().gs_score_keep_bits(ptr(score), int(n), int(n_drop), ptr(keep_bits), ptr(ws), ws.numel(),
                                     stream_handle(stream)), "gs_score_keep_bits")
+
+
+def gs_voxel_levels(mean, n, origin, delta0, n_levels, lod, ws, stream=None):
+    o = (c_f * 3)(*[float(v) for v in origin])
+    _check(lib().gs_voxel_levels(ptr(mean), int(n), o, float(delta0), int(n_levels), ptr(lod), ptr(ws), ws.numel(),
+                                 stream_handle(stream)), "gs_voxel_levels")
+
+
+def gs_spawn_gate(lod, clone_parent, p_clone, n_clone, split_parent, p_split, n_split, rho, n_levels,
+                  child_parent, child_lod, child_split, ws, stream=None) -> int:
+    """Returns the number of instantiated candidates (known on the host)."""
+    out = c_i64(-1)
+    _check(lib().gs_spawn_gate(ptr(lod), ptr(clone_parent), ptr(p_clone), int(n_clone), ptr(split_parent),
+                               ptr(p_split), int(n_split), float(rho), int(n_levels), ptr(child_parent),
+                               ptr(child_lod), ptr(child_split), ctypes.byref(out), ptr(ws), ws.numel(),
+                               stream_handle(stream)), "gs_spawn_gate")
+    return int(out.value)
+
+
+def gs_spawn_stub_score(scn: GsScene, parent, n, p, stream=None):
+    _check(lib().gs_spawn_stub_score(ctypes.byref(scn), ptr(parent), int(n), ptr(p), stream_handle(stream)),
+           "gs_spawn_stub_score")
 
 
 def gs_mass_keep_bits(score, n, mass_frac, keep_bits, n_keep_dev, ws, stream=None):
