@@ -69,9 +69,9 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="capture the step in a HIP graph and replay it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (counter calibration)")
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="measured seconds of the serving trace (0 disables serving)")
-    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--serve-n", type=int, default=8 << 20, help="Gaussians of the served scene")
     ap.add_argument("--layout", default="morton", choices=["morton", "generated"],
                     help="memory order of the Gaussians: Morton order of the means, or the generator's order")
@@ -287,17 +287,28 @@ class Bench:
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    def kernel_time(self, name, fn, reps):
+    def kernel_time(self, name, fn, reps, after_each=None):
         """Average duration of kernel `name` over `reps` calls of fn, from HIP
-        events recorded around the kernel itself on its own stream."""
+        events recorded around the kernel itself on its own stream.  With
+        after_each, the launch durations are returned one per call, and
+        after_each() runs after each call (outside the kernel's events) to
+        record the work that launch did."""
         G = self.G
         evs = [(G.HipEvent(), G.HipEvent()) for _ in range(reps)]
+        work = []
         for e0, e1 in evs:
             G.gs_profile_kernel(name, e0.handle, e1.handle)
             fn()
+            if after_each is not None:
+                G.gs_profile_kernel(None)
+                self.torch.cuda.synchronize()
+                work.append(after_each())
         G.gs_profile_kernel(None)
         self.torch.cuda.synchronize()
-        return sum(e0.elapsed_ms(e1) for e0, e1 in evs) / reps
+        ms = [e0.elapsed_ms(e1) for e0, e1 in evs]
+        if after_each is not None:
+            return ms, work
+        return sum(ms) / reps
 
     def psnr_gated_vs_plain(self):
         torch = self.torch
@@ -330,13 +341,13 @@ def finite(x):
 
 
 def hbm_fractions(ds, cam, n, capacity, dev, reps=5):
-    """Algorithmic HBM bytes per second of the ungated projection and of the
-    whole binning call (scan, emission, radix passes, ranges, per-tile sort)
-    on one view, timed with events on their stream, against 8 TB/s.  Bytes:
-    projection 12 N (means, read to cull) + 224 N_vis (the rest) + 49 N
+    """Algorithmic HBM bytes per second of the ungated projection, of the
+    whole binning call (scan, emission, sort, ranges) and of the projection
+    backward on one view, timed with events on their stream, against 8 TB/s.
+    Bytes: projection 12 N (means, read to cull) + 224 N_vis (the rest) + 49 N
     (outputs); binning 8 N (scan) + 20 N_vis + 12 K (emission) + K (8 + 24 d)
-    (d = 8-bit passes over the 32 depth and the tile bits) + 8 K + 8 tiles
-    (ranges)."""
+    (d = 8-bit passes of a full-key radix sort over the 32 depth and the tile
+    bits) + 8 K + 8 tiles (ranges); projection backward 557 N_vis."""
     import torch
 
     from paper_2605_13794_amd import gsmi as G
@@ -362,30 +373,84 @@ def hbm_fractions(ds, cam, n, capacity, dev, reps=5):
     d = (32 + max(1, (tiles - 1).bit_length()) + 7) // 8
     b_proj = 12 * n + 224 * n_vis + 49 * n
     b_sort = 8 * n + 20 * n_vis + 12 * K + K * (8 + 24 * d) + 8 * K + 8 * tiles
+    # projection backward: parameters (236), projection (49) and screen-space
+    # partials (36) read, parameter gradients (236) written per visible entry;
+    # its two kernels timed on their own launches
+    grads = [torch.zeros_like(p) for p in ds.params()]
+    gs = G.grads(*grads)
+    f.render_fwd()
+    g_img = [torch.full_like(f.rgb[0], 1e-7)]
+    t_pbwd = 0.0
+    for kname in ("project_bwd", "project_bwd_sh"):
+        evs = [(G.HipEvent(), G.HipEvent()) for _ in range(reps)]
+        for e0, e1 in evs:
+            G.gs_profile_kernel(kname, e0.handle, e1.handle)
+            f.backward(ds.struct(), gs, grad_rgb=g_img)
+        G.gs_profile_kernel(None)
+        torch.cuda.synchronize()
+        t_pbwd += sum(e0.elapsed_ms(e1) for e0, e1 in evs) / reps
+    b_pbwd = (236 + 49 + 36 + 236) * n_vis
     res = {}
-    for name, b, t in (("project", b_proj, t_proj), ("bin_sort", b_sort, t_sort)):
+    for name, b, t in (("project", b_proj, t_proj), ("bin_sort", b_sort, t_sort), ("project_bwd", b_pbwd, t_pbwd)):
         gbs = b / (t * 1e-3) / 1e9
         res[name] = {"ms": t, "bytes": b, "GB_per_s": gbs, "frac": gbs / PEAK_HBM_GBS}
     res["n"], res["n_visible"], res["pairs"] = n, n_vis, K
+    res["sort_path"] = "per-tile depth sort" if f.capacity <= 256 * tiles else "depth-first"
     return res
 
 
-def run_cfg3(args):
-    """8M city: importance over 64 orbit views, score mask (drop 40%), then per
-    view the 0.5 px radius gate; gated vs ungated forward and forward+backward
-    time and PSNR on a subset of views."""
+LOD_LEVELS = 8
+
+
+def voxel_lod(ds, mean_host, cams, dev):
+    """LOD labels of the resident scene by multi-resolution voxelisation
+    (gs_voxel_levels), replacing the generator's labels.  d0 is the median
+    over the views of the camera's distance to the centroid of the means; the
+    level-0 cube edge is d0 / fx, so a level-l cube spans about one pixel at
+    distance d0 / 2^l and the level gate keeps one Gaussian per cube of about
+    a pixel or more.  Returns (d0, seconds of the labelling call, counts per
+    level)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_13794_amd import gsmi as G
+    from paper_2605_13794_amd.raster import Workspace
+    centre = mean_host.astype(np.float64).mean(axis=1)
+    d0 = float(np.median([np.linalg.norm(c.position - centre) for c in cams]))
+    origin = mean_host.min(axis=1).astype(np.float32)
+    delta0 = d0 / cams[0].fx
+    n = ds.n
+    lod = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_VOXEL_LEVELS, n))
+    G.gs_voxel_levels(ds.mean, n, origin, delta0, LOD_LEVELS, lod, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G.gs_voxel_levels(ds.mean, n, origin, delta0, LOD_LEVELS, lod, ws)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ds.lod = lod
+    counts = torch.bincount(lod.to(torch.int64), minlength=LOD_LEVELS).tolist()
+    return d0, delta0, sec, counts
+
+
+def active_set_leg(ds, mean_host, args, sample_views=tuple(range(0, 64, 8)), reps=5, drop_sweep=False):
+    """Active-set reduction on one GPU's shard (Sec. 3.2-3.3): importance over
+    64 orbit views, the score mask (drop the lowest 40% by score), then per
+    view the projected-radius gate (0.5 px) or the level gate (Eqs. 1-2, labels
+    by voxelisation), each AND the mask (Eq. 3); forward+backward (L1) of the
+    plain and gated views timed side by side, PSNR of each gated image against
+    the plain one."""
     import numpy as np
     import torch
 
     from paper_2605_13794_amd import gsmi as G
     from paper_2605_13794_amd import scenes as S
-    from paper_2605_13794_amd.raster import DeviceScene, Frame, Workspace
-    n = args.n if args.n != (1 << 20) else (8 << 20)
-    sc = layout(S.city_scene(n, seed=5), args)
-    ds = DeviceScene(sc, "cuda:0")
-    del sc
+    from paper_2605_13794_amd.raster import Frame, Workspace
     dev = torch.device("cuda:0")
-    cams = S.orbit_cameras(64, 500.0, 300.0, args.width, args.height)
+    n = ds.n
+    W, H = args.width, args.height
+    cams = S.orbit_cameras(64, 500.0, 300.0, W, H)
+    d0, delta0, lod_sec, lod_counts = voxel_lod(ds, mean_host, cams, dev)
     fr = Frame([cams[0]], n, dev)
     w = torch.empty(n, device=dev)
     a = torch.empty(n, dtype=torch.int32, device=dev)
@@ -394,7 +459,6 @@ def run_cfg3(args):
     c_vis = torch.zeros(n, dtype=torch.int32, device=dev)
     cull = torch.zeros(64, (n + 31) // 32, dtype=torch.int32, device=dev)
     ws_imp = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_IMPORTANCE, n))
-    # size the pair buffer on the first view
     fr.project(ds.struct())
     K0 = fr.bin_sort(check=True)
     fr.ensure_capacity(int(K0 * 1.5) + 4096)
@@ -402,8 +466,7 @@ def run_cfg3(args):
     t0 = time.perf_counter()
     Ks = []
     for v, cam in enumerate(cams):
-        fr.cams = [cam]
-        fr.cam_arr = G.camera_array([cam])
+        fr.cams, fr.cam_arr = [cam], G.camera_array([cam])
         fr.project(ds.struct())
         fr.bin_sort(check=False)
         G.gs_importance(fr.proj[0].struct(), G.camera(cam), n, fr.vals, fr.ranges, 0.99, 1e-6, w, a, score, c_rad,
@@ -413,79 +476,125 @@ def run_cfg3(args):
     sweep_ms = 1e3 * (time.perf_counter() - t0) / 64
     Kmax = max(int(k.item()) for k in Ks)
     if Kmax > fr.capacity:
-        raise RuntimeError("pair capacity exceeded during the sweep; rerun")
+        raise RuntimeError("pair capacity exceeded during the importance sweep")
     keep = torch.zeros((n + 31) // 32, dtype=torch.int32, device=dev)
-    G.gs_score_keep_bits(score, n, int(math.ceil(0.4 * n)), keep, Workspace(dev).get(
-        G.gs_workspace_size(G.GS_OP_SCORE_KEEP, n)))
+    ws_keep = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_SCORE_KEEP, n))
+    G.gs_score_keep_bits(score, n, int(math.ceil(0.4 * n)), keep, ws_keep)
     active = torch.empty(n, dtype=torch.int32, device=dev)
     n_act = torch.zeros(1, dtype=torch.int64, device=dev)
     ws_lod = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_LOD_MASK, n))
-    lodp = G.lod_params(G.GS_LOD_RADIUS, fallback_ratio=0.95, radius_min_px=0.5)
-    fracs, rows = [], []
+    modes = {
+        "mask": (G.lod_params(G.GS_LOD_NONE, fallback_ratio=0.95), keep),
+        "radius+mask": (G.lod_params(G.GS_LOD_RADIUS, fallback_ratio=0.95, radius_min_px=0.5), keep),
+        "level+mask": (G.lod_params(G.GS_LOD_LEVEL, d0=d0, f=2.0, l_max=LOD_LEVELS - 1, fallback_ratio=0.95), keep),
+        "level": (G.lod_params(G.GS_LOD_LEVEL, d0=d0, f=2.0, l_max=LOD_LEVELS - 1, fallback_ratio=0.95), None),
+    }
+    fractions = {}
+    for name, (prm, kb) in modes.items():
+        got = []
+        for cam in cams:
+            G.gs_lod_mask(ds.struct(), G.camera(cam), prm, kb, active, n_act, ws_lod)
+            got.append(n_act.clone())
+        f = [int(x.item()) / n for x in got]
+        fractions[name] = {"mean": float(np.mean(f)), "min": float(np.min(f)), "max": float(np.max(f))}
     grads = [torch.zeros_like(p) for p in ds.params()]
     gs = G.grads(*grads)
-    target = torch.from_numpy(S.target_image(args.width, args.height, seed=1)).to(dev)
-    for v, cam in enumerate(cams):
-        G.gs_lod_mask(ds.struct(), G.camera(cam), lodp, keep, active, n_act, ws_lod)
-        fracs.append(n_act)
-    fracs = [int(x.item()) / n for x in fracs]
-    for v in range(0, 64, 8):
-        cam = cams[v]
-        res = {}
-        for mode in ("plain", "gated"):
-            f = Frame([cam], n, dev, capacity=int(Kmax * 1.2) + 4096)
-            def fwd():
-                if mode == "gated":
-                    G.gs_lod_mask(ds.struct(), G.camera(cam), lodp, keep, active, n_act, ws_lod)
-                    f.forward(ds.struct(), active, n, n_act, check=False)
-                else:
-                    f.forward(ds.struct(), check=False)
-            def fb():
-                fwd()
-                f.l1_loss([target])
-                f.backward(ds.struct(), gs)
-            for fn, key in ((fwd, "fwd_ms"), (fb, "fwd_bwd_ms")):
-                fn()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(5):
-                    fn()
-                torch.cuda.synchronize()
-                res[(mode, key)] = 1e3 * (time.perf_counter() - t0) / 5
-            res[(mode, "img")] = f.rgb[0].clone()
-        mse = float(((res[("gated", "img")] - res[("plain", "img")]) ** 2).mean().item())
-        rows.append({"view": v, "active_fraction": fracs[v],
-                     "plain_fwd_ms": res[("plain", "fwd_ms")], "gated_fwd_ms": res[("gated", "fwd_ms")],
-                     "plain_fwd_bwd_ms": res[("plain", "fwd_bwd_ms")],
-                     "gated_fwd_bwd_ms": res[("gated", "fwd_bwd_ms")],
-                     "psnr_db": psnr_db(mse)})
-    # speed at equal image error: drop share x radius threshold on two views
-    sweep = []
-    ws_keep = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_SCORE_KEEP, n))
-    keep2 = torch.zeros_like(keep)
+    target = torch.from_numpy(S.target_image(W, H, seed=1)).to(dev)
     f = Frame([cams[0]], n, dev, capacity=int(Kmax * 1.2) + 4096)
-    plain_img, plain_ms = {}, {}
-    for v in (0, 32):
+
+    def timed_fb(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    rows = []
+    for v in sample_views:
         cam = cams[v]
         f.cams, f.cam_arr = [cam], G.camera_array([cam])
+        camc = G.camera(cam)
 
         def fb_plain():
             f.forward(ds.struct(), check=False)
             f.l1_loss([target])
             f.backward(ds.struct(), gs)
-        fb_plain()
+
+        row = {"view": v, "plain_fwd_bwd_ms": timed_fb(fb_plain), "plain_pairs": int(f.n_pairs.item())}
+        plain_img = f.rgb[0].clone()
+        for name, (prm, kb) in modes.items():
+            def fb_gated(prm=prm, kb=kb):
+                G.gs_lod_mask(ds.struct(), camc, prm, kb, active, n_act, ws_lod)
+                f.forward(ds.struct(), active, n, n_act, check=False)
+                f.l1_loss([target])
+                f.backward(ds.struct(), gs)
+            ms = timed_fb(fb_gated)
+            mse = float(((f.rgb[0] - plain_img) ** 2).mean().item())
+            row[name] = {"fwd_bwd_ms": ms, "speedup": row["plain_fwd_bwd_ms"] / ms, "psnr_db": psnr_db(mse),
+                         "active_fraction": int(n_act.item()) / n, "pairs": int(f.n_pairs.item())}
+        rows.append(row)
+    px = W * H
+    summary = {}
+    plain_ms = float(np.mean([r["plain_fwd_bwd_ms"] for r in rows]))
+    summary["plain"] = {"fwd_bwd_ms": plain_ms, "it_per_s": 1e3 / plain_ms, "mpix_per_s": px / 1e3 / plain_ms}
+    for name in modes:
+        ms = float(np.mean([r[name]["fwd_bwd_ms"] for r in rows]))
+        ps = [r[name]["psnr_db"] for r in rows]
+        summary[name] = {"fwd_bwd_ms": ms, "it_per_s": 1e3 / ms, "mpix_per_s": px / 1e3 / ms,
+                         "speedup": plain_ms / ms,
+                         "psnr_db_min": None if any(p is None for p in ps) else float(np.min(ps)),
+                         "psnr_db_mean": None if any(p is None for p in ps) else float(np.mean(ps)),
+                         "active_fraction_64_views": fractions[name]}
+    hbm = hbm_fractions(ds, cams[0], n, Kmax, dev)
+    out = {"workload": f"aerial city {n} Gaussians, 64 orbit views {W}x{H} (radius 500 m, altitude 300 m): "
+                       f"importance sweep, score mask (drop 40%), radius gate 0.5 px or level gate (Eqs. 1-2), "
+                       f"fwd+bwd L1 on views {list(sample_views)}",
+           "importance_ms_per_view": sweep_ms, "pairs_max": Kmax,
+           "lod": {"levels": LOD_LEVELS, "d0_m": d0, "delta0_m": delta0, "labelling_ms": 1e3 * lod_sec,
+                   "gaussians_per_level": lod_counts},
+           "summary": summary, "views": rows, "hbm_fraction": hbm}
+    if drop_sweep:
+        out["drop_radius_sweep"] = drop_radius_sweep(ds, cams, score, f, target, gs, active, n_act, ws_lod, dev)
+    return out
+
+
+def drop_radius_sweep(ds, cams, score, f, target, gs, active, n_act, ws_lod, dev, views=(0, 32)):
+    """Speed at equal image error: drop share x radius threshold on two views."""
+    import torch
+
+    from paper_2605_13794_amd import gsmi as G
+    from paper_2605_13794_amd.raster import Workspace
+    n = ds.n
+    sweep = []
+    ws_keep = Workspace(dev).get(G.gs_workspace_size(G.GS_OP_SCORE_KEEP, n))
+    keep2 = torch.zeros((n + 31) // 32, dtype=torch.int32, device=dev)
+    plain_img, plain_ms = {}, {}
+
+    def timed(fn):
+        fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(5):
-            fb_plain()
+            fn()
         torch.cuda.synchronize()
-        plain_ms[v] = 1e3 * (time.perf_counter() - t0) / 5
+        return 1e3 * (time.perf_counter() - t0) / 5
+
+    for v in views:
+        f.cams, f.cam_arr = [cams[v]], G.camera_array([cams[v]])
+
+        def fb_plain():
+            f.forward(ds.struct(), check=False)
+            f.l1_loss([target])
+            f.backward(ds.struct(), gs)
+        plain_ms[v] = timed(fb_plain)
         plain_img[v] = f.rgb[0].clone()
     for drop in (0.0, 0.2, 0.4, 0.6):
         G.gs_score_keep_bits(score, n, int(math.ceil(drop * n)), keep2, ws_keep)
         for rmin in (0.0, 0.5, 1.0):
             p2 = G.lod_params(G.GS_LOD_RADIUS, fallback_ratio=0.95, radius_min_px=rmin)
-            for v in (0, 32):
+            for v in views:
                 cam = cams[v]
                 f.cams, f.cam_arr = [cam], G.camera_array([cam])
 
@@ -494,96 +603,146 @@ def run_cfg3(args):
                     f.forward(ds.struct(), active, n, n_act, check=False)
                     f.l1_loss([target])
                     f.backward(ds.struct(), gs)
-                fb_gated()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(5):
-                    fb_gated()
-                torch.cuda.synchronize()
-                ms = 1e3 * (time.perf_counter() - t0) / 5
+                ms = timed(fb_gated)
                 mse = float(((f.rgb[0] - plain_img[v]) ** 2).mean().item())
                 sweep.append({"drop": drop, "radius_min_px": rmin, "view": v,
                               "active_fraction": int(n_act.item()) / n, "fwd_bwd_ms": ms,
-                              "speedup": plain_ms[v] / ms,
-                              "psnr_db": psnr_db(mse)})
-    hbm = hbm_fractions(ds, cams[0], n, Kmax, dev)
-    out = {"metric": METRIC, "config": {"workload": f"aerial city {n} Gaussians, 64 orbit views 1080p: importance "
-                                                    f"sweep, drop 40% by score, 0.5 px radius gate"},
-           "importance_ms_per_view": sweep_ms, "pairs_max": Kmax, "drop_radius_sweep": sweep,
-           "hbm_fraction": hbm,
-           "active_fraction": {"mean": float(np.mean(fracs)), "min": float(np.min(fracs)),
-                               "max": float(np.max(fracs))},
-           "views": rows,
-           "speedup_fwd_bwd": float(np.mean([r["plain_fwd_bwd_ms"] / r["gated_fwd_bwd_ms"] for r in rows]))}
+                              "speedup": plain_ms[v] / ms, "psnr_db": psnr_db(mse)})
+    return sweep
+
+
+def run_cfg3(args):
+    """8M city on its own: the active-set leg of the default line plus the
+    drop x radius sweep."""
+    import torch
+
+    from paper_2605_13794_amd import scenes as S
+    from paper_2605_13794_amd.raster import DeviceScene
+    n = args.n if args.n != (1 << 20) else (8 << 20)
+    sc = layout(S.city_scene(n, seed=5), args)
+    ds = DeviceScene(sc, "cuda:0")
+    mean_host = sc.mean
+    del sc
+    res = active_set_leg(ds, mean_host, args, drop_sweep=True)
+    torch.cuda.synchronize()
+    out = {"metric": METRIC, "config": {"workload": res.pop("workload")}, **res}
     print(json.dumps(finite(out), allow_nan=False), flush=True)
 
 
-def run_cfg4(args):
+def batch4_leg(args, n=5 << 20, steps=10, warmup=3):
     """5M city, a batch of 4 1080p views (the aerial pose at headings 0, 90,
-    180, 270 degrees) through RasterizeFn, L1, backward and Adam."""
+    180, 270 degrees) through RasterizeFn, the L1 autograd function (both
+    through the library) and Adam; once with the transmittance recomputed
+    from the final T in the backward, once with the forward storing the
+    chain; peak device memory of each."""
     import torch
 
     from paper_2605_13794_amd import gsmi as G
     from paper_2605_13794_amd import scenes as S
-    from paper_2605_13794_amd.raster import Adam, DEFAULT_LRS, DeviceScene, Frame, rasterize
-    n = args.n if args.n != (1 << 20) else (5 << 20)
+    from paper_2605_13794_amd.raster import Adam, DEFAULT_LRS, DeviceScene, Frame, l1_loss, rasterize
+    t0 = time.time()
     sc = layout(S.city_scene(n, seed=3), args)
     ds = DeviceScene(sc, "cuda:0", requires_grad=True)
     del sc
+    log(f"5M scene ready in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     cams = [S.aerial_camera(args.width, args.height, h) for h in (0.0, 90.0, 180.0, 270.0)]
-    fr = Frame(cams, n, dev)
-    fr.forward(G.scene(*[p.detach() for p in ds.params()], lod=ds.lod), check=True)
-    fr.ensure_capacity(int(int(fr.n_pairs.item()) * 1.25) + 4096)
     targets = torch.stack([torch.from_numpy(S.target_image(args.width, args.height, seed=10 + k)) for k in
                            range(4)]).to(dev)
-    opt = Adam(ds.params(), DEFAULT_LRS)
+    res = {}
+    for mode, store in (("recompute", False), ("stored_chain", True)):
+        fr = Frame(cams, n, dev, store_chain=store)
+        fr.forward(G.scene(*[p.detach() for p in ds.params()], lod=ds.lod), check=True)
+        fr.ensure_capacity(int(int(fr.n_pairs.item()) * 1.25) + 4096)
+        opt = Adam(ds.params(), DEFAULT_LRS)
 
-    def step():
-        imgs = rasterize(fr, ds)
-        loss = (imgs - targets).abs().mean()
-        loss.backward()
-        opt.step([p.grad for p in ds.params()], clear_grads=True)
+        def step():
+            imgs = rasterize(fr, ds)
+            loss = l1_loss(imgs, targets)
+            loss.backward()
+            opt.step([p.grad for p in ds.params()], clear_grads=True)
 
-    for _ in range(args.warmup):
-        step()
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        res[mode] = {"it_per_s": 1 / sec, "ms_per_step": 1e3 * sec,
+                     "mpix_per_s": 4 * args.width * args.height / 1e6 / sec,
+                     "peak_allocated_gib": torch.cuda.max_memory_allocated() / 2**30,
+                     "pairs": int(fr.n_pairs.item()), "steps": steps}
+        del fr, opt
+        for p in ds.params():
+            p.grad = None
+        torch.cuda.empty_cache()
+    return {"workload": f"aerial city {n} Gaussians, batch of 4 {args.width}x{args.height} views, RasterizeFn + "
+                        f"L1 + Adam", **res}
+
+
+def run_cfg4(args):
+    import torch
+    n = args.n if args.n != (1 << 20) else (5 << 20)
+    res = batch4_leg(args, n=n, steps=args.steps, warmup=args.warmup)
     torch.cuda.synchronize()
-    torch.cuda.reset_peak_memory_stats()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
-    out = {"metric": METRIC, "value": 1 / sec, "unit": "it/s", "ms_per_step": 1e3 * sec,
-           "mpix_per_s": 4 * args.width * args.height / 1e6 / sec, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"aerial city {n} Gaussians, batch of 4 {args.width}x{args.height} views, "
-                                  f"RasterizeFn + L1 + Adam"},
-           "peak_allocated_gib": torch.cuda.max_memory_allocated() / 2**30,
-           "backward": "transmittance recomputed from the final T (no stored chain)"}
+    out = {"metric": METRIC, "value": res["recompute"]["it_per_s"], "unit": "it/s", "dtype": "f32",
+           "data": "synthetic", "config": {"workload": res.pop("workload")}, **res}
     print(json.dumps(finite(out), allow_nan=False), flush=True)
 
 
-def cpu_baseline(scene, cam, min_seconds=10.0):
-    """The float64 reference (test infrastructure) timed on the host over
-    whole steps of the same workload (at least min_seconds), single-threaded."""
+def host_cpu():
+    """CPU model and logical CPU count of the host."""
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def cpu_baseline(scene, cam, sweep_cams, min_seconds=15.0):
+    """The float64 reference (test infrastructure) timed on the host: its
+    compiled compositing loops on all OpenMP threads (OMP_NUM_THREADS, else
+    every available CPU) and its float64 projection on as many torch threads.
+    As on the GPU, the score mask comes from an untimed importance sweep over
+    the same 8 views; then whole steps of the workload run until min_seconds
+    have passed."""
     import numpy as np
     import torch
 
     import oracle
-    torch.set_num_threads(1)
+    model, n_cpu, n_avail = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or n_avail
+    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    torch.set_num_threads(threads)
     oracle.build()
+    omp = oracle.num_threads()
     S = __import__("paper_2605_13794_amd.scenes", fromlist=["x"])
     tgt = S.target_image(cam.width, cam.height, seed=1)
     arrays = scene.arrays()
+    t0 = time.perf_counter()
+    st = oracle.ImportanceState(scene.n, len(sweep_cams) + 1)
+    for v, c in enumerate(sweep_cams):
+        oracle.importance_view(arrays, c, st, v)
+    keep = oracle.score_keep(st.score, oracle.drop_count(scene.n, 0.4))
+    keep_bits = oracle.pack_bits(keep)
+    sweep_s = time.perf_counter() - t0
 
     def one_step():
-        # importance refresh of the view
-        st = oracle.ImportanceState(scene.n, 1)
-        info = oracle.importance_view(arrays, cam, st, 0)
-        # gate + score mask (the sweep's score is replaced by this view's)
-        keep = oracle.score_keep(st.score, oracle.drop_count(scene.n, 0.4))
+        # importance refresh of the training view
+        info = oracle.importance_view(arrays, cam, st, len(sweep_cams))
         gate, _ = oracle.lod_gate_radius(scene.mean, scene.log_scale, cam.position, cam.fx, 0.5)
-        act = oracle.active_set(gate, oracle.pack_bits(keep), 0.95)
+        act = oracle.active_set(gate, keep_bits, 0.95)
         sub = scene.subset(act)
         r = oracle.forward_backward(sub.arrays(), cam, target=tgt)
         lrs = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)
@@ -592,7 +751,6 @@ def cpu_baseline(scene, cam, min_seconds=10.0):
             oracle.adam_step(p, g, np.zeros_like(g), np.zeros_like(g), lr, 1)
         return r, info
 
-    # whole steps until at least 10 s of host work
     t0 = time.perf_counter()
     steps = 0
     while True:
@@ -601,52 +759,63 @@ def cpu_baseline(scene, cam, min_seconds=10.0):
         if time.perf_counter() - t0 >= min_seconds:
             break
     dt = time.perf_counter() - t0
-    return dict(value=steps / dt, unit="it/s", cores=1, kind="oracle",
+    return dict(value=steps / dt, unit="it/s", cores=omp, kind="oracle",
                 sample=f"{steps} full steps ({scene.n} Gaussians, {cam.width}x{cam.height}: importance refresh, "
-                       f"gate, projection, sort, compositing, L1, backward, Adam) in {dt:.1f} s on one "
-                       f"{platform.processor() or 'host'} core", seconds=dt, pairs=int(r["K"]),
-                imp_pairs=int(info["K"]))
+                       f"gate with the score mask of an untimed 8-view reference sweep ({sweep_s:.1f} s), "
+                       f"projection, sort, compositing, L1, backward, Adam) in {dt:.1f} s on {omp} threads",
+                seconds=dt, threads_compositing=omp, threads_torch=torch.get_num_threads(), nproc=n_cpu,
+                cpus_available=n_avail, cpu_model=model, pairs=int(r["K"]), imp_pairs=int(info["K"]))
 
 
-def serving(args):
+def serving(args, ds):
     """Continuous-batching server over the resident city: Poisson arrivals at
     200 requests/s, resolutions uniform over {640x360, 1280x720, 1920x1080,
     3840x2160}, random aerial poses.  Latency runs from arrival to the
-    completion event of the request's batch."""
+    completion of the request's batch on the device clock (its completion
+    event).  A second, saturating trace (2,000 requests offered at 1,000/s)
+    measures the served capacity."""
     import torch
 
     from paper_2605_13794_amd import scenes as S
-    from paper_2605_13794_amd.raster import DeviceScene
     from paper_2605_13794_amd.serve import GpuExecutor, Request, Scheduler, percentile, serve
-    t0 = time.time()
-    sc = layout(S.city_scene(args.serve_n, seed=5), args)
-    ds = DeviceScene(sc, "cuda:0")
-    del sc
-    log(f"served scene {ds.n} Gaussians ready in {time.time() - t0:.1f}s")
-    total = args.serve_warmup + args.serve_seconds
-    n_req = int(total * 200 * 1.2) + 16
-    trace = [(t, cam) for t, cam in S.serving_requests(n_req, rate_hz=200.0, seed=6) if t < total]
-    reqs = [Request(rid=i, arrival=t, cam=cam) for i, (t, cam) in enumerate(trace)]
     pool = 16 << 30
-    ex = GpuExecutor(ds, n_slots=3, max_batch=8)
-    sch = Scheduler(n_slots=3, max_batch=8, memory_budget=pool, pairs_per_px=2.0)
-    # one untimed request compiles nothing but warms the allocator and sizes buffers
-    serve([Request(rid=-1, arrival=0.0, cam=trace[0][1])], ex, sch)
-    torch.cuda.synchronize()
-    done, _ = serve(reqs, ex, sch)
-    meas = [r for r in done if r.arrival >= args.serve_warmup]
-    lat = [1e3 * r.latency for r in meas]
-    mpix = sum(r.pixels for r in meas) / 1e6
-    span = max(r.t_done for r in meas) - min(r.arrival for r in meas)
-    by_res = {}
-    for r in meas:
-        by_res.setdefault(f"{r.cam.width}x{r.cam.height}", []).append(1e3 * r.latency)
-    return {"requests": len(meas), "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
-            "p50_p99_ms_by_resolution": {k: [percentile(v, 50), percentile(v, 99)] for k, v in sorted(by_res.items())},
-            "mean_ms": sum(lat) / len(lat), "mpix_per_s": mpix / span, "offered_req_per_s": 200.0,
-            "served_req_per_s": len(meas) / span, "batches": sch.n_batches, "memory_pool_gib": pool / 2**30,
-            "retries": sum(r.retries for r in done), "gaussians": ds.n, "slots": 3, "max_batch": 8,
-            "measured_s": args.serve_seconds}
+
+    def run(rate, seconds, warmup, seed):
+        total = warmup + seconds
+        n_req = int(total * rate * 1.2) + 16
+        trace = [(t, cam) for t, cam in S.serving_requests(n_req, rate_hz=rate, seed=seed) if t < total]
+        reqs = [Request(rid=i, arrival=t, cam=cam) for i, (t, cam) in enumerate(trace)]
+        ex = GpuExecutor(ds, n_slots=3, max_batch=8)
+        sch = Scheduler(n_slots=3, max_batch=8, memory_budget=pool, pairs_per_px=2.0)
+        serve([Request(rid=-1, arrival=0.0, cam=trace[0][1])], ex, sch)
+        torch.cuda.synchronize()
+        done, _ = serve(reqs, ex, sch)
+        meas = [r for r in done if r.arrival >= warmup]
+        lat = [1e3 * r.latency for r in meas]
+        seen = [1e3 * (r.t_seen - r.arrival) for r in meas]
+        mpix = sum(r.pixels for r in meas) / 1e6
+        span = max(r.t_done for r in meas) - min(r.arrival for r in meas)
+        by_res = {}
+        for r in meas:
+            by_res.setdefault(f"{r.cam.width}x{r.cam.height}", []).append(1e3 * r.latency)
+        out = {"requests": len(meas), "offered_req_per_s": rate, "measured_s": seconds,
+               "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "mean_ms": sum(lat) / len(lat),
+               "p50_p99_ms_by_resolution": {k: [percentile(v, 50), percentile(v, 99)] for k, v in
+                                            sorted(by_res.items())},
+               "p99_ms_host_observed": percentile(seen, 99), "mpix_per_s": mpix / span,
+               "served_req_per_s": len(meas) / span, "batches": sch.n_batches,
+               "retries": sum(r.retries for r in done)}
+        del ex
+        torch.cuda.empty_cache()
+        return out
+
+    res = run(200.0, args.serve_seconds, args.serve_warmup, 6)
+    res.update({"memory_pool_gib": pool / 2**30, "gaussians": ds.n, "slots": 3, "max_batch": 8,
+                "latency_clock": "device completion event"})
+    sat = run(1000.0, 2.0, 0.0, 7)
+    res["saturation"] = {k: sat[k] for k in ("requests", "offered_req_per_s", "mpix_per_s", "served_req_per_s",
+                                            "p50_ms", "p99_ms", "batches")}
+    return res
 
 
 def copy_calibration():
@@ -666,8 +835,8 @@ def roofline(b, name, reps, args):
     steps (HIP events around its own launches) against its algorithmic work
     per launch."""
     torch = b.torch
-    kms = b.kernel_time(name, b.step, reps)
     if name == "adam":
+        kms = b.kernel_time(name, b.step, reps)
         floats = sum(int(p.numel()) for p in b.ds.params())
         nbytes = ADAM_BYTES_PER_FLOAT * floats
         achieved = nbytes / (kms * 1e-3) / 1e9
@@ -675,23 +844,32 @@ def roofline(b, name, reps, args):
                     traffic=recorded_traffic(name, args), kernel=name, ms=kms, bytes_per_launch=nbytes,
                     floats=floats, bytes_per_float=ADAM_BYTES_PER_FLOAT)
     if name == "render_bwd":
-        # algorithmic work of one launch on the gated frame (the step leaves
-        # the gated frame's lists and forward outputs in place)
+        # algorithmic work of each timed launch, read right after its step from
+        # the gated frame's lists and forward outputs (which that backward used)
         G = b.G
-        last_sum = int(b.fr.last[0].to(torch.int64).sum().item())
         a2 = torch.empty(b.n, dtype=torch.int32, device=b.dev)
         w2, s2 = torch.empty(b.n, device=b.dev), torch.zeros(b.n, device=b.dev)
         c2 = torch.zeros(b.n, dtype=torch.int32, device=b.dev)
         cull2 = torch.zeros((b.n + 31) // 32, dtype=torch.int32, device=b.dev)
-        G.gs_importance(b.fr.proj[0].struct(), b.camc, b.n, b.fr.vals, b.fr.ranges, 0.99, 1e-6, w2, a2, s2, c2,
-                        c2.clone(), cull2, b.ws_imp)
-        composited = int(a2.to(torch.int64).sum().item())
-        ops = ALPHA_OPS * last_sum + BWD_COMPOSITED_OPS * composited
-        achieved = ops / (kms * 1e-3) / 1e12
+
+        def work():
+            last_sum = int(b.fr.last[0].to(torch.int64).sum().item())
+            G.gs_importance(b.fr.proj[0].struct(), b.camc, b.n, b.fr.vals, b.fr.ranges, 0.99, 1e-6, w2, a2, s2, c2,
+                            c2.clone(), cull2, b.ws_imp)
+            composited = int(a2.to(torch.int64).sum().item())
+            return last_sum, composited, int(b.fr.n_pairs.item())
+
+        ms, counts = b.kernel_time(name, b.step, reps, after_each=work)
+        ops = [ALPHA_OPS * ls + BWD_COMPOSITED_OPS * cp for ls, cp, _ in counts]
+        achieved = sum(ops) / (sum(ms) * 1e-3) / 1e12
         return dict(bound="alu", achieved=achieved, peak=PEAK_ALU_GOPS / 1e3, unit="TOP/s",
                     frac=achieved / (PEAK_ALU_GOPS / 1e3), traffic=recorded_traffic(name, args), kernel=name,
-                    ms=kms, positions=last_sum, composited=composited, ops_per_position=ALPHA_OPS,
-                    ops_per_composited=BWD_COMPOSITED_OPS)
+                    ms=sum(ms) / reps, launches=reps, positions=sum(c[0] for c in counts) // reps,
+                    composited=sum(c[1] for c in counts) // reps,
+                    pairs_min_max=[min(c[2] for c in counts), max(c[2] for c in counts)],
+                    ops_per_position=ALPHA_OPS, ops_per_composited=BWD_COMPOSITED_OPS,
+                    counted="per timed launch, from that launch's own lists and forward outputs")
+    kms = b.kernel_time(name, b.step, reps)
     return dict(bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s", frac=None, traffic=None,
                 kernel=name, ms=kms)
 
@@ -719,10 +897,16 @@ def main():
     act_frac = int(b.n_act.item()) / b.n
     log(f"active fraction {act_frac:.3f}")
     log(f"step {sec * 1e3:.3f} ms")
+    px = args.width * args.height
     extras = {}
     if not args.quick:
-        extras["gated_train_ms"] = 1e3 * b.timed(lambda: b.train_iter(True), args.steps, 2)
-        extras["plain_train_ms"] = 1e3 * b.timed(lambda: b.train_iter(False), args.steps, 2)
+        g_ms = 1e3 * b.timed(lambda: b.train_iter(True), args.steps, 2)
+        p_ms = 1e3 * b.timed(lambda: b.train_iter(False), args.steps, 2)
+        extras["train_iteration"] = {
+            "what": "one fwd+bwd training iteration on the 1080p view (gate, projection, sort, compositing, L1, "
+                    "backward, Adam), without the importance refresh",
+            "gated": {"ms": g_ms, "it_per_s": 1e3 / g_ms, "mpix_per_s": px / 1e3 / g_ms},
+            "plain": {"ms": p_ms, "it_per_s": 1e3 / p_ms, "mpix_per_s": px / 1e3 / p_ms}}
         extras["importance_view_ms"] = 1e3 * b.timed(
             lambda: b.importance_view(b.fr_all, b.camc, b.sweep_views), args.steps, 2)
         b.check_capacity()
@@ -732,7 +916,6 @@ def main():
     roof = roofline(b, args.kernel, reps, args)
     roof_blend = roofline(b, "render_bwd", reps, args) if args.kernel != "render_bwd" else None
     pairs = int(b.fr.n_pairs.item())
-    px = args.width * args.height
     out = {
         "metric": METRIC,
         "value": 1.0 / sec,
@@ -747,6 +930,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "launch": "hip graph replay" if args.graph else "eager",
+        "step": "one pass of the whole hot path on the view: its importance refresh (projection, sort, importance "
+                "blend, top-99% mass, fold) on a second stream beside the gated training iteration (gate with "
+                "the score mask, projection, sort, compositing, L1, backward, Adam)",
         "config": {"workload": f"aerial city {b.n} Gaussians, one {args.width}x{args.height} view per step: "
                                f"importance refresh + gated (r>={args.rmin}px, drop {args.drop:.0%} by score) "
                                f"fwd+bwd L1 + Adam",
@@ -761,19 +947,37 @@ def main():
     if roof_blend is not None:
         out["roofline_blend"] = roof_blend
     out.update(extras)
-    if "gated_train_ms" in extras:
-        out["gated_train_it_per_s"] = 1e3 / extras["gated_train_ms"]
-        out["plain_train_it_per_s"] = 1e3 / extras["plain_train_ms"]
-    if args.serve_seconds > 0:
-        del b
+    del b
+    torch.cuda.empty_cache()
+    ds8 = None
+    if not args.quick or args.serve_seconds > 0:
+        from paper_2605_13794_amd import scenes as S
+        from paper_2605_13794_amd.raster import DeviceScene
+        t0 = time.time()
+        sc8 = layout(S.city_scene(args.serve_n, seed=5), args)
+        ds8 = DeviceScene(sc8, "cuda:0")
+        mean8 = sc8.mean
+        del sc8
+        log(f"8M scene ready in {time.time() - t0:.1f}s")
+    if not args.quick:
+        log("active-set leg (64-view importance sweep, gates, gated vs plain) ...")
+        out["active_set_8M"] = active_set_leg(ds8, mean8, args)
         torch.cuda.empty_cache()
+        log("batch of four views on 5M (recompute vs stored chain) ...")
+        out["batch4_5M"] = batch4_leg(args)
+        torch.cuda.empty_cache()
+    if args.serve_seconds > 0:
         log("serving trace ...")
-        out["serving"] = serving(args)
+        out["serving"] = serving(args, ds8)
+    del ds8
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        log("timing the CPU reference on one step ...")
+        log("timing the CPU reference ...")
         from paper_2605_13794_amd import scenes as S
         out["cpu_baseline"] = cpu_baseline(layout(S.city_scene(args.n, seed=2), args),
-                                           S.aerial_camera(args.width, args.height))
+                                           S.aerial_camera(args.width, args.height),
+                                           [S.aerial_camera(args.width, args.height, heading_deg=45.0 * v)
+                                            for v in range(8)])
     print(json.dumps(finite(out), allow_nan=False), flush=True)
 
 

@@ -32,6 +32,7 @@ class Request:
     cam: object
     t_start: float | None = None
     t_done: float | None = None
+    t_seen: float | None = None
     pairs: int | None = None
     batch: int | None = None
     retries: int = 0
@@ -177,9 +178,22 @@ class GpuExecutor:
                           stream)
             G.gs_render_fwd(projs, carr, s["vals"], s["ranges"], self.bg, [o[0] for o in out], [o[1] for o in out],
                             [o[2] for o in out], stream=stream)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(stream)
         s["event"], s["batch"], s["out"] = ev, batch, out
+
+    def start_clock(self):
+        """Records the reference event of device time stamps (after every
+        earlier launch) and waits for it; returns nothing."""
+        torch = self.torch
+        self.ref = torch.cuda.Event(enable_timing=True)
+        self.ref.record(torch.cuda.current_stream())
+        self.ref.synchronize()
+
+    def device_time(self, slot: int) -> float:
+        """Seconds from the reference event to the completion event of the
+        slot's batch, on the device clock."""
+        return self.ref.elapsed_time(self.slots[slot]["event"]) / 1e3
 
     def done(self, slot: int) -> bool:
         ev = self.slots[slot]["event"]
@@ -212,11 +226,19 @@ class GpuExecutor:
 def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, keep_images=False, idle_sleep=0.0):
     """Runs the arrival trace (request.arrival in seconds from the start)
     through the scheduler and executor; returns the completed requests (with
-    t_done set) and, if asked, their images keyed by request id."""
+    t_done set) and, if asked, their images keyed by request id.
+
+    If the executor keeps device time stamps (start_clock / device_time),
+    t_done is the completion of the request's batch on the device clock,
+    mapped to the trace's clock at the moment the reference event completed;
+    t_seen is when the host observed it."""
     pending = sorted(requests, key=lambda r: r.arrival)
     pi = 0
     done = []
     images = {}
+    device_clock = hasattr(executor, "start_clock")
+    if device_clock:
+        executor.start_clock()
     t0 = clock()
     while len(done) < len(pending):
         now = clock() - t0
@@ -231,10 +253,12 @@ def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, kee
                     scheduler.retry(slot, K)
                     continue
                 t = clock() - t0
+                t_dev = executor.device_time(slot) if device_clock else t
                 batch = scheduler.finish(slot, K)
                 imgs = executor.copy_images(slot) if keep_images else None
                 for k, r in enumerate(batch):
-                    r.t_done = t
+                    r.t_done = t_dev
+                    r.t_seen = t
                     r.pairs = K
                     done.append(r)
                     if keep_images:

@@ -26,3 +26,13 @@ def test_printed_line_is_strict_json():
     assert abs(bench.psnr_db(1e-4) - 40.0) < 1e-12
     line = json.dumps(bench.finite({"psnr": float("inf"), "rows": [{"x": float("nan")}, 1.5]}), allow_nan=False)
     assert json.loads(line) == {"psnr": None, "rows": [{"x": None}, 1.5]}
+
+
+def test_host_cpu_reports_model_and_counts():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    model, n_cpu, n_avail = bench.host_cpu()
+    assert isinstance(model, str) and model
+    assert n_cpu >= 1 and 1 <= n_avail <= n_cpu

@@ -112,3 +112,26 @@ def test_charge_scales_with_pixels():
 def test_percentile():
     assert percentile([1, 2, 3, 4, 5], 50) == 3
     assert abs(percentile(list(range(101)), 99) - 99) < 1e-9
+
+
+class DeviceClockExecutor(FakeExecutor):
+    """Like FakeExecutor, but keeps device time stamps: a batch completes on
+    the device `dur` after its launch, while the host observes it later."""
+
+    def start_clock(self):
+        self.ref = self.clock.t
+
+    def device_time(self, slot):
+        return self.slots[slot][0] - self.ref
+
+
+def test_latency_uses_device_completion_time():
+    clock = FakeClock()
+    ex = DeviceClockExecutor(clock, dur=2e-3)
+    sch = Scheduler(n_slots=2, max_batch=4, memory_budget=1 << 40)
+    done, _ = serve(_reqs(20), ex, sch, clock=clock)
+    assert len(done) == 20
+    for r in done:
+        # completion on the device clock, never after the host saw it
+        assert r.t_done is not None and r.t_seen is not None
+        assert r.arrival <= r.t_done <= r.t_seen + 1e-12
