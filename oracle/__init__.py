@@ -68,7 +68,7 @@ def lib():
         L.gso_render_bwd.restype = None
         L.gso_render_bwd.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P]
         L.gso_importance_blend.restype = None
-        L.gso_importance_blend.argtypes = [i32, i32, i64, P, P, P, P, P, P, P]
+        L.gso_importance_blend.argtypes = [i32, i32, i64, P, P, P, P, P, P, P, i32]
         L.gso_num_threads.restype = ctypes.c_int
         L.gso_num_threads.argtypes = []
         _lib = L
@@ -247,10 +247,12 @@ def forward_backward(scene_arrays: dict, cam, target=None, bg=(0.0, 0.0, 0.0),
 # --------------------------------------------------------------------------
 # Importance sweep (Sec. 3.2, Fig. 3)
 # --------------------------------------------------------------------------
-def importance_blend(pr: Projected, vals, ranges, width, height):
+def importance_blend(pr: Projected, vals, ranges, width, height, footprint: bool = False):
     """Per-view w_{i,v} = sum_p alpha_p T_p and a_{i,v} = number of pixels at
     which g_i is composited (reading: the pixels that the instrumented blend
-    actually visits and composites)."""
+    actually visits and composites).  footprint=True takes the other reading
+    of "pixels it touches": a_{i,v} counts every pixel of g_i's tiles inside
+    its footprint (kernel value passing the 1/255 test), occluded or not."""
     w = np.zeros(pr.n)
     a = np.zeros(pr.n, dtype=np.int64)
     vals = np.ascontiguousarray(vals, dtype=np.uint32)
@@ -258,7 +260,7 @@ def importance_blend(pr: Projected, vals, ranges, width, height):
     if vals.size == 0:
         vals = np.zeros(1, dtype=np.uint32)
     lib().gso_importance_blend(width, height, pr.n, _p(pr.mean2d), _p(pr.conic), _p(pr.opacity),
-                               _p(vals), _p(ranges), _p(w), _p(a))
+                               _p(vals), _p(ranges), _p(w), _p(a), 1 if footprint else 0)
     return w, a
 
 
@@ -327,11 +329,11 @@ def importance_fold(state: ImportanceState, view: int, w, a, radius, frac=0.99, 
 
 
 def importance_view(scene_arrays, cam, state: ImportanceState, view: int, frac=0.99, eps=1e-6,
-                    projected_override: Projected | None = None):
+                    projected_override: Projected | None = None, footprint: bool = False):
     _, _, pr = project(scene_arrays, cam)
     prx = projected_override if projected_override is not None else pr
     K, keys, vals, ranges = bin_sort(prx, cam.width, cam.height)
-    w, a = importance_blend(prx, vals, ranges, cam.width, cam.height)
+    w, a = importance_blend(prx, vals, ranges, cam.width, cam.height, footprint)
     crad, cvis = importance_fold(state, view, w, a, prx.radius, frac, eps)
     return dict(w=w, a=a, c_rad=crad, c_vis=cvis, K=K)
 

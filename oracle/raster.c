@@ -304,11 +304,14 @@ void gso_render_bwd(int32_t width, int32_t height, int64_t n, const double* mean
 /*
  * Instrumented blend without colour for one view: for each pixel and each
  * Gaussian composited at it, w[j] += alpha T (T before compositing j) and
- * a[j] += 1.  Accumulates into w and a.
+ * a[j] += 1.  Accumulates into w and a.  With footprint = 1, a[j] instead
+ * counts every pixel of j's tiles inside its footprint (the kernel value
+ * passes the 1/255 test), composited or not: occluded pixels and pixels that
+ * stopped earlier count too (w is unchanged).
  */
 void gso_importance_blend(int32_t width, int32_t height, int64_t n, const double* mean2d,
                           const double* conic, const double* opacity, const uint32_t* vals,
-                          const uint32_t* ranges, double* w, int64_t* a) {
+                          const uint32_t* ranges, double* w, int64_t* a, int32_t footprint) {
     const int64_t TX = (width + TILE - 1) / TILE, TY = (height + TILE - 1) / TILE;
     const int64_t n_tiles = TX * TY;
     const int nt = omp_get_max_threads();
@@ -326,6 +329,7 @@ void gso_importance_blend(int32_t width, int32_t height, int64_t n, const double
             const int64_t start = ranges[t], end = ranges[n_tiles + t];
             const double px = u + 0.5, py = v + 0.5;
             double T = 1.0;
+            int stopped = 0;
             for (int64_t k = start; k < end; ++k) {
                 const uint32_t j = vals[k];
                 const double dx = mean2d[j] - px, dy = mean2d[n + j] - py;
@@ -335,10 +339,16 @@ void gso_importance_blend(int32_t width, int32_t height, int64_t n, const double
                 const double g = opacity[j] * exp(power);
                 const double alpha = g < ALPHA_MAX ? g : ALPHA_MAX;
                 if (alpha < ALPHA_MIN) continue;
+                if (footprint) a_t[j] += 1;
+                if (stopped) continue;
                 const double Tn = T * (1.0 - alpha);
-                if (Tn < T_MIN) break;
+                if (Tn < T_MIN) {
+                    if (!footprint) break;
+                    stopped = 1;
+                    continue;
+                }
                 w_t[j] += alpha * T;
-                a_t[j] += 1;
+                if (!footprint) a_t[j] += 1;
                 T = Tn;
             }
         }

@@ -463,6 +463,50 @@ def test_importance_sum_identity(oracle):
     assert (a[pr.radius == 0] == 0).all()
 
 
+def _footprint_brute(pr, i, width, height):
+    """Pixels of Gaussian i's tile rectangle (the tiles it is listed in, inside
+    the image) whose kernel value passes the 1/255 test, counted pixel by
+    pixel from the definition: what the footprint reading of a_{i,v} counts,
+    and what the composited count is when nothing else is drawn."""
+    if pr.radius[i] <= 0:
+        return 0
+    TX, TY = -(-width // 16), -(-height // 16)
+    r = int(pr.radius[i])
+    xi, yi = math.floor(pr.mean2d[0, i]), math.floor(pr.mean2d[1, i])
+    tx0, tx1 = min(max((xi - r) // 16, 0), TX), min(max((xi + r) // 16 + 1, 0), TX)
+    ty0, ty1 = min(max((yi - r) // 16, 0), TY), min(max((yi + r) // 16 + 1, 0), TY)
+    a, b, c = pr.conic[0, i], pr.conic[1, i], pr.conic[2, i]
+    count = 0
+    for v in range(ty0 * 16, min(ty1 * 16, height)):
+        for u in range(tx0 * 16, min(tx1 * 16, width)):
+            dx, dy = pr.mean2d[0, i] - (u + 0.5), pr.mean2d[1, i] - (v + 0.5)
+            power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+            if power > 0:
+                continue
+            if min(0.99, pr.opacity[i] * math.exp(power)) >= 1.0 / 255.0:
+                count += 1
+    return count
+
+
+def test_importance_footprint_count_ignores_occlusion(oracle):
+    """Footprint reading of a_{i,v}: the count of every Gaussian equals its
+    count when drawn alone (occluders and stopped pixels do not change it),
+    computed pixel by pixel; the composited count is never larger, and is
+    smaller where an opaque stack stops pixels early."""
+    w_, h_ = 48, 40
+    cam = S.cube_camera(w_, h_, 48.0)
+    scn = _tiny_scene(120, seed=5, log_mu=-1.8)
+    scn["opacity_logit"] = scn["opacity_logit"] + 4.0        # nearly opaque: pixels stop
+    _, _, pr = oracle.project(scn, cam)
+    K, keys, vals, ranges = oracle.bin_sort(pr, w_, h_)
+    w_c, a_c = oracle.importance_blend(pr, vals, ranges, w_, h_)
+    w_f, a_f = oracle.importance_blend(pr, vals, ranges, w_, h_, footprint=True)
+    want = np.array([_footprint_brute(pr, i, w_, h_) for i in range(pr.n)])
+    np.testing.assert_array_equal(a_f, want)
+    np.testing.assert_array_equal(w_f, w_c)                  # w is the same either way
+    assert (a_c <= a_f).all() and (a_c < a_f).any()
+
+
 def test_top_mass_hand_cases(oracle):
     # W = 100, 0.99 W = 99: prefix 50, 30, 10, 9.5 reaches 99.5 (crossing included)
     w = np.array([10.0, 0.5, 30.0, 9.5, 50.0, 0.0])

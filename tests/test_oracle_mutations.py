@@ -233,3 +233,10 @@ def test_level_mutation_is_caught(name):
         except (AssertionError, IndexError, ValueError):
             failed.append(pin.__name__)
     assert failed, f"no pin catches: {name}"
+
+
+def test_footprint_count_that_stops_with_the_pixel_is_caught(oracle, with_c_mutation):
+    old = "if (footprint) a_t[j] += 1;\n                if (stopped) continue;"
+    new = "if (stopped) continue;\n                if (footprint) a_t[j] += 1;"
+    with_c_mutation([(old, new, 1)])
+    _fails(P.test_importance_footprint_count_ignores_occlusion, oracle)
