@@ -97,13 +97,19 @@ typedef struct gs_projected {
     float* rgb;               /* [3][n] optional */
 } gs_projected;
 
-/* Parameter gradients, same layouts as gs_scene; accumulated (+=). */
+/* Parameter gradients, same layouts as gs_scene.  overwrite = 0: the
+ * backward adds (+=) into them.  overwrite = 1: the gradients of the
+ * Gaussians the backward reaches (visible in some camera of the call) are
+ * stored (=) instead, which saves reading them; for callers whose gradient
+ * arrays hold zeros there (e.g. cleared by gs_adam_step), where both give the
+ * same result.  Gaussians the call does not reach are untouched either way. */
 typedef struct gs_grads {
     float* mean;
     float* log_scale;
     float* quat;
     float* opacity_logit;
     float* sh;
+    int32_t overwrite;
 } gs_grads;
 
 enum { GS_LOD_NONE = 0, GS_LOD_LEVEL = 1, GS_LOD_RADIUS = 2 };
@@ -290,12 +296,19 @@ int gs_render_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t n_in
  * (w descending, i ascending) whose mass reaches mass_frac * sum(w),
  * Cull = 1 - c^vis written as bitmap row cull_row [ceil(n/32)],
  * score_i += w_i / (a_i + eps) where a_i > 0, c_rad_i += c^rad,
- * c_vis_i += c^vis.  Workspace: GS_OP_IMPORTANCE.
+ * c_vis_i += c^vis.  count_mode chooses the reading of a_i ("the number of
+ * pixels it touches"): GS_COUNT_COMPOSITED (the pixels at which i is
+ * composited, the default reading) or GS_COUNT_FOOTPRINT (every pixel of
+ * i's tiles, inside the image, whose kernel value passes the 1/255 test,
+ * occluded or not; the blend then visits whole lists).  w is the same in both.
+ * Workspace: GS_OP_IMPORTANCE.
  */
+enum { GS_COUNT_COMPOSITED = 0, GS_COUNT_FOOTPRINT = 1 };
+
 int gs_importance(const gs_projected* proj, const gs_camera* cam, int64_t n,
                   const uint32_t* vals, const uint32_t* tile_ranges, float mass_frac, float eps,
-                  float* w, uint32_t* a, float* score, uint32_t* c_rad, uint32_t* c_vis,
-                  uint32_t* cull_row, void* ws, size_t ws_bytes, hipStream_t stream);
+                  int32_t count_mode, float* w, uint32_t* a, float* score, uint32_t* c_rad,
+                  uint32_t* c_vis, uint32_t* cull_row, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Score mask: keep_bits [ceil(n/32)] with the n_drop lowest scores (order:
@@ -405,6 +418,17 @@ int gs_adam_step(float* const* params, float* const* grads, float* const* m,
  */
 int gs_voxel_levels(const float* mean, int64_t n, const float* origin, float delta0, int32_t n_levels,
                     uint8_t* lod, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Coarse-to-fine ceiling L_max(t) of the level gate (Sec. 3.3, after Eq. 2:
+ * levels unlock coarse to fine on a geometric schedule).  Level k unlocks at
+ * iteration u_k = t0 * (t1 / t0)^(k / (n_levels - 1)) (double arithmetic), so
+ * u_0 = t0, u_{n_levels-1} = t1 and consecutive unlock times have a constant
+ * ratio; returns the largest k with u_k <= t (0 up to t0, n_levels - 1 from
+ * t1 on).  Pass the result as gs_lod_params.l_max.  Host only; needs
+ * 0 < t0 < t1.
+ */
+int32_t gs_lod_level_ceiling(int64_t t, int64_t t0, int64_t t1, int32_t n_levels);
 
 /*
  * Spawn gate of one densification event (Sec. 3.2 "Spawn gate"; the veto

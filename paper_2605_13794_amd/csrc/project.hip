@@ -253,18 +253,12 @@ __global__ __launch_bounds__(256) void k_project_cull(SceneP P, const int32_t* _
     }
 }
 
-// Pass 2: full projection of the candidates.
-__global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
-                                                 const uint32_t* __restrict__ list,
-                                                 const uint32_t* __restrict__ count, CamSet C, ProjOut O) {
-    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= *count) return;
-    const int64_t j = list[t];
-    const int64_t i = active ? int64_t(active[j]) : j;
+// Full projection of entry j (Gaussian i) into every camera in which the
+// conservative test left it possibly visible.
+__device__ __forceinline__ void project_entry(const SceneP& P, int64_t i, int64_t j, int64_t n_in, const CamSet& C,
+                                              const ProjOut& O, const float mu[3], const float ls[3],
+                                              uint32_t maybe) {
     const int64_t N = P.n;
-    float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
-    const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
-    const uint32_t maybe = maybe_visible(C, mu, ls);
     const float q[4] = {P.quat[i], P.quat[N + i], P.quat[2 * N + i], P.quat[3 * N + i]};
     float s[3], qn[4], R[9], M[9], S[6], qlen;
     covariance(ls, q, s, qn, R, M, S, qlen);
@@ -327,6 +321,48 @@ __global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __rest
     }
 }
 
+// Pass 2: full projection of the candidates.
+__global__ __launch_bounds__(256) void k_project(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
+                                                 const uint32_t* __restrict__ list,
+                                                 const uint32_t* __restrict__ count, CamSet C, ProjOut O) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= *count) return;
+    const int64_t j = list[t];
+    const int64_t i = active ? int64_t(active[j]) : j;
+    const int64_t N = P.n;
+    const float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
+    const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
+    project_entry(P, i, j, n_in, C, O, mu, ls, maybe_visible(C, mu, ls));
+}
+
+// Single pass for large inputs: one thread per input entry, culled entries
+// leave at once.  With the Gaussians in spatial (Morton) order, visibility is
+// coherent along the entries, so wavefronts are mostly all-culled or
+// all-visible; the candidate list and the second read of the means and
+// scales of the two-pass form are saved.
+__global__ __launch_bounds__(256) void k_project_all(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
+                                                     const int64_t* __restrict__ n_in_dev, CamSet C, ProjOut O) {
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= n_in) return;
+    int64_t cnt = n_in;
+    if (n_in_dev) cnt = min(cnt, *n_in_dev);
+    int64_t i = j;
+    if (active) i = j < cnt ? int64_t(active[j]) : -1;
+    const int64_t N = P.n;
+    if (j >= cnt || i < 0 || i >= N) {
+        for (int c = 0; c < C.n; ++c) culled_out(O, c, j, n_in);
+        return;
+    }
+    const float mu[3] = {P.mean[i], P.mean[N + i], P.mean[2 * N + i]};
+    const float ls[3] = {P.log_scale[i], P.log_scale[N + i], P.log_scale[2 * N + i]};
+    const uint32_t maybe = maybe_visible(C, mu, ls);
+    if (!maybe) {
+        for (int c = 0; c < C.n; ++c) culled_out(O, c, j, n_in);
+        return;
+    }
+    project_entry(P, i, j, n_in, C, O, mu, ls, maybe);
+}
+
 // ---------------------------------------------------------------------------
 // Backward: screen-space partials d2 = (d mean2d x, y, d conic a, b, c,
 // d opacity, d rgb r, g, b) of every camera -> parameter gradients.
@@ -343,6 +379,7 @@ struct GradOut {
     float* quat;
     float* opacity_logit;
     float* sh;
+    int overwrite;  // 1: store the reached Gaussians' gradients instead of adding them
 };
 
 // Entries visible in at least one camera, appended to `list` (order is
@@ -519,6 +556,17 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __
                    y * dR[7]);
     const float qd = dq[0] * qn[0] + dq[1] * qn[1] + dq[2] * qn[2] + dq[3] * qn[3];
     const float iq = 1.f / qlen;
+    // (the SH kernel runs after this one and adds its part of the mean
+    // gradient to what is stored here)
+    if (GO.overwrite) {
+        for (int k = 0; k < 4; ++k) GO.quat[int64_t(k) * N + i] = (dq[k] - qd * qn[k]) * iq;
+        for (int k = 0; k < 3; ++k) {
+            GO.mean[int64_t(k) * N + i] = dmu[k];
+            GO.log_scale[int64_t(k) * N + i] = dls[k];
+        }
+        GO.opacity_logit[i] = dlogit;
+        return;
+    }
     for (int k = 0; k < 4; ++k) GO.quat[int64_t(k) * N + i] += (dq[k] - qd * qn[k]) * iq;
     for (int k = 0; k < 3; ++k) {
         GO.mean[int64_t(k) * N + i] += dmu[k];
@@ -583,11 +631,16 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(SceneP P, const int32_t*
         dmu[1] += (gd[1] - dot * y) * il;
         dmu[2] += (gd[2] - dot * z) * il;
     }
-    float old[48];
+    if (GO.overwrite) {
 #pragma unroll
-    for (int o = 0; o < 48; ++o) old[o] = GO.sh[int64_t(o) * N + i];
+        for (int o = 0; o < 48; ++o) GO.sh[int64_t(o) * N + i] = gacc[o];
+    } else {
+        float old[48];
 #pragma unroll
-    for (int o = 0; o < 48; ++o) GO.sh[int64_t(o) * N + i] = old[o] + gacc[o];
+        for (int o = 0; o < 48; ++o) old[o] = GO.sh[int64_t(o) * N + i];
+#pragma unroll
+        for (int o = 0; o < 48; ++o) GO.sh[int64_t(o) * N + i] = old[o] + gacc[o];
+    }
     for (int k = 0; k < 3; ++k) GO.mean[int64_t(k) * N + i] += dmu[k];
 }
 
@@ -660,7 +713,7 @@ int launch_project_bwd(const gs_scene* scene, const int32_t* active_idx, int64_t
     SceneP P{scene->mean, scene->log_scale, scene->quat, scene->opacity_logit, scene->sh, scene->n};
     BwdIn B;
     fill_bwdin(B, d2, proj, n_cams);
-    GradOut G{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh};
+    GradOut G{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->sh, grads->overwrite ? 1 : 0};
     if (n_in == 0) return GS_OK;
     launch("project_bwd", k_project_bwd, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx,
            n_in, list, count, C, B, G);
@@ -713,13 +766,13 @@ extern "C" int gs_project(const gs_scene* scene, const int32_t* active_idx, int6
     uint32_t* list = cv.take<uint32_t>(size_t(n_in));
     uint32_t* count = cv.take<uint32_t>(4);
     if ((rc = fill_u32(count, 0u, 1, stream))) return rc;
-    if (n_in <= kSmallListInput)
-        launch("project_cull", k_project_cull<kChunkSmall>, dim3(unsigned((n_in + kChunkSmall - 1) / kChunkSmall)),
-               dim3(256), 0, stream, P, active_idx, n_in, n_in_dev, C, O, list, count);
-    else
-        launch("project_cull", k_project_cull<kCullChunkLarge>,
-               dim3(unsigned((n_in + kCullChunkLarge - 1) / kCullChunkLarge)), dim3(256), 0, stream, P, active_idx,
-               n_in, n_in_dev, C, O, list, count);
+    if (n_in > kSmallListInput) {
+        launch("project", k_project_all, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx,
+               n_in, n_in_dev, C, O);
+        return check_launch("gs_project");
+    }
+    launch("project_cull", k_project_cull<kChunkSmall>, dim3(unsigned((n_in + kChunkSmall - 1) / kChunkSmall)),
+           dim3(256), 0, stream, P, active_idx, n_in, n_in_dev, C, O, list, count);
     launch("project", k_project, dim3(unsigned((n_in + 255) / 256)), dim3(256), 0, stream, P, active_idx, n_in,
            static_cast<const uint32_t*>(list), static_cast<const uint32_t*>(count), C, O);
     return check_launch("gs_project");

@@ -385,6 +385,10 @@ __global__ __launch_bounds__(64) void k_render_bwd(RenderCams A, const uint32_t*
 // w and the composited count of Gaussian j accumulate in one 8-byte record
 // wa[2j], wa[2j+1] (the count as a float, exact below 2^24), so that one
 // atomic instruction of two lanes updates both.
+// FOOTPRINT: the count is every pixel (inside the image) whose kernel value
+// passes the 1/255 test, composited or not, so the loop runs over the whole
+// list instead of ending when every pixel has stopped.
+template <bool FOOTPRINT>
 __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uint32_t* __restrict__ vals,
                                                          const uint32_t* __restrict__ ranges, uint32_t n_tiles,
                                                          float* __restrict__ wa) {
@@ -403,8 +407,11 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
     const int lane = threadIdx.x;
     RawRec R = {};
     fetch_record(rec, vals, t.start, t.end, lane, R);
+    float cthr[4];  // footprint count: 1/255 inside the image
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cthr[r] = t.valid[r] ? kAlphaMin : 2.f;
     for (uint32_t b0 = t.start; b0 < t.end; b0 += 64) {
-        if (__all(thr[0] > 1.f && thr[1] > 1.f && thr[2] > 1.f && thr[3] > 1.f)) break;
+        if (!FOOTPRINT && __all(thr[0] > 1.f && thr[1] > 1.f && thr[2] > 1.f && thr[3] > 1.f)) break;
         const uint32_t nb = min(64u, t.end - b0);
         __syncthreads();
         if (uint32_t(lane) < nb) {
@@ -433,7 +440,10 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
                 const bool stop = ok && (Tn < kTMin);
                 const bool comp = ok && !stop;
                 sw += comp ? alpha * T[r] : 0.f;
-                sn += comp ? 1.f : 0.f;
+                if (FOOTPRINT)
+                    sn += ((e2 <= 0.f) && (alpha >= cthr[r])) ? 1.f : 0.f;
+                else
+                    sn += comp ? 1.f : 0.f;
                 T[r] = comp ? Tn : T[r];
                 thr[r] = stop ? 2.f : thr[r];
             }
@@ -451,7 +461,7 @@ __global__ __launch_bounds__(64) void k_importance_blend(RenderCams A, const uin
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-            if (__all(thr[0] > 1.f && thr[1] > 1.f && thr[2] > 1.f && thr[3] > 1.f)) break;
+            if (!FOOTPRINT && __all(thr[0] > 1.f && thr[1] > 1.f && thr[2] > 1.f && thr[3] > 1.f)) break;
         }
     }
 }
@@ -478,14 +488,18 @@ int fill_render_cams(const gs_projected* proj, const gs_camera* cams, int n_cams
 }
 
 int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, const uint32_t* vals,
-                            const uint32_t* ranges, float* wa, hipStream_t stream) {
+                            const uint32_t* ranges, float* wa, int footprint, hipStream_t stream) {
     RenderCams A;
     int64_t tt = 0;
     int rc = fill_render_cams(proj, cam, 1, A, &tt);
     if (rc) return rc;
     if (tt == 0) return GS_OK;
-    launch("importance_blend", k_importance_blend, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals, ranges,
-           uint32_t(tt), wa);
+    if (footprint)
+        launch("importance_blend", k_importance_blend<true>, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals,
+               ranges, uint32_t(tt), wa);
+    else
+        launch("importance_blend", k_importance_blend<false>, dim3(unsigned(tt)), dim3(64), 0, stream, A, vals,
+               ranges, uint32_t(tt), wa);
     return check_launch("importance blend");
 }
 

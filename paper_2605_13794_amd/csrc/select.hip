@@ -595,7 +595,7 @@ size_t ws_score_keep(int64_t n) {
 
 namespace gsmi {
 int launch_importance_blend(const gs_projected* proj, const gs_camera* cam, const uint32_t* vals,
-                            const uint32_t* ranges, float* wa, hipStream_t stream);
+                            const uint32_t* ranges, float* wa, int footprint, hipStream_t stream);
 }
 
 static int lod_mask_checks(const gs_scene* scene, const gs_camera* cam, const gs_lod_params* params,
@@ -709,14 +709,16 @@ extern "C" int gs_lod_mask_noalloc(const gs_scene* scene, const gs_camera* cam, 
 }
 
 extern "C" int gs_importance(const gs_projected* proj, const gs_camera* cam, int64_t n, const uint32_t* vals,
-                             const uint32_t* tile_ranges, float mass_frac, float eps, float* w, uint32_t* a,
-                             float* score, uint32_t* c_rad, uint32_t* c_vis, uint32_t* cull_row, void* ws,
-                             size_t ws_bytes, hipStream_t stream) {
+                             const uint32_t* tile_ranges, float mass_frac, float eps, int32_t count_mode, float* w,
+                             uint32_t* a, float* score, uint32_t* c_rad, uint32_t* c_vis, uint32_t* cull_row,
+                             void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!proj || !cam || !tile_ranges || !w || !a || !score || !c_rad || !c_vis || !cull_row)
         return fail(GS_ERR_INVALID_ARG, "gs_importance: null argument");
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(GS_ERR_INVALID_ARG, "gs_importance: bad n");
     if (!(mass_frac > 0.f) || mass_frac > 1.f) return fail(GS_ERR_INVALID_ARG, "gs_importance: mass_frac in (0, 1]");
     if (!proj->radius) return fail(GS_ERR_INVALID_ARG, "gs_importance: null radius");
+    if (count_mode != GS_COUNT_COMPOSITED && count_mode != GS_COUNT_FOOTPRINT)
+        return fail(GS_ERR_INVALID_ARG, "gs_importance: unknown count mode %d", count_mode);
     const size_t need = ws_importance(n);
     if (!ws || ws_bytes < need || !aligned(ws, 256))
         return fail(GS_ERR_WORKSPACE, "gs_importance: workspace needs %zu bytes (256-aligned)", need);
@@ -725,7 +727,8 @@ extern "C" int gs_importance(const gs_projected* proj, const gs_camera* cam, int
     Carve cv(ws);
     float* wa = cv.take<float>(size_t(2 * n));
     if ((rc = fill_u32(wa, 0u, size_t(2 * n), stream))) return rc;
-    if ((rc = launch_importance_blend(proj, cam, vals, tile_ranges, wa, stream))) return rc;
+    if ((rc = launch_importance_blend(proj, cam, vals, tile_ranges, wa, count_mode == GS_COUNT_FOOTPRINT, stream)))
+        return rc;
     const int64_t nbs = (n + kBlk - 1) / kBlk;
     launch("importance_split", k_importance_split, dim3(unsigned(nbs)), dim3(256), 0, stream,
            static_cast<const float2*>(static_cast<void*>(wa)), n, w, a);
@@ -946,4 +949,16 @@ extern "C" int gs_spawn_stub_score(const gs_scene* scene, const int32_t* parent,
     launch("spawn_stub", k_spawn_stub, dim3(unsigned((n + kBlk - 1) / kBlk)), dim3(256), 0, stream,
            scene->opacity_logit, parent, n, p);
     return check_launch("gs_spawn_stub_score");
+}
+
+// Coarse-to-fine ceiling L_max(t) of the level gate (host arithmetic).
+extern "C" int32_t gs_lod_level_ceiling(int64_t t, int64_t t0, int64_t t1, int32_t n_levels) {
+    if (n_levels <= 1 || t <= t0) return 0;
+    if (t >= t1) return n_levels - 1;
+    int32_t best = 0;
+    for (int32_t k = 0; k < n_levels; ++k) {
+        const double u = double(t0) * std::pow(double(t1) / double(t0), double(k) / double(n_levels - 1));
+        if (u <= double(t)) best = k;
+    }
+    return best;
 }

@@ -21,6 +21,7 @@ GS_ERR_WORKSPACE = -3
 GS_ERR_HIP = -4
 
 GS_LOD_NONE, GS_LOD_LEVEL, GS_LOD_RADIUS = 0, 1, 2
+GS_COUNT_COMPOSITED, GS_COUNT_FOOTPRINT = 0, 1
 (GS_OP_LOD_MASK, GS_OP_BIN_SORT, GS_OP_RENDER_BWD, GS_OP_IMPORTANCE, GS_OP_SCORE_KEEP, GS_OP_L1_LOSS,
  GS_OP_SIMPLIFY, GS_OP_PHOTO_LOSS, GS_OP_SCALE_REG, GS_OP_PROJECT, GS_OP_VOXEL_LEVELS, GS_OP_SPAWN_GATE) = range(12)
 GS_MAX_CAMS = 8
@@ -31,7 +32,7 @@ EXPORTED = ("gs_workspace_size", "gs_last_error", "gs_num_tiles", "gs_lod_mask",
             "gs_render_fwd", "gs_render_bwd", "gs_importance", "gs_score_keep_bits", "gs_l1_loss",
             "gs_adam_step", "gs_profile_kernel", "gs_mass_keep_bits", "gs_sample_keep_bits", "gs_compact",
             "gs_photo_loss", "gs_scale_reg", "gs_lod_mask_noalloc", "gs_voxel_levels", "gs_spawn_gate",
-            "gs_spawn_stub_score")
+            "gs_spawn_stub_score", "gs_lod_level_ceiling")
 
 c_int, c_i32, c_i64, c_f, c_p, c_sz = (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                        ctypes.c_void_p, ctypes.c_size_t)
@@ -53,7 +54,8 @@ class GsProjected(ctypes.Structure):
 
 
 class GsGrads(ctypes.Structure):
-    _fields_ = [("mean", c_p), ("log_scale", c_p), ("quat", c_p), ("opacity_logit", c_p), ("sh", c_p)]
+    _fields_ = [("mean", c_p), ("log_scale", c_p), ("quat", c_p), ("opacity_logit", c_p), ("sh", c_p),
+                ("overwrite", c_i32)]
 
 
 class GsLodParams(ctypes.Structure):
@@ -83,11 +85,13 @@ def lib() -> ctypes.CDLL:
         L.gs_voxel_levels.argtypes = [P, c_i64, P, c_f, c_i32, P, P, c_sz, P]
         L.gs_spawn_gate.argtypes = [P, P, P, c_i64, P, P, c_i64, ctypes.c_double, c_i32, P, P, P, P, P, c_sz, P]
         L.gs_spawn_stub_score.argtypes = [P, P, c_i64, P, P]
+        L.gs_lod_level_ceiling.argtypes = [c_i64, c_i64, c_i64, c_i32]
+        L.gs_lod_level_ceiling.restype = c_i32
         L.gs_project.argtypes = [P, P, c_i64, P, P, c_int, P, P, c_sz, P]
         L.gs_bin_sort.argtypes = [P, P, c_int, c_i64, P, P, c_i64, P, P, P, c_sz, P]
         L.gs_render_fwd.argtypes = [P, P, c_int, P, P, P, P, P, P, P, P, P]
         L.gs_render_bwd.argtypes = [P, P, c_i64, P, P, P, c_int, P, P, P, P, P, P, P, P, P, P, P, c_sz, P]
-        L.gs_importance.argtypes = [P, P, c_i64, P, P, c_f, c_f, P, P, P, P, P, P, P, c_sz, P]
+        L.gs_importance.argtypes = [P, P, c_i64, P, P, c_f, c_f, c_i32, P, P, P, P, P, P, P, c_sz, P]
         L.gs_score_keep_bits.argtypes = [P, c_i64, c_i64, P, P, c_sz, P]
         L.gs_l1_loss.argtypes = [P, P, c_i64, P, P, P, P, c_sz, P]
         L.gs_adam_step.argtypes = [P, P, P, P, P, c_int, P, c_f, c_f, c_f, c_int, P, c_int, P]
@@ -98,7 +102,7 @@ def lib() -> ctypes.CDLL:
         L.gs_photo_loss.argtypes = [P, P, c_i32, c_i32, c_f, c_f, P, P, P, c_sz, P]
         L.gs_scale_reg.argtypes = [P, P, c_i64, P, P, c_f, P, P, P, c_sz, P]
         for name in EXPORTED:
-            if name not in ("gs_workspace_size", "gs_last_error", "gs_num_tiles"):
+            if name not in ("gs_workspace_size", "gs_last_error", "gs_num_tiles", "gs_lod_level_ceiling"):
                 getattr(L, name).restype = c_int
         _lib = L
     return _lib
@@ -169,10 +173,11 @@ def projected(rec, depth, radius, tiles_touched, clamp_bits, mean2d=None, conic=
     return p
 
 
-def grads(mean, log_scale, quat, opacity_logit, sh) -> GsGrads:
+def grads(mean, log_scale, quat, opacity_logit, sh, overwrite: bool = False) -> GsGrads:
     g = GsGrads()
     g.mean, g.log_scale, g.quat, g.opacity_logit, g.sh = (ptr(mean), ptr(log_scale), ptr(quat),
                                                           ptr(opacity_logit), ptr(sh))
+    g.overwrite = 1 if overwrite else 0
     return g
 
 
@@ -255,10 +260,11 @@ def gs_render_bwd(scn: GsScene, active_idx, n_in, n_in_dev, projs, cams, vals, t
 
 
 def gs_importance(proj: GsProjected, cam: GsCamera, n, vals, tile_ranges, mass_frac, eps, w, a, score, c_rad, c_vis,
-                  cull_row, ws, stream=None):
+                  cull_row, ws, stream=None, count_mode=0):
     _check(lib().gs_importance(ctypes.byref(proj), ctypes.byref(cam), int(n), ptr(vals), ptr(tile_ranges),
-                               float(mass_frac), float(eps), ptr(w), ptr(a), ptr(score), ptr(c_rad), ptr(c_vis),
-                               ptr(cull_row), ptr(ws), ws.numel(), stream_handle(stream)), "gs_importance")
+                               float(mass_frac), float(eps), int(count_mode), ptr(w), ptr(a), ptr(score), ptr(c_rad),
+                               ptr(c_vis), ptr(cull_row), ptr(ws), ws.numel(), stream_handle(stream)),
+           "gs_importance")
 
 
 def gs_score_keep_bits(score, n, n_drop, keep_bits, ws, stream=None):
@@ -281,6 +287,10 @@ def gs_spawn_gate(lod, clone_parent, p_clone, n_clone, split_parent, p_split, n_
                                ptr(child_lod), ptr(child_split), ctypes.byref(out), ptr(ws), ws.numel(),
                                stream_handle(stream)), "gs_spawn_gate")
     return int(out.value)
+
+
+def gs_lod_level_ceiling(t, t0, t1, n_levels) -> int:
+    return int(lib().gs_lod_level_ceiling(int(t), int(t0), int(t1), int(n_levels)))
 
 
 def gs_spawn_stub_score(scn: GsScene, parent, n, p, stream=None):

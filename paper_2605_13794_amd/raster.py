@@ -242,7 +242,7 @@ class RasterizeFn(torch.autograd.Function):
                                "transmittance no longer belong to this graph (use one frame per graph)")
         gr = [torch.zeros_like(p) for p in ctx.params]
         grad_out = grad_out.contiguous()
-        frame.backward(ctx.scn, G.grads(*gr), grad_rgb=list(grad_out.unbind(0)))
+        frame.backward(ctx.scn, G.grads(*gr, overwrite=True), grad_rgb=list(grad_out.unbind(0)))
         return (None, None, *gr, None, None)
 
 

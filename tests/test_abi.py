@@ -88,3 +88,12 @@ def test_noalloc_gate_refuses_oversized_input_on_the_host(G):
                                      None)
     assert rc == G.GS_ERR_INVALID_ARG
     assert "exceeds the fixed scratch" in G.lib().gs_last_error().decode()
+
+
+def test_level_ceiling_matches_reference(G):
+    """L_max(t) of the library (host arithmetic) against the reference
+    schedule: geometric unlock times between t0 and t1."""
+    from oracle import levels as LV
+    for t0, t1, K in ((2000, 32000, 5), (1000, 128000, 8), (500, 90000, 12), (5, 50, 1), (24000, 32000, 3)):
+        for t in list(range(0, t1 + 2000, max(1, (t1 + 2000) // 997))) + [t0, t1, t0 - 1, t1 - 1, t1 + 1]:
+            assert G.gs_lod_level_ceiling(t, t0, t1, K) == LV.level_ceiling(t, t0, t1, K), (t, t0, t1, K)

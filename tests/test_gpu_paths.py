@@ -273,3 +273,32 @@ def test_rasterize_stale_frame_raises(oracle):
     second.sum().backward()     # the latest forward still differentiates
     torch.cuda.synchronize()
     assert ds.mean.grad is not None and torch.isfinite(ds.mean.grad).all()
+
+
+def test_backward_overwrite_mode():
+    """gs_grads.overwrite = 1 stores the reached Gaussians' gradients: equal
+    to accumulating into zeros (up to the last bits of the blend's float
+    atomics, which differ between two backward calls), and Gaussians the view
+    does not reach keep whatever their arrays held."""
+    from paper_2605_13794_amd.raster import DeviceScene
+    dev = device()
+    G = gsmi()
+    sc = S.city_scene(200_000, seed=31)
+    cam = S.aerial_camera(480, 270, 20.0)
+    ds = DeviceScene(sc, dev)
+    fr = _frame([cam], sc.n, dev)
+    fr.forward(ds.struct())
+    tgt = torch.from_numpy(S.target_image(480, 270, seed=3)).to(dev)
+    fr.l1_loss([tgt])
+    acc = [torch.zeros_like(p) for p in ds.params()]
+    fr.backward(ds.struct(), G.grads(*acc))
+    over = [torch.full_like(p, 7.0) for p in ds.params()]
+    fr.backward(ds.struct(), G.grads(*over, overwrite=True))
+    torch.cuda.synchronize()
+    reached = (fr.proj[0].radius[:sc.n] > 0)
+    assert 0 < int(reached.sum()) < sc.n
+    for a, o in zip(acc, over):
+        a2, o2 = a.reshape(-1, sc.n), o.reshape(-1, sc.n)
+        ar, orr = a2[:, reached], o2[:, reached]
+        assert float((ar - orr).abs().max()) <= 1e-5 * float(ar.abs().max())
+        assert bool((o2[:, ~reached] == 7.0).all())
