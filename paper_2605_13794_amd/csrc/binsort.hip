@@ -455,15 +455,16 @@ __global__ __launch_bounds__(256) void k_bin_hist(const uint32_t* __restrict__ d
     }
 }
 
-// Per block of 256 depth-sorted visible entries: their pair count.
-__global__ __launch_bounds__(256) void k_emit_reduce(const uint4* __restrict__ vrec, const uint32_t* __restrict__ dval,
+// Per block of 256 depth-sorted visible entries (their records in depth
+// order, written by the last depth pass): their pair count.
+__global__ __launch_bounds__(256) void k_emit_reduce(const uint4* __restrict__ srec,
                                                      const uint32_t* __restrict__ n_sorted,
                                                      uint32_t* __restrict__ sums) {
     __shared__ uint32_t lds4[4];
     const uint32_t n_v = n_sorted[1];
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
     if (blockIdx.x * 256u >= n_v) return;  // uniform per block
-    const uint32_t cnt = i < n_v ? vrec[dval[i]].w : 0u;
+    const uint32_t cnt = i < n_v ? srec[i].w : 0u;
     uint32_t tot;
     block_excl_scan(cnt, lds4, &tot);
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
@@ -482,8 +483,7 @@ __global__ __launch_bounds__(kScanWgThreads) void k_scan_sums(uint32_t* __restri
 // block's pairs are written as one contiguous run, spread over all threads;
 // clears the first tile pass's status.  (The tile-digit histograms come from
 // k_bin_hist.)
-__global__ __launch_bounds__(256) void k_emit_sorted(const uint4* __restrict__ vrec, const uint32_t* __restrict__ dkey,
-                                                     const uint32_t* __restrict__ dval,
+__global__ __launch_bounds__(256) void k_emit_sorted(const uint4* __restrict__ srec, const uint32_t* __restrict__ dkey,
                                                      const uint32_t* __restrict__ n_sorted,
                                                      const uint32_t* __restrict__ offs, uint64_t* __restrict__ keys,
                                                      uint32_t* __restrict__ vals, int part,
@@ -502,7 +502,7 @@ __global__ __launch_bounds__(256) void k_emit_sorted(const uint4* __restrict__ v
     uint4 r = make_uint4(0u, 0u, 1u, 0u);
     uint32_t db = 0;
     if (i < n_v) {
-        r = vrec[dval[i]];
+        r = srec[i];
         db = dkey[i];
     }
     uint32_t tot;
@@ -547,6 +547,8 @@ struct SortLds {
 // 170 VGPRs, two wavefronts; 168 and three match its LDS limit of three
 // workgroups per compute unit): 142 -> 121 us per pass at 13.5M pairs.
 // KeyT: uint64_t (pairs) or uint32_t (depth keys of the depth-first path).
+// With gather_src set, the pass writes gather_dst[g] = gather_src[value]
+// instead of the value (the last depth pass: the records in depth order).
 template <int IPT, typename KeyT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_sort_pass(const KeyT* __restrict__ keys_in,
                                                    const uint32_t* __restrict__ vals_in,
@@ -555,7 +557,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                                    const uint32_t* __restrict__ hist_pass,
                                                    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
                                                    uint32_t* __restrict__ counter, uint32_t* __restrict__ err,
-                                                   int shift) {
+                                                   int shift, const uint4* __restrict__ gather_src,
+                                                   uint4* __restrict__ gather_dst) {
     constexpr int kSortPerThread = IPT;
     constexpr int kPart = kSortThreads * IPT;
     __shared__ SortLds<IPT, KeyT> L;
@@ -580,7 +583,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         const uint32_t stride = gridDim.x * kSortThreads;
         for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n; i += stride) {
             keys_out[i] = keys_in[i];
-            vals_out[i] = vals_in[i];
+            if (gather_src) gather_dst[i] = gather_src[vals_in[i]];
+            else vals_out[i] = vals_in[i];
         }
         if (status_next)
             for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n_parts * 256u; i += stride) status_next[i] = 0;
@@ -642,14 +646,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             L.bin_start[tid] = ex;
         }
 
-        // 3. decoupled look-back for bin tid
+        // 3a. publish this partition's count of bin tid at once (successors
+        // may be waiting for it); partition 0's count is already inclusive
+        uint32_t* st = status + size_t(part) * 256 + tid;
+        st_agent(st, (part == 0 ? kFlagInc : kFlagAgg) | total);
+        __syncthreads();
+
+        // 4. stage in LDS in (digit, input order) order (before the look-back,
+        // so that the loaded keys are no longer live during the wait)
+#pragma unroll
+        for (int it = 0; it < kSortPerThread; ++it) {
+            const uint32_t idx = wbase + uint32_t(it) * 64 + lane;
+            if (idx < n) {
+                const uint32_t d = uint32_t(k_[it] >> shift) & 255u;
+                const uint32_t lp = L.bin_start[d] + L.wcnt[w][d] + rank_[it];
+                L.keys[lp] = k_[it];
+                L.vals[lp] = v_[it];
+            }
+        }
+
+        // 3b. decoupled look-back for bin tid
         {
-            uint32_t* st = status + size_t(part) * 256 + tid;
             uint32_t excl = 0;
-            if (part == 0) {
-                st_agent(st, kFlagInc | total);
-            } else {
-                st_agent(st, kFlagAgg | total);
+            if (part > 0) {
                 // Walk back kLookWin predecessors per round trip: their status
                 // words are loaded together, then consumed in order up to the
                 // first inclusive prefix (done) or the first one not yet
@@ -689,19 +708,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         }
         __syncthreads();
 
-        // 4. stage in LDS in (digit, input order) order
-#pragma unroll
-        for (int it = 0; it < kSortPerThread; ++it) {
-            const uint32_t idx = wbase + uint32_t(it) * 64 + lane;
-            if (idx < n) {
-                const uint32_t d = uint32_t(k_[it] >> shift) & 255u;
-                const uint32_t lp = L.bin_start[d] + L.wcnt[w][d] + rank_[it];
-                L.keys[lp] = k_[it];
-                L.vals[lp] = v_[it];
-            }
-        }
-        __syncthreads();
-
         // 5. coalesced write-out
         const uint32_t cnt = min<uint32_t>(kPart, n - part * kPart);
         for (uint32_t i = tid; i < cnt; i += 256) {
@@ -710,7 +716,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             const uint32_t g = L.gbase[d] + i;
             if (g < n) {  // always true unless a look-back wait timed out
                 keys_out[g] = key;
-                vals_out[g] = L.vals[i];
+                if (gather_src) gather_dst[g] = gather_src[L.vals[i]];
+                else vals_out[g] = L.vals[i];
             }
         }
         if (one_each) break;
@@ -963,7 +970,8 @@ struct SortWs {
     uint32_t* block_sums;
     uint32_t* vis_sums;   // depth-first path only
     uint32_t* emit_sums;  // depth-first path only
-    uint4* vrec;          // depth-first path only
+    uint4* vrec;          // depth-first path only: records in entry order
+    uint4* srec;          // depth-first path only: records in depth order
     uint32_t* n_sorted;
     uint32_t* hist;
     uint32_t* counters;
@@ -992,6 +1000,7 @@ static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity, int64_t n_
     s.vis_sums = depth_first ? cv.take<uint32_t>(size_t(nb)) : nullptr;
     s.emit_sums = depth_first ? cv.take<uint32_t>(size_t(nb)) : nullptr;
     s.vrec = depth_first ? cv.take<uint4>(size_t(n_total > 0 ? n_total : 1)) : nullptr;
+    s.srec = depth_first ? cv.take<uint4>(size_t(n_total > 0 ? n_total : 1)) : nullptr;
     s.n_sorted = cv.take<uint32_t>(4);
     s.hist = cv.take<uint32_t>(8 * 256);
     s.counters = cv.take<uint32_t>(8);
@@ -1170,11 +1179,13 @@ extern "C" int gs_voxel_levels(const float* mean, int64_t n, const float* origin
         if (small)
             launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
                    V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
-                   static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p);
+                   static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
+                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr));
         else
             launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
                    V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
-                   static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p);
+                   static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
+                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr));
     }
     launch("voxel_label", k_voxel_label, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream,
            static_cast<const uint64_t*>(V.keys[0]), static_cast<const uint32_t*>(V.vals[0]), n, int(n_levels),
@@ -1249,11 +1260,13 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         if (small)
             launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
                    vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
-                   S.counters + counter, S.err, 32 + 8 * q);
+                   S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
+                   static_cast<uint4*>(nullptr));
         else
             launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
                    vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
-                   S.counters + counter, S.err, 32 + 8 * q);
+                   S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
+                   static_cast<uint4*>(nullptr));
     };
 
     if (!per_tile) {
@@ -1280,25 +1293,26 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         for (int p = 0; p < 4; ++p) {
             uint32_t* st_next = p < 3 ? S.status[(p + 1) & 1] : nullptr;
             const int a = p & 1, b = a ^ 1;
+            // the last pass writes the records in depth order instead of the ranks
+            const uint4* gsrc = p == 3 ? static_cast<const uint4*>(S.vrec) : nullptr;
+            uint4* gdst = p == 3 ? S.srec : nullptr;
             if (small_d)
                 launch("sort_pass", k_sort_pass<kIptSmall, uint32_t>, dim3(grid_d), dim3(kSortThreads), 0, stream,
                        dk[a], dv[a], dk[b], dv[b], S.n_sorted + 1, S.hist + p * 256, S.status[p & 1], st_next,
-                       S.counters + p, S.err, 8 * p);
+                       S.counters + p, S.err, 8 * p, gsrc, gdst);
             else
                 launch("sort_pass", k_sort_pass<kIptLarge, uint32_t>, dim3(grid_d), dim3(kSortThreads), 0, stream,
                        dk[a], dv[a], dk[b], dv[b], S.n_sorted + 1, S.hist + p * 256, S.status[p & 1], st_next,
-                       S.counters + p, S.err, 8 * p);
+                       S.counters + p, S.err, 8 * p, gsrc, gdst);
         }
         if (nb > 0) {
             launch("emit_reduce", k_emit_reduce, dim3(unsigned(nb)), dim3(256), 0, stream,
-                   static_cast<const uint4*>(S.vrec), static_cast<const uint32_t*>(dv[0]),
-                   static_cast<const uint32_t*>(S.n_sorted), S.emit_sums);
+                   static_cast<const uint4*>(S.srec), static_cast<const uint32_t*>(S.n_sorted), S.emit_sums);
             hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanWgThreads), 0, stream, S.emit_sums,
                                static_cast<const uint32_t*>(S.n_sorted));
-            launch("emit", k_emit_sorted, dim3(unsigned(nb)), dim3(256), 0, stream, static_cast<const uint4*>(S.vrec),
-                   static_cast<const uint32_t*>(dk[0]), static_cast<const uint32_t*>(dv[0]),
-                   static_cast<const uint32_t*>(S.n_sorted), static_cast<const uint32_t*>(S.emit_sums), kb[z], vb[z],
-                   part, S.status[0]);
+            launch("emit", k_emit_sorted, dim3(unsigned(nb)), dim3(256), 0, stream, static_cast<const uint4*>(S.srec),
+                   static_cast<const uint32_t*>(dk[0]), static_cast<const uint32_t*>(S.n_sorted),
+                   static_cast<const uint32_t*>(S.emit_sums), kb[z], vb[z], part, S.status[0]);
         }
         int cur = z;
         for (int q = 0; q < tile_passes; ++q) {
