@@ -44,7 +44,9 @@ extern "C" {
 enum {
     GS_OK = 0,
     GS_ERR_INVALID_ARG = -1, /* null/misaligned pointer, bad size or count */
-    GS_ERR_CAPACITY = -2,    /* reserved for host-checked capacity misses */
+    GS_ERR_CAPACITY = -2,    /* not returned by the asynchronous calls: a pair-buffer overflow is
+                                only known on the device and is reported through the device count
+                                (gs_bin_sort: *n_pairs_dev > capacity, every tile range empty) */
     GS_ERR_WORKSPACE = -3,   /* ws_bytes below gs_workspace_size() */
     GS_ERR_HIP = -4          /* a HIP launch failed; see gs_last_error() */
 };
