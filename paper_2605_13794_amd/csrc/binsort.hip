@@ -16,8 +16,8 @@ constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 24;
 
-constexpr int kScanIters = 1;
-constexpr int kScanItems = kScanThreads * kScanIters;  // entries per block
+constexpr int kScanItems = kScanThreads;  // entries per block (per round of a larger block)
+constexpr int kScanItLong = 8;            // rounds per block of a long depth-first input
 
 struct EmitIn {
     const float* rec[GS_MAX_CAMS];
@@ -30,6 +30,37 @@ struct EmitIn {
     int n_cams;
     int64_t n_in;  // entries per camera
 };
+
+// Per-camera input pointers staged in LDS.  Indexing the kernel-argument
+// arrays with a per-lane camera index loads the pointer from memory, and that
+// load shares the in-order counter of the data loads behind it, so a kernel
+// that issues several rounds of loads would wait after each pointer.
+// The pointers keep the global address space: read back from LDS, plain
+// pointers would be generic, and generic loads make every wait a full one.
+#define GS_GLOBAL __attribute__((address_space(1)))
+struct CamPtrs {
+    const float GS_GLOBAL* rec[GS_MAX_CAMS];
+    const float GS_GLOBAL* depth[GS_MAX_CAMS];
+    const int32_t GS_GLOBAL* radius[GS_MAX_CAMS];
+    const uint32_t GS_GLOBAL* tiles[GS_MAX_CAMS];
+    uint32_t tile_off[GS_MAX_CAMS];
+    int32_t TX[GS_MAX_CAMS];
+    int32_t TY[GS_MAX_CAMS];
+};
+
+__device__ __forceinline__ void stage_cam_ptrs(const EmitIn& E, CamPtrs& P) {
+    const int t = threadIdx.x;
+    if (t < GS_MAX_CAMS) {
+        P.rec[t] = (const float GS_GLOBAL*)E.rec[t];
+        P.depth[t] = (const float GS_GLOBAL*)E.depth[t];
+        P.radius[t] = (const int32_t GS_GLOBAL*)E.radius[t];
+        P.tiles[t] = (const uint32_t GS_GLOBAL*)E.tiles[t];
+        P.tile_off[t] = E.tile_off[t];
+        P.TX[t] = E.TX[t];
+        P.TY[t] = E.TY[t];
+    }
+    __syncthreads();
+}
 
 __device__ __forceinline__ uint32_t tiles_of(const EmitIn& E, int64_t e) {
     const int c = int(e / E.n_in);
@@ -68,21 +99,29 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds4, 
     return before + inc - v;
 }
 
-// Per block of 256 entries: the number of pairs and, if vis_sums is set, the
-// number of visible entries (tile count > 0).
+// Per block of 256 * ITERS entries: the number of pairs and, if vis_sums is
+// set, the number of visible entries (tile count > 0).  All tile counts are
+// loaded before the first is used (index clamped to the last entry).
+template <int ITERS>
 __global__ __launch_bounds__(256) void k_scan_reduce(EmitIn E, int64_t n_total, uint32_t* __restrict__ block_sums,
                                                      uint32_t* __restrict__ vis_sums) {
     __shared__ uint32_t lds4[4];
-    const int64_t base = int64_t(blockIdx.x) * kScanItems;
+    __shared__ CamPtrs P;
+    stage_cam_ptrs(E, P);
+    const int64_t base = int64_t(blockIdx.x) * (kScanThreads * ITERS) + threadIdx.x;
+    uint32_t c_[ITERS];
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const int64_t e = min<int64_t>(base + it * kScanThreads, n_total - 1);
+        const int c = int(e / E.n_in);
+        c_[it] = P.tiles[c][e - int64_t(c) * E.n_in];
+    }
     uint32_t acc = 0, vis = 0;
-#pragma unroll 4
-    for (int it = 0; it < kScanIters; ++it) {
-        const int64_t e = base + int64_t(it) * kScanThreads + threadIdx.x;
-        if (e < n_total) {
-            const uint32_t c = tiles_of(E, e);
-            acc += c;
-            vis += c > 0u;
-        }
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const uint32_t c = base + it * kScanThreads < n_total ? c_[it] : 0u;
+        acc += c;
+        vis += c > 0u;
     }
     uint32_t tot;
     block_excl_scan(acc, lds4, &tot);
@@ -177,19 +216,22 @@ __device__ __forceinline__ int64_t fdiv16(int64_t a) { return a >= 0 ? a / 16 : 
 
 // Integer tile rectangle of a visible entry: first global tile, width in
 // tiles, and the camera's tiles per row.
-__device__ __forceinline__ void vis_rect(const EmitIn& E, int c, int64_t j, uint32_t* bt, uint32_t* wd,
-                                         uint32_t* tx) {
-    const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
-    const int64_t r = E.radius[c][j];
+__device__ __forceinline__ void vis_rect_of(uint32_t tile_off, int64_t TX, int64_t TY, float2 q0, int64_t r,
+                                            uint32_t* bt, uint32_t* wd, uint32_t* tx) {
     const int64_t xi = int64_t(floorf(fminf(fmaxf(q0.x, -1073741824.f), 1073741824.f)));
     const int64_t yi = int64_t(floorf(fminf(fmaxf(q0.y, -1073741824.f), 1073741824.f)));
-    const int64_t TX = E.TX[c], TY = E.TY[c];
     const int64_t x0 = min<int64_t>(max<int64_t>(fdiv16(xi - r), 0), TX);
     const int64_t x1 = min<int64_t>(max<int64_t>(fdiv16(xi + r) + 1, 0), TX);
     const int64_t y0 = min<int64_t>(max<int64_t>(fdiv16(yi - r), 0), TY);
-    *bt = uint32_t(E.tile_off[c]) + uint32_t(y0 * TX + x0);
+    *bt = tile_off + uint32_t(y0 * TX + x0);
     *wd = uint32_t(max<int64_t>(x1 - x0, 1));
     *tx = uint32_t(TX);
+}
+
+__device__ __forceinline__ void vis_rect(const EmitIn& E, int c, int64_t j, uint32_t* bt, uint32_t* wd,
+                                         uint32_t* tx) {
+    const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
+    vis_rect_of(E.tile_off[c], E.TX[c], E.TY[c], make_float2(q0.x, q0.y), E.radius[c][j], bt, wd, tx);
 }
 
 
@@ -275,9 +317,9 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
         for (uint32_t k = blockIdx.x * 256 + tid; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
     }
     for (int k = tid; k < passes * 256; k += 256) (&h[0][0])[k] = 0;
-    uint32_t run = block_offs[blockIdx.x];
-    for (int it = 0; it < kScanIters; ++it) {
-        const int64_t e = base + int64_t(it) * kScanThreads + tid;
+    const uint32_t run = block_offs[blockIdx.x];
+    {
+        const int64_t e = base + tid;
         int c = 0;
         int64_t j = 0;
         uint32_t cnt = 0;
@@ -303,7 +345,6 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
         __syncthreads();
         emit_block_pairs(L, h, tot, run, keys, vals, passes, shift0);
         __syncthreads();
-        run += tot;
     }
     for (int p = 0; p < passes; ++p) {
         const uint32_t v = h[p][tid];
@@ -322,136 +363,73 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
 // ---------------------------------------------------------------------------
 // Visible-entry record: entry index within its camera, first global tile of
 // the rectangle, rectangle width | camera tiles-per-row << 16, tile count.
-// Compaction of the visible entries (ascending entry order): depth bits and
-// rank for the depth sort, and the entry's record; clears the first depth
-// pass's look-back status.
+// Compaction of the visible entries (ascending entry order): depth bits (the
+// depth sort's keys; its first pass takes the rank from the position) and
+// the entry's record.  Per block of 256 * ITERS entries: the visible ones are
+// listed in LDS in entry order, then read back in list order, so that every
+// load of a round is issued before the first is used and the stores are
+// consecutive.
+template <int ITERS>
 __global__ __launch_bounds__(256) void k_vis_compact(EmitIn E, int64_t n_total, const uint32_t* __restrict__ vis_offs,
                                                      const uint32_t* __restrict__ n_sorted,
-                                                     uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
-                                                     uint4* __restrict__ vrec, int part,
-                                                     uint32_t* __restrict__ status0) {
+                                                     uint32_t* __restrict__ dkey, uint4* __restrict__ vrec) {
     __shared__ uint32_t lds4[4];
+    __shared__ uint32_t list[kScanThreads * ITERS];
+    __shared__ uint32_t lcnt[kScanThreads * ITERS];
+    __shared__ CamPtrs P;
     const uint32_t n_v = n_sorted[1];
     if (n_v == 0) return;  // nothing visible, or the pairs do not fit
+    stage_cam_ptrs(E, P);
     const uint32_t tid = threadIdx.x;
-    {
-        const uint32_t n_parts = (n_v + uint32_t(part) - 1) / uint32_t(part);
-        for (uint32_t k = blockIdx.x * 256 + tid; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
-    }
-    const int64_t e = int64_t(blockIdx.x) * kScanItems + tid;
-    int c = 0;
-    int64_t j = 0;
-    uint32_t cnt = 0;
-    if (e < n_total) {
-        c = int(e / E.n_in);
-        j = e - int64_t(c) * E.n_in;
-        cnt = E.tiles[c][j];
-    }
-    const bool vis = cnt > 0;
-    uint32_t tot;
-    const uint32_t o = vis_offs[blockIdx.x] + block_excl_scan(vis ? 1u : 0u, lds4, &tot);
-    if (vis) {
-        uint32_t bt, wd, tx;
-        vis_rect(E, c, j, &bt, &wd, &tx);
-        dkey[o] = __float_as_uint(E.depth[c][j]);
-        dval[o] = o;
-        vrec[o] = make_uint4(uint32_t(j), bt, wd | (tx << 16), cnt);
-    }
-}
-
-// Digit histograms of the depth-first path in one read of the compacted
-// visible entries (ascending entry order, so a workgroup's rectangles are
-// close together on screen): the four depth-digit histograms, and for every
-// tile pass q the histogram of digit q of the tiles of every rectangle.  A
-// rectangle row is a run of at most 255 consecutive tile ids, so digit 0 of
-// the run is a (cyclic) range of digits, added through a difference array,
-// and every higher digit takes at most two values along the run.  Few
-// workgroups, so that few global atomics meet the same addresses.
-constexpr int kBinHistGroups = 1024;
-
-__global__ __launch_bounds__(256) void k_bin_hist(const uint32_t* __restrict__ dkey, const uint4* __restrict__ vrec,
-                                                  const uint32_t* __restrict__ n_sorted, int tile_passes,
-                                                  uint32_t* __restrict__ hist) {
-    __shared__ uint32_t hd[4][256];
-    __shared__ int32_t dlo[257];
-    __shared__ uint32_t ht[4][256];
-    __shared__ uint32_t uni;
-    const uint32_t tid = threadIdx.x;
-    for (int k = tid; k < 4 * 256; k += 256) {
-        (&hd[0][0])[k] = 0;
-        (&ht[0][0])[k] = 0;
-    }
-    for (int k = tid; k < 257; k += 256) dlo[k] = 0;
-    if (tid == 0) uni = 0;
-    __syncthreads();
-    const uint32_t n_v = n_sorted[1];
-    constexpr int kU = 4;  // items per thread per round, loaded before use
-    const uint32_t stride = gridDim.x * 256;
-    const uint32_t span = (n_v + 255) / 256 * 256;  // whole wavefronts iterate together
-    for (uint32_t i0 = blockIdx.x * 256 + tid; i0 < span; i0 += kU * stride) {
-    uint32_t dbs[kU];
-    uint4 rs[kU];
+    const int64_t base = int64_t(blockIdx.x) * (kScanThreads * ITERS);
+    uint32_t c_[ITERS];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        const uint32_t i = i0 + u * stride;
-        dbs[u] = i < n_v ? dkey[i] : 0u;
-        rs[u] = i < n_v ? vrec[i] : make_uint4(0u, 0u, 1u, 0u);
+    for (int it = 0; it < ITERS; ++it) {
+        const int64_t e = min<int64_t>(base + it * kScanThreads + tid, n_total - 1);
+        const int c = int(e / E.n_in);
+        c_[it] = P.tiles[c][e - int64_t(c) * E.n_in];
+    }
+    uint32_t nv = 0;
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const uint32_t off = uint32_t(it * kScanThreads) + tid;
+        const bool v = base + off < n_total && c_[it] > 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v ? 1u : 0u, lds4, &tot);
+        if (v) {
+            list[nv + ex] = off;
+            lcnt[nv + ex] = c_[it];
+        }
+        nv += tot;
+    }
+    __syncthreads();
+    if (nv == 0) return;  // uniform
+    const uint32_t o0 = vis_offs[blockIdx.x];
+    float2 q_[ITERS];
+    int32_t r_[ITERS];
+    uint32_t d_[ITERS];
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+        const int64_t e = base + list[min(uint32_t(it * kScanThreads) + tid, nv - 1u)];
+        const int c = int(e / E.n_in);
+        const int64_t j = e - int64_t(c) * E.n_in;
+        const float GS_GLOBAL* q = P.rec[c] + j * kRec;
+        q_[it] = make_float2(q[0], q[1]);
+        r_[it] = P.radius[c][j];
+        d_[it] = __float_as_uint(P.depth[c][j]);
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-        const uint32_t i = i0 + u * stride;
-        const bool valid = i < n_v;
-        const uint32_t db = dbs[u];
-        const uint4 r = rs[u];
-        hist_add(hd, uint64_t(db), valid, 4, 0);
-        if (!valid || tile_passes == 0) continue;
-        const uint32_t w = r.z & 0xffffu, tx = r.z >> 16;
-        const uint32_t rows = r.w / w;
-        for (uint32_t dy = 0; dy < rows; ++dy) {
-            const uint32_t s0 = r.y + dy * tx;  // first tile of the row
-            const uint32_t a = s0 & 255u;
-            // digit 0: every digit w / 256 times, then the cyclic range
-            // [a, a + w % 256)
-            const uint32_t rem = w & 255u;
-            if (w >= 256u) atomicAdd(&uni, w >> 8);
-            if (rem) {
-                atomicAdd(&dlo[a], 1);
-                if (a + rem <= 256u) {
-                    atomicAdd(&dlo[a + rem], -1);
-                } else {
-                    atomicAdd(&dlo[256], -1);
-                    atomicAdd(&dlo[0], 1);
-                    atomicAdd(&dlo[a + rem - 256u], -1);
-                }
-            }
-            // digit q >= 1: constant over runs of 256^q consecutive tiles
-            for (int q = 1; q < tile_passes; ++q) {
-                const uint32_t end = s0 + w;
-                for (uint32_t t = s0; t < end;) {
-                    const uint32_t next = min(end, ((t >> (8 * q)) + 1u) << (8 * q));
-                    atomicAdd(&ht[q][(t >> (8 * q)) & 255u], next - t);
-                    t = next;
-                }
-            }
+    for (int it = 0; it < ITERS; ++it) {
+        const uint32_t k = uint32_t(it * kScanThreads) + tid;
+        if (k < nv) {
+            const int64_t e = base + list[k];
+            const int c = int(e / E.n_in);
+            const int64_t j = e - int64_t(c) * E.n_in;
+            uint32_t bt, wd, tx;
+            vis_rect_of(P.tile_off[c], P.TX[c], P.TY[c], q_[it], r_[it], &bt, &wd, &tx);
+            dkey[o0 + k] = d_[it];
+            vrec[o0 + k] = make_uint4(uint32_t(j), bt, wd | (tx << 16), lcnt[k]);
         }
-    }
-    }
-    __syncthreads();
-    if (tile_passes > 0 && tid == 0) {
-        int32_t run = 0;
-        for (int d = 0; d < 256; ++d) {
-            run += dlo[d];
-            ht[0][d] = uint32_t(run) + uni;
-        }
-    }
-    __syncthreads();
-    for (int p = 0; p < 4; ++p) {
-        const uint32_t v = hd[p][tid];
-        if (v) atomicAdd(&hist[p * 256 + tid], v);
-    }
-    for (int q = 0; q < tile_passes; ++q) {
-        const uint32_t v = ht[q][tid];
-        if (v) atomicAdd(&hist[(4 + q) * 256 + tid], v);
     }
 }
 
@@ -480,23 +458,16 @@ __global__ __launch_bounds__(kScanWgThreads) void k_scan_sums(uint32_t* __restri
 }
 
 // Emission in depth order: per block of 256 depth-sorted visible entries, the
-// block's pairs are written as one contiguous run, spread over all threads;
-// clears the first tile pass's status.  (The tile-digit histograms come from
-// k_bin_hist.)
+// block's pairs are written as one contiguous run, spread over all threads.
 __global__ __launch_bounds__(256) void k_emit_sorted(const uint4* __restrict__ srec, const uint32_t* __restrict__ dkey,
                                                      const uint32_t* __restrict__ n_sorted,
                                                      const uint32_t* __restrict__ offs, uint64_t* __restrict__ keys,
-                                                     uint32_t* __restrict__ vals, int part,
-                                                     uint32_t* __restrict__ status0) {
+                                                     uint32_t* __restrict__ vals) {
     __shared__ uint32_t lds4[4];
     __shared__ EmitLds L;
-    const uint32_t n_s = n_sorted[0], n_v = n_sorted[1];
+    const uint32_t n_v = n_sorted[1];
     if (n_v == 0) return;
     const uint32_t tid = threadIdx.x;
-    {
-        const uint32_t n_parts = (n_s + uint32_t(part) - 1) / uint32_t(part);
-        for (uint32_t k = blockIdx.x * 256 + tid; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
-    }
     if (blockIdx.x * 256u >= n_v) return;  // uniform per block
     const uint32_t i = blockIdx.x * 256 + tid;
     uint4 r = make_uint4(0u, 0u, 1u, 0u);
@@ -549,6 +520,7 @@ struct SortLds {
 // KeyT: uint64_t (pairs) or uint32_t (depth keys of the depth-first path).
 // With gather_src set, the pass writes gather_dst[g] = gather_src[value]
 // instead of the value (the last depth pass: the records in depth order).
+// Without vals_in the value of the key at position i is i.
 template <int IPT, typename KeyT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_sort_pass(const KeyT* __restrict__ keys_in,
                                                    const uint32_t* __restrict__ vals_in,
@@ -558,7 +530,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                                    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
                                                    uint32_t* __restrict__ counter, uint32_t* __restrict__ err,
                                                    int shift, const uint4* __restrict__ gather_src,
-                                                   uint4* __restrict__ gather_dst) {
+                                                   uint4* __restrict__ gather_dst,
+                                                   const uint32_t* __restrict__ offs, uint32_t offs_stride) {
     constexpr int kSortPerThread = IPT;
     constexpr int kPart = kSortThreads * IPT;
     __shared__ SortLds<IPT, KeyT> L;
@@ -583,8 +556,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         const uint32_t stride = gridDim.x * kSortThreads;
         for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n; i += stride) {
             keys_out[i] = keys_in[i];
-            if (gather_src) gather_dst[i] = gather_src[vals_in[i]];
-            else vals_out[i] = vals_in[i];
+            const uint32_t v = vals_in ? vals_in[i] : i;
+            if (gather_src) gather_dst[i] = gather_src[v];
+            else vals_out[i] = v;
         }
         if (status_next)
             for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n_parts * 256u; i += stride) status_next[i] = 0;
@@ -594,10 +568,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     // workgroups claim one partition each and the rest leave at once, so the
     // claim counter sees n_parts atomics; a smaller grid loops.
     // A smaller grid loops, claiming one partition at a time.
+    // With offs (the reduce-then-scan form) partitions are independent and
+    // taken in grid-stride order.
     if (blockIdx.x >= n_parts) return;
     const bool one_each = gridDim.x >= n_parts;
+    uint32_t next_part = blockIdx.x;
     for (;;) {
-        if (tid == 0) L.part = atomicAdd(counter, 1u);
+        if (tid == 0) L.part = offs ? next_part : atomicAdd(counter, 1u);
+        next_part += gridDim.x;
         for (int k = tid; k < kWaves * 256; k += 256) (&L.wcnt[0][0])[k] = 0;
         __syncthreads();
         const uint32_t part = L.part;
@@ -609,12 +587,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         KeyT k_[kSortPerThread];
         uint32_t v_[kSortPerThread];
         uint32_t rank_[kSortPerThread];
+        // unconditional loads (index clamped to the last key), all issued
+        // before the ranking; a guarded load would wait on its own
+#pragma unroll
+        for (int it = 0; it < kSortPerThread; ++it) {
+            const uint32_t idx = min(wbase + uint32_t(it) * 64 + lane, n - 1u);
+            k_[it] = keys_in[idx];
+            v_[it] = vals_in ? vals_in[idx] : idx;
+        }
 #pragma unroll
         for (int it = 0; it < kSortPerThread; ++it) {
             const uint32_t idx = wbase + uint32_t(it) * 64 + lane;
             const bool valid = idx < n;
-            k_[it] = valid ? keys_in[idx] : ~KeyT(0);
-            v_[it] = valid ? vals_in[idx] : 0u;
+            if (!valid) k_[it] = ~KeyT(0);
             const uint32_t d = uint32_t(k_[it] >> shift) & 255u;
             uint64_t peers = ballot(valid);
 #pragma unroll
@@ -648,8 +633,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 
         // 3a. publish this partition's count of bin tid at once (successors
         // may be waiting for it); partition 0's count is already inclusive
-        uint32_t* st = status + size_t(part) * 256 + tid;
-        st_agent(st, (part == 0 ? kFlagInc : kFlagAgg) | total);
+        uint32_t* st = offs ? nullptr : status + size_t(part) * 256 + tid;
+        if (!offs) st_agent(st, (part == 0 ? kFlagInc : kFlagAgg) | total);
         __syncthreads();
 
         // 4. stage in LDS in (digit, input order) order (before the look-back,
@@ -668,7 +653,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         // 3b. decoupled look-back for bin tid
         {
             uint32_t excl = 0;
-            if (part > 0) {
+            if (offs) {
+                // the partitions before this one: their counts of bin tid, scanned
+                excl = offs[size_t(tid) * offs_stride + part];
+            } else if (part > 0) {
                 // Walk back kLookWin predecessors per round trip: their status
                 // words are loaded together, then consumed in order up to the
                 // first inclusive prefix (done) or the first one not yet
@@ -723,6 +711,80 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         if (one_each) break;
         __syncthreads();
     }
+}
+
+// Reduce-then-scan form of a pass (depth-first path): the digit counts of
+// every partition, then one scan per digit over the partitions, then
+// k_sort_pass with offs set ranks and scatters each partition independently.
+// Every partition waits for nothing, where the look-back form serialises on
+// a chain of round trips between partitions resident at the same time.
+// counts is digit-major: counts[d * stride + partition] (the scan reads a
+// digit's counts contiguously; a partition-major table made it 2.4x slower).
+template <int IPT, typename KeyT>
+__global__ __launch_bounds__(256) void k_part_count(const KeyT* __restrict__ keys,
+                                                    const uint32_t* __restrict__ n_sorted, int shift,
+                                                    uint32_t* __restrict__ counts, uint32_t stride, int wave_agg) {
+    constexpr int kPart = kSortThreads * IPT;
+    __shared__ uint32_t h[256];
+    const uint32_t n = *n_sorted;
+    const uint32_t n_parts = (n + kPart - 1) / kPart;
+    const int tid = threadIdx.x;
+    for (uint32_t part = blockIdx.x; part < n_parts; part += gridDim.x) {
+        h[tid] = 0;
+        __syncthreads();
+        const uint32_t wbase = part * kPart + uint32_t(tid / 64) * (IPT * 64);
+        // unconditional loads (index clamped to the last key), all issued
+        // before the first use; a guarded load would wait on its own
+        KeyT k_[IPT];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it)
+            k_[it] = keys[min(wbase + uint32_t(it) * 64 + lane_id(), n - 1u)];
+        uint32_t d_[IPT];
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const uint32_t idx = wbase + uint32_t(it) * 64 + lane_id();
+            d_[it] = idx < n ? uint32_t(k_[it] >> shift) & 255u : 256u;
+        }
+        if (!wave_agg) {
+            // spread digits: one LDS atomic per key
+#pragma unroll
+            for (int it = 0; it < IPT; ++it)
+                if (d_[it] < 256u) atomicAdd(&h[d_[it]], 1u);
+        } else {
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            // few distinct digits (a key's top digit), where lanes would
+            // collide on the same counters: lanes with equal digits found by
+            // eight ballots, the lowest adds for all of them
+            const uint32_t d = d_[it];
+            const bool valid = d < 256u;
+            uint64_t peers = ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&h[d], popc64(peers));
+        }
+        }
+        __syncthreads();
+        counts[size_t(tid) * stride + part] = h[tid];
+        __syncthreads();
+    }
+}
+
+// One workgroup per digit: exclusive scan in place of the digit's partition
+// counts (a row of the table); total[d] = the digit's count over the pass.
+__global__ __launch_bounds__(kScanWgThreads) void k_part_scan(uint32_t* __restrict__ counts, uint32_t stride,
+                                                             const uint32_t* __restrict__ n_sorted, int part,
+                                                             uint32_t* __restrict__ total) {
+    __shared__ uint32_t lds_w[kScanWgThreads / 64];
+    __shared__ uint64_t carry_s;
+    __shared__ uint32_t stage[kScanStage];
+    const int64_t np = (int64_t(*n_sorted) + part - 1) / part;
+    const uint64_t t = scan_sums_1wg(counts + size_t(blockIdx.x) * stride, np, lds_w, &carry_s, stage);
+    if (threadIdx.x == 0) total[blockIdx.x] = uint32_t(t);
 }
 
 // Tile ranges from the sorted keys: boundary b (0 <= b <= n_tiles) is the
@@ -1137,6 +1199,28 @@ static VoxWs carve_vox(void* ws, int64_t n) {
     return s;
 }
 
+// Workgroups of a reduce-then-scan pass (larger inputs loop over partitions).
+constexpr int64_t kRtsGrid = 2048;
+
+// One reduce-then-scan radix pass over the n = *n_sorted keys in kin/vin
+// (top: the key's most significant digit, counted with wave aggregation):
+// partition counts into counts (digit-major, rows of `stride` >= max_parts
+// partitions), their scan (digit totals into total), then the ranking scatter.
+template <int IPT, typename KeyT>
+static void rts_pass(const KeyT* kin, const uint32_t* vin, KeyT* kout, uint32_t* vout, const uint32_t* n_sorted,
+                     int shift, bool top, uint32_t* counts, uint32_t stride, uint32_t* total, uint32_t* err,
+                     int64_t max_parts, const uint4* gsrc, uint4* gdst, hipStream_t stream) {
+    const int grid = int(std::max<int64_t>(1, std::min<int64_t>(max_parts, kRtsGrid)));
+    launch("part_count", k_part_count<IPT, KeyT>, dim3(grid), dim3(256), 0, stream, kin, n_sorted, shift, counts,
+           stride, int(top));
+    hipLaunchKernelGGL(k_part_scan, dim3(256), dim3(kScanWgThreads), 0, stream, counts, stride, n_sorted,
+                       int(kSortThreads * IPT), total);
+    launch("sort_pass", k_sort_pass<IPT, KeyT>, dim3(grid), dim3(kSortThreads), 0, stream, kin, vin, kout, vout,
+           n_sorted, static_cast<const uint32_t*>(total), static_cast<uint32_t*>(nullptr),
+           static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr), err, shift, gsrc, gdst,
+           static_cast<const uint32_t*>(counts), stride);
+}
+
 }  // namespace gsmi
 
 using namespace gsmi;
@@ -1180,12 +1264,12 @@ extern "C" int gs_voxel_levels(const float* mean, int64_t n, const float* origin
             launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
                    V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
                    static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
-                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr));
+                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u);
         else
             launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
                    V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
                    static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
-                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr));
+                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u);
     }
     launch("voxel_label", k_voxel_label, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream,
            static_cast<const uint64_t*>(V.keys[0]), static_cast<const uint32_t*>(V.vals[0]), n, int(n_levels),
@@ -1237,10 +1321,19 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     const int tile_passes = (tile_bits + 7) / 8;
     if (tile_passes > 4) return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: too many tiles");
 
-    const int64_t nb = (n_total + kScanItems - 1) / kScanItems;
-    if (nb > 0)
-        launch("scan_reduce", k_scan_reduce, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total,
-               S.block_sums, per_tile ? nullptr : S.vis_sums);
+    // Entry blocks of 256 * scan_it entries: larger blocks for long inputs
+    // (fewer, fuller workgroups and a one-round scan of the block sums).
+    const int scan_it = (!per_tile && n_total >= (int64_t(1) << 21)) ? kScanItLong : 1;
+    const int64_t nb = (n_total + kScanItems * scan_it - 1) / (kScanItems * scan_it);
+    const int64_t nb256 = (n_total + kScanItems - 1) / kScanItems;
+    if (nb > 0) {
+        if (scan_it == 1)
+            launch("scan_reduce", k_scan_reduce<1>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total,
+                   S.block_sums, per_tile ? nullptr : S.vis_sums);
+        else
+            launch("scan_reduce", k_scan_reduce<kScanItLong>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E,
+                   n_total, S.block_sums, S.vis_sums);
+    }
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanWgThreads), 0, stream, S.block_sums, nb, n_pairs_dev, capacity,
                        S.n_sorted, S.hist, S.counters, S.err, per_tile ? nullptr : S.vis_sums);
     if ((rc = check_launch("gs_bin_sort scan"))) return rc;
@@ -1261,62 +1354,75 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
             launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
                    vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
                    S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
-                   static_cast<uint4*>(nullptr));
+                   static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u);
         else
             launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
                    vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
                    S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
-                   static_cast<uint4*>(nullptr));
+                   static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u);
     };
 
     if (!per_tile) {
         // Depth-first path.  The emission writes into buffer z and the tile
         // passes ping-pong from there, ending in the caller's keys/vals; the
         // depth sort runs in the other buffer x (its 32-bit keys in the
-        // first half of the key array), ending where it started.
+        // first half of the key array), ending where it started.  Every pass
+        // takes the reduce-then-scan form; its partition counts live in the
+        // first status array (rows of `stride` partitions, enough for any
+        // pass: visible entries and pairs are both at most the capacity).
         const int z = tile_passes & 1, x = z ^ 1;
         uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(kb[x]), reinterpret_cast<uint32_t*>(kb[z])};
         uint32_t* dv[2] = {vb[x], vb[z]};
         const bool small_d = n_total <= kSmallSortCapacity;
         const int part_d = kSortThreads * (small_d ? kIptSmall : kIptLarge);
-        int grid_d = int(std::min<int64_t>((n_total + part_d - 1) / part_d, 256 * (small_d ? 6 : 3)));
-        if (grid_d < 1) grid_d = 1;
+        const uint32_t stride = uint32_t((capacity + kPartMin - 1) / kPartMin + 1);
+        const int64_t parts_d = (std::min(n_total, capacity) + part_d - 1) / part_d;
+        uint32_t* counts = S.status[0];
         if (nb > 0) {
-            launch("vis_compact", k_vis_compact, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total,
-                   static_cast<const uint32_t*>(S.vis_sums), static_cast<const uint32_t*>(S.n_sorted), dk[0], dv[0],
-                   S.vrec, part_d, S.status[0]);
-            const int64_t hg = std::min<int64_t>(kBinHistGroups, nb);
-            launch("bin_hist", k_bin_hist, dim3(unsigned(hg)), dim3(256), 0, stream,
-                   static_cast<const uint32_t*>(dk[0]), static_cast<const uint4*>(S.vrec),
-                   static_cast<const uint32_t*>(S.n_sorted), tile_passes, S.hist);
+            if (scan_it == 1)
+                launch("vis_compact", k_vis_compact<1>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E,
+                       n_total, static_cast<const uint32_t*>(S.vis_sums), static_cast<const uint32_t*>(S.n_sorted),
+                       dk[0], S.vrec);
+            else
+                launch("vis_compact", k_vis_compact<kScanItLong>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream,
+                       E, n_total, static_cast<const uint32_t*>(S.vis_sums),
+                       static_cast<const uint32_t*>(S.n_sorted), dk[0], S.vrec);
         }
         for (int p = 0; p < 4; ++p) {
-            uint32_t* st_next = p < 3 ? S.status[(p + 1) & 1] : nullptr;
             const int a = p & 1, b = a ^ 1;
             // the last pass writes the records in depth order instead of the ranks
             const uint4* gsrc = p == 3 ? static_cast<const uint4*>(S.vrec) : nullptr;
             uint4* gdst = p == 3 ? S.srec : nullptr;
+            // the first pass ranks by position (the compaction stores no values)
+            const uint32_t* vin = p == 0 ? nullptr : dv[a];
             if (small_d)
-                launch("sort_pass", k_sort_pass<kIptSmall, uint32_t>, dim3(grid_d), dim3(kSortThreads), 0, stream,
-                       dk[a], dv[a], dk[b], dv[b], S.n_sorted + 1, S.hist + p * 256, S.status[p & 1], st_next,
-                       S.counters + p, S.err, 8 * p, gsrc, gdst);
+                rts_pass<kIptSmall, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
+                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, stream);
             else
-                launch("sort_pass", k_sort_pass<kIptLarge, uint32_t>, dim3(grid_d), dim3(kSortThreads), 0, stream,
-                       dk[a], dv[a], dk[b], dv[b], S.n_sorted + 1, S.hist + p * 256, S.status[p & 1], st_next,
-                       S.counters + p, S.err, 8 * p, gsrc, gdst);
+                rts_pass<kIptLarge, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
+                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, stream);
         }
-        if (nb > 0) {
-            launch("emit_reduce", k_emit_reduce, dim3(unsigned(nb)), dim3(256), 0, stream,
+        if (nb256 > 0) {
+            launch("emit_reduce", k_emit_reduce, dim3(unsigned(nb256)), dim3(256), 0, stream,
                    static_cast<const uint4*>(S.srec), static_cast<const uint32_t*>(S.n_sorted), S.emit_sums);
             hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanWgThreads), 0, stream, S.emit_sums,
                                static_cast<const uint32_t*>(S.n_sorted));
-            launch("emit", k_emit_sorted, dim3(unsigned(nb)), dim3(256), 0, stream, static_cast<const uint4*>(S.srec),
+            launch("emit", k_emit_sorted, dim3(unsigned(nb256)), dim3(256), 0, stream, static_cast<const uint4*>(S.srec),
                    static_cast<const uint32_t*>(dk[0]), static_cast<const uint32_t*>(S.n_sorted),
-                   static_cast<const uint32_t*>(S.emit_sums), kb[z], vb[z], part, S.status[0]);
+                   static_cast<const uint32_t*>(S.emit_sums), kb[z], vb[z]);
         }
         int cur = z;
         for (int q = 0; q < tile_passes; ++q) {
-            tile_pass(q, cur, 4 + q, 4 + q, q + 1 == tile_passes);
+            if (small)
+                rts_pass<kIptSmall, uint64_t>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, 32 + 8 * q,
+                                              q + 1 == tile_passes, counts, stride, S.hist + (4 + q) * 256, S.err,
+                                              max_parts, static_cast<const uint4*>(nullptr),
+                                              static_cast<uint4*>(nullptr), stream);
+            else
+                rts_pass<kIptLarge, uint64_t>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, 32 + 8 * q,
+                                              q + 1 == tile_passes, counts, stride, S.hist + (4 + q) * 256, S.err,
+                                              max_parts, static_cast<const uint4*>(nullptr),
+                                              static_cast<uint4*>(nullptr), stream);
             cur ^= 1;
         }
         if ((rc = check_launch("gs_bin_sort sort"))) return rc;
