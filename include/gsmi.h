@@ -221,10 +221,14 @@ int gs_project(const gs_scene* scene, const int32_t* active_idx, int64_t n_in,
  * radius > 0 (in order of camera, then j) and each tile of its rectangle in
  * row-major order, a pair (key = global_tile << 32 | float bits of depth,
  * value = j) is emitted; pairs are sorted stably by key, so each tile's list
- * is ordered by (depth, j).  (Implementation: LSD radix passes over the tile
- * bits, then each tile's segment sorted by (depth bits, position); the result
- * equals the stable full-key sort.)  tile_ranges [2][total_tiles]: row 0
- * start, row 1 end.
+ * is ordered by (depth, j).  (Implementation: short lists, LSD radix passes
+ * over the tile bits, then each tile's segment sorted by (depth bits,
+ * position); long lists (capacity above 256 pairs per tile), the visible
+ * entries sorted by depth first, the pairs emitted in that order, then stable
+ * passes over the tile bits.  Both equal the stable full-key sort.)
+ * tile_ranges [2][total_tiles]: row 0 start, row 1 end.
+ * Reads rec (or, when every camera has it, the mean2d copy), depth, radius
+ * and tiles_touched of the projection.
  * *n_pairs_dev = number of pairs K.  If K > capacity nothing is sorted and
  * every tile range is empty; the caller re-runs with capacity >= K.  A
  * negative count reports an internal failure of the sort (a bounded wait

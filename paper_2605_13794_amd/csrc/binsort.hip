@@ -21,6 +21,7 @@ constexpr int kScanItLong = 8;            // rounds per block of a long depth-fi
 
 struct EmitIn {
     const float* rec[GS_MAX_CAMS];
+    const float* m2d[GS_MAX_CAMS];  // [2][n_in] screen centres, if use_m2d
     const float* depth[GS_MAX_CAMS];
     const int32_t* radius[GS_MAX_CAMS];
     const uint32_t* tiles[GS_MAX_CAMS];
@@ -28,6 +29,7 @@ struct EmitIn {
     int32_t TX[GS_MAX_CAMS];
     int32_t TY[GS_MAX_CAMS];
     int n_cams;
+    int use_m2d;   // every camera has its component-major centres
     int64_t n_in;  // entries per camera
 };
 
@@ -40,6 +42,7 @@ struct EmitIn {
 #define GS_GLOBAL __attribute__((address_space(1)))
 struct CamPtrs {
     const float GS_GLOBAL* rec[GS_MAX_CAMS];
+    const float GS_GLOBAL* m2d[GS_MAX_CAMS];
     const float GS_GLOBAL* depth[GS_MAX_CAMS];
     const int32_t GS_GLOBAL* radius[GS_MAX_CAMS];
     const uint32_t GS_GLOBAL* tiles[GS_MAX_CAMS];
@@ -52,6 +55,7 @@ __device__ __forceinline__ void stage_cam_ptrs(const EmitIn& E, CamPtrs& P) {
     const int t = threadIdx.x;
     if (t < GS_MAX_CAMS) {
         P.rec[t] = (const float GS_GLOBAL*)E.rec[t];
+        P.m2d[t] = (const float GS_GLOBAL*)E.m2d[t];
         P.depth[t] = (const float GS_GLOBAL*)E.depth[t];
         P.radius[t] = (const int32_t GS_GLOBAL*)E.radius[t];
         P.tiles[t] = (const uint32_t GS_GLOBAL*)E.tiles[t];
@@ -150,10 +154,15 @@ __device__ uint64_t scan_sums_1wg(uint32_t* __restrict__ sums, int64_t nb, uint3
     if (tid == 0) *carry_s = 0;
     __syncthreads();
     for (int64_t b0 = 0; b0 < nb; b0 += kScanRound) {
+        // unconditional loads (index clamped to the last sum), all issued
+        // before the first store to LDS
+        uint32_t ld[kScanPer];
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) ld[q] = sums[min<int64_t>(b0 + q * kScanWgThreads + tid, nb - 1)];
 #pragma unroll
         for (int q = 0; q < kScanPer; ++q) {
             const int idx = q * kScanWgThreads + tid;
-            stage[scan_pad(idx)] = (b0 + idx < nb) ? sums[b0 + idx] : 0u;
+            stage[scan_pad(idx)] = (b0 + idx < nb) ? ld[q] : 0u;
         }
         __syncthreads();
         uint32_t v[kScanPer], sum = 0;
@@ -230,8 +239,14 @@ __device__ __forceinline__ void vis_rect_of(uint32_t tile_off, int64_t TX, int64
 
 __device__ __forceinline__ void vis_rect(const EmitIn& E, int c, int64_t j, uint32_t* bt, uint32_t* wd,
                                          uint32_t* tx) {
-    const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
-    vis_rect_of(E.tile_off[c], E.TX[c], E.TY[c], make_float2(q0.x, q0.y), E.radius[c][j], bt, wd, tx);
+    float2 q;
+    if (E.use_m2d) {
+        q = make_float2(E.m2d[c][j], E.m2d[c][E.n_in + j]);
+    } else {
+        const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
+        q = make_float2(q0.x, q0.y);
+    }
+    vis_rect_of(E.tile_off[c], E.TX[c], E.TY[c], q, E.radius[c][j], bt, wd, tx);
 }
 
 
@@ -267,10 +282,25 @@ __device__ __forceinline__ void hist_add(uint32_t (*h)[256], uint64_t key, bool 
     }
 }
 
-// Writes a block's `tot` pairs at keys/vals[run ...]: output o belongs to the
-// last entry l with start[l] <= o (zero-count entries share the next start);
-// its tile is the (o - start[l])-th of the entry's rectangle in row-major
-// order.  The whole block iterates together (the histogram ballots).
+// Output o of a block belongs to the last entry l with start[l] <= o
+// (zero-count entries share the next start); its tile is the
+// (o - start[l])-th of the entry's rectangle in row-major order.  Returns l.
+__device__ __forceinline__ uint32_t block_pair(const EmitLds& L, uint32_t o, uint32_t* tile) {
+    uint32_t lo = 0, hi = kScanThreads;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (L.start[mid] <= o) lo = mid;
+        else hi = mid;
+    }
+    const uint32_t local = o - L.start[lo];
+    const uint32_t ww = L.w[lo];
+    const uint32_t dy = local / ww, dx = local - dy * ww;
+    *tile = L.base_tile[lo] + dy * L.tx[lo] + dx;
+    return lo;
+}
+
+// Writes a block's `tot` pairs at keys/vals[run ...].  The whole block
+// iterates together (the histogram ballots).
 __device__ __forceinline__ void emit_block_pairs(const EmitLds& L, uint32_t (*h)[256], uint32_t tot, uint32_t run,
                                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, int passes,
                                                  int shift0) {
@@ -279,21 +309,25 @@ __device__ __forceinline__ void emit_block_pairs(const EmitLds& L, uint32_t (*h)
         const bool valid = o < tot;
         uint64_t key = 0;
         if (valid) {
-            uint32_t lo = 0, hi = kScanThreads;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (L.start[mid] <= o) lo = mid;
-                else hi = mid;
-            }
-            const uint32_t local = o - L.start[lo];
-            const uint32_t ww = L.w[lo];
-            const uint32_t dy = local / ww, dx = local - dy * ww;
-            const uint64_t tile = uint64_t(L.base_tile[lo] + dy * L.tx[lo] + dx);
-            key = (tile << 32) | uint64_t(L.dbits[lo]);
+            uint32_t tile;
+            const uint32_t l = block_pair(L, o, &tile);
+            key = (uint64_t(tile) << 32) | uint64_t(L.dbits[l]);
             keys[run + o] = key;
-            vals[run + o] = L.j[lo];
+            vals[run + o] = L.j[l];
         }
         hist_add(h, key, valid, passes, shift0);
+    }
+}
+
+// The same pairs in the compact layout of the tile passes (at most 65,536
+// tiles): the tile id as 16 bits, and depth bits << 32 | entry as the value.
+__device__ __forceinline__ void emit_block_pairs_compact(const EmitLds& L, uint32_t tot, uint32_t run,
+                                                         uint16_t* __restrict__ tile16, uint64_t* __restrict__ dv) {
+    for (uint32_t o = threadIdx.x; o < tot; o += kScanThreads) {
+        uint32_t tile;
+        const uint32_t l = block_pair(L, o, &tile);
+        tile16[run + o] = uint16_t(tile);
+        dv[run + o] = (uint64_t(L.dbits[l]) << 32) | uint64_t(L.j[l]);
     }
 }
 
@@ -413,8 +447,12 @@ __global__ __launch_bounds__(256) void k_vis_compact(EmitIn E, int64_t n_total, 
         const int64_t e = base + list[min(uint32_t(it * kScanThreads) + tid, nv - 1u)];
         const int c = int(e / E.n_in);
         const int64_t j = e - int64_t(c) * E.n_in;
-        const float GS_GLOBAL* q = P.rec[c] + j * kRec;
-        q_[it] = make_float2(q[0], q[1]);
+        if (E.use_m2d) {
+            q_[it] = make_float2(P.m2d[c][j], P.m2d[c][E.n_in + j]);
+        } else {
+            const float GS_GLOBAL* q = P.rec[c] + j * kRec;
+            q_[it] = make_float2(q[0], q[1]);
+        }
         r_[it] = P.radius[c][j];
         d_[it] = __float_as_uint(P.depth[c][j]);
     }
@@ -458,11 +496,13 @@ __global__ __launch_bounds__(kScanWgThreads) void k_scan_sums(uint32_t* __restri
 }
 
 // Emission in depth order: per block of 256 depth-sorted visible entries, the
-// block's pairs are written as one contiguous run, spread over all threads.
+// block's pairs are written as one contiguous run, spread over all threads;
+// with tile16 set, in the compact layout (tile16, dv) instead of keys/vals.
 __global__ __launch_bounds__(256) void k_emit_sorted(const uint4* __restrict__ srec, const uint32_t* __restrict__ dkey,
                                                      const uint32_t* __restrict__ n_sorted,
                                                      const uint32_t* __restrict__ offs, uint64_t* __restrict__ keys,
-                                                     uint32_t* __restrict__ vals) {
+                                                     uint32_t* __restrict__ vals, uint16_t* __restrict__ tile16,
+                                                     uint64_t* __restrict__ dv) {
     __shared__ uint32_t lds4[4];
     __shared__ EmitLds L;
     const uint32_t n_v = n_sorted[1];
@@ -486,7 +526,8 @@ __global__ __launch_bounds__(256) void k_emit_sorted(const uint4* __restrict__ s
     L.j[tid] = r.x;
     if (tid == 0) L.start[kScanThreads] = tot;
     __syncthreads();
-    emit_block_pairs(L, nullptr, tot, offs[blockIdx.x], keys, vals, 0, 0);
+    if (tile16) emit_block_pairs_compact(L, tot, offs[blockIdx.x], tile16, dv);
+    else emit_block_pairs(L, nullptr, tot, offs[blockIdx.x], keys, vals, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,10 +543,10 @@ constexpr int64_t kSmallSortCapacity = 2 << 20;
 constexpr int kPartMin = kSortThreads * kIptSmall;
 constexpr int kLookWin = 8;  // predecessors read per look-back round trip
 
-template <int IPT, typename KeyT>
+template <int IPT, typename KeyT, typename ValT>
 struct SortLds {
+    ValT vals[kSortThreads * IPT];
     KeyT keys[kSortThreads * IPT];
-    uint32_t vals[kSortThreads * IPT];
     uint32_t wcnt[kWaves][256];
     uint32_t bin_start[256];
     uint32_t gbase[256];
@@ -520,21 +561,26 @@ struct SortLds {
 // KeyT: uint64_t (pairs) or uint32_t (depth keys of the depth-first path).
 // With gather_src set, the pass writes gather_dst[g] = gather_src[value]
 // instead of the value (the last depth pass: the records in depth order).
-// Without vals_in the value of the key at position i is i.
-template <int IPT, typename KeyT>
+// Without vals_in the value of the key at position i is i.  With final_keys
+// set (the last tile pass of the compact layout: 16-bit tile keys, values
+// depth bits << 32 | entry) the pass writes the full pairs instead,
+// final_keys[g] = tile << 32 | depth bits and final_vals[g] = entry.
+template <int IPT, typename KeyT, typename ValT = uint32_t>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_sort_pass(const KeyT* __restrict__ keys_in,
-                                                   const uint32_t* __restrict__ vals_in,
-                                                   KeyT* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                   const ValT* __restrict__ vals_in,
+                                                   KeyT* __restrict__ keys_out, ValT* __restrict__ vals_out,
                                                    const uint32_t* __restrict__ n_sorted,
                                                    const uint32_t* __restrict__ hist_pass,
                                                    uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
                                                    uint32_t* __restrict__ counter, uint32_t* __restrict__ err,
                                                    int shift, const uint4* __restrict__ gather_src,
                                                    uint4* __restrict__ gather_dst,
-                                                   const uint32_t* __restrict__ offs, uint32_t offs_stride) {
+                                                   const uint32_t* __restrict__ offs, uint32_t offs_stride,
+                                                   uint64_t* __restrict__ final_keys,
+                                                   uint32_t* __restrict__ final_vals) {
     constexpr int kSortPerThread = IPT;
     constexpr int kPart = kSortThreads * IPT;
-    __shared__ SortLds<IPT, KeyT> L;
+    __shared__ SortLds<IPT, KeyT, ValT> L;
     const uint32_t n = *n_sorted;
     const uint32_t n_parts = (n + kPart - 1) / kPart;
     const int tid = threadIdx.x;
@@ -555,8 +601,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         // the pass is a copy (and clears the next pass's look-back status)
         const uint32_t stride = gridDim.x * kSortThreads;
         for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n; i += stride) {
-            keys_out[i] = keys_in[i];
-            const uint32_t v = vals_in ? vals_in[i] : i;
+            const KeyT key = keys_in[i];
+            const ValT v = vals_in ? vals_in[i] : ValT(i);
+            if (final_keys) {
+                final_keys[i] = (uint64_t(key) << 32) | (uint64_t(v) >> 32);
+                final_vals[i] = uint32_t(v);
+                continue;
+            }
+            keys_out[i] = key;
             if (gather_src) gather_dst[i] = gather_src[v];
             else vals_out[i] = v;
         }
@@ -585,7 +637,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         // 1. load (wave-striped) and rank within the wavefront, stably
         const uint32_t wbase = part * kPart + uint32_t(w) * (kSortPerThread * 64);
         KeyT k_[kSortPerThread];
-        uint32_t v_[kSortPerThread];
+        ValT v_[kSortPerThread];
         uint32_t rank_[kSortPerThread];
         // unconditional loads (index clamped to the last key), all issued
         // before the ranking; a guarded load would wait on its own
@@ -593,7 +645,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         for (int it = 0; it < kSortPerThread; ++it) {
             const uint32_t idx = min(wbase + uint32_t(it) * 64 + lane, n - 1u);
             k_[it] = keys_in[idx];
-            v_[it] = vals_in ? vals_in[idx] : idx;
+            v_[it] = vals_in ? vals_in[idx] : ValT(idx);
         }
 #pragma unroll
         for (int it = 0; it < kSortPerThread; ++it) {
@@ -703,6 +755,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             const uint32_t d = uint32_t(key >> shift) & 255u;
             const uint32_t g = L.gbase[d] + i;
             if (g < n) {  // always true unless a look-back wait timed out
+                if (final_keys) {
+                    final_keys[g] = (uint64_t(key) << 32) | (uint64_t(L.vals[i]) >> 32);
+                    final_vals[g] = uint32_t(L.vals[i]);
+                    continue;
+                }
                 keys_out[g] = key;
                 if (gather_src) gather_dst[g] = gather_src[L.vals[i]];
                 else vals_out[g] = L.vals[i];
@@ -1203,22 +1260,23 @@ static VoxWs carve_vox(void* ws, int64_t n) {
 constexpr int64_t kRtsGrid = 2048;
 
 // One reduce-then-scan radix pass over the n = *n_sorted keys in kin/vin
-// (top: the key's most significant digit, counted with wave aggregation):
+// (few: a digit with few distinct values, counted with wave aggregation):
 // partition counts into counts (digit-major, rows of `stride` >= max_parts
 // partitions), their scan (digit totals into total), then the ranking scatter.
-template <int IPT, typename KeyT>
-static void rts_pass(const KeyT* kin, const uint32_t* vin, KeyT* kout, uint32_t* vout, const uint32_t* n_sorted,
-                     int shift, bool top, uint32_t* counts, uint32_t stride, uint32_t* total, uint32_t* err,
-                     int64_t max_parts, const uint4* gsrc, uint4* gdst, hipStream_t stream) {
+template <int IPT, typename KeyT, typename ValT = uint32_t>
+static void rts_pass(const KeyT* kin, const ValT* vin, KeyT* kout, ValT* vout, const uint32_t* n_sorted, int shift,
+                     bool few, uint32_t* counts, uint32_t stride, uint32_t* total, uint32_t* err, int64_t max_parts,
+                     const uint4* gsrc, uint4* gdst, uint64_t* final_keys, uint32_t* final_vals,
+                     hipStream_t stream) {
     const int grid = int(std::max<int64_t>(1, std::min<int64_t>(max_parts, kRtsGrid)));
     launch("part_count", k_part_count<IPT, KeyT>, dim3(grid), dim3(256), 0, stream, kin, n_sorted, shift, counts,
-           stride, int(top));
+           stride, int(few));
     hipLaunchKernelGGL(k_part_scan, dim3(256), dim3(kScanWgThreads), 0, stream, counts, stride, n_sorted,
                        int(kSortThreads * IPT), total);
-    launch("sort_pass", k_sort_pass<IPT, KeyT>, dim3(grid), dim3(kSortThreads), 0, stream, kin, vin, kout, vout,
+    launch("sort_pass", k_sort_pass<IPT, KeyT, ValT>, dim3(grid), dim3(kSortThreads), 0, stream, kin, vin, kout, vout,
            n_sorted, static_cast<const uint32_t*>(total), static_cast<uint32_t*>(nullptr),
            static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr), err, shift, gsrc, gdst,
-           static_cast<const uint32_t*>(counts), stride);
+           static_cast<const uint32_t*>(counts), stride, final_keys, final_vals);
 }
 
 }  // namespace gsmi
@@ -1264,12 +1322,14 @@ extern "C" int gs_voxel_levels(const float* mean, int64_t n, const float* origin
             launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
                    V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
                    static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
-                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u);
+                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
+                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr));
         else
             launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
                    V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
                    static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
-                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u);
+                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
+                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr));
     }
     launch("voxel_label", k_voxel_label, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream,
            static_cast<const uint64_t*>(V.keys[0]), static_cast<const uint32_t*>(V.vals[0]), n, int(n_levels),
@@ -1302,6 +1362,7 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         if (n_in > 0 && (!p.rec || !p.depth || !p.radius || !p.tiles_touched))
             return fail(GS_ERR_INVALID_ARG, "gs_bin_sort: camera %d: null projection array", c);
         E.rec[c] = p.rec; E.depth[c] = p.depth; E.radius[c] = p.radius; E.tiles[c] = p.tiles_touched;
+        E.m2d[c] = p.mean2d;
         E.tile_off[c] = off;
         E.TX[c] = int32_t(tiles_x(cams[c].width));
         E.TY[c] = int32_t(tiles_y(cams[c].height));
@@ -1309,6 +1370,11 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     }
     E.n_cams = n_cams;
     E.n_in = n_in > 0 ? n_in : 1;
+    // the rectangles read the screen centre from the component-major copy
+    // when every camera has one (8 bytes per entry instead of a line of the
+    // 48-byte records)
+    E.use_m2d = 1;
+    for (int c = 0; c < n_cams; ++c) E.use_m2d &= proj[c].mean2d != nullptr;
 
     // Two orderings with the same result (the stable sort by the full key).
     // Short tile lists: radix passes over the global tile id only (bits 32
@@ -1354,12 +1420,14 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
             launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
                    vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
                    S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
-                   static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u);
+                   static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
+                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr));
         else
             launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
                    vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
                    S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
-                   static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u);
+                   static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
+                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr));
     };
 
     if (!per_tile) {
@@ -1371,6 +1439,8 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         // first status array (rows of `stride` partitions, enough for any
         // pass: visible entries and pairs are both at most the capacity).
         const int z = tile_passes & 1, x = z ^ 1;
+        // compact layout of the tile passes: tile ids fit 16 bits
+        const bool compact = tile_passes >= 1 && tile_bits <= 16;
         uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(kb[x]), reinterpret_cast<uint32_t*>(kb[z])};
         uint32_t* dv[2] = {vb[x], vb[z]};
         const bool small_d = n_total <= kSmallSortCapacity;
@@ -1397,10 +1467,12 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
             const uint32_t* vin = p == 0 ? nullptr : dv[a];
             if (small_d)
                 rts_pass<kIptSmall, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
-                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, stream);
+                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
+                                              stream);
             else
                 rts_pass<kIptLarge, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
-                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, stream);
+                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
+                                              stream);
         }
         if (nb256 > 0) {
             launch("emit_reduce", k_emit_reduce, dim3(unsigned(nb256)), dim3(256), 0, stream,
@@ -1409,20 +1481,42 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
                                static_cast<const uint32_t*>(S.n_sorted));
             launch("emit", k_emit_sorted, dim3(unsigned(nb256)), dim3(256), 0, stream, static_cast<const uint4*>(S.srec),
                    static_cast<const uint32_t*>(dk[0]), static_cast<const uint32_t*>(S.n_sorted),
-                   static_cast<const uint32_t*>(S.emit_sums), kb[z], vb[z]);
+                   static_cast<const uint32_t*>(S.emit_sums), kb[z], vb[z],
+                   compact ? reinterpret_cast<uint16_t*>(vb[z]) : nullptr, compact ? kb[z] : nullptr);
         }
         int cur = z;
         for (int q = 0; q < tile_passes; ++q) {
-            if (small)
+            const bool last = q + 1 == tile_passes;
+            // wave-aggregated counting for the top digit, whose few values
+            // make lanes collide on the same counters (per-lane atomics: 33
+            // -> 38 us for the 32 values of the 8M orbit view)
+            const bool few = last;
+            uint32_t* hist = S.hist + (4 + q) * 256;
+            if (compact) {
+                // 16-bit tile keys in the value arrays, depth << 32 | entry
+                // in the key arrays; the last pass writes the full pairs
+                const uint16_t* tin = reinterpret_cast<const uint16_t*>(vb[cur]);
+                uint16_t* tout = last ? nullptr : reinterpret_cast<uint16_t*>(vb[cur ^ 1]);
+                uint64_t* dvout = last ? nullptr : kb[cur ^ 1];
+                uint64_t* fk = last ? kb[cur ^ 1] : nullptr;
+                uint32_t* fv = last ? vb[cur ^ 1] : nullptr;
+                if (small)
+                    rts_pass<kIptSmall, uint16_t, uint64_t>(tin, kb[cur], tout, dvout, S.n_sorted, 8 * q, few,
+                                                            counts, stride, hist, S.err, max_parts, nullptr, nullptr,
+                                                            fk, fv, stream);
+                else
+                    rts_pass<kIptLarge, uint16_t, uint64_t>(tin, kb[cur], tout, dvout, S.n_sorted, 8 * q, few,
+                                                            counts, stride, hist, S.err, max_parts, nullptr, nullptr,
+                                                            fk, fv, stream);
+            } else if (small) {
                 rts_pass<kIptSmall, uint64_t>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, 32 + 8 * q,
-                                              q + 1 == tile_passes, counts, stride, S.hist + (4 + q) * 256, S.err,
-                                              max_parts, static_cast<const uint4*>(nullptr),
-                                              static_cast<uint4*>(nullptr), stream);
-            else
+                                              few, counts, stride, hist, S.err, max_parts, nullptr, nullptr,
+                                              nullptr, nullptr, stream);
+            } else {
                 rts_pass<kIptLarge, uint64_t>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, 32 + 8 * q,
-                                              q + 1 == tile_passes, counts, stride, S.hist + (4 + q) * 256, S.err,
-                                              max_parts, static_cast<const uint4*>(nullptr),
-                                              static_cast<uint4*>(nullptr), stream);
+                                              few, counts, stride, hist, S.err, max_parts, nullptr, nullptr,
+                                              nullptr, nullptr, stream);
+            }
             cur ^= 1;
         }
         if ((rc = check_launch("gs_bin_sort sort"))) return rc;

@@ -61,7 +61,9 @@ class DeviceScene:
 class ProjBuffers:
     """Per-camera outputs of gs_project for up to n entries."""
 
-    def __init__(self, n: int, device, soa: bool = False):
+    def __init__(self, n: int, device, soa: bool = False, centre: bool = True):
+        """soa: all component-major copies; centre: the [2][n] mean2d copy
+        only, which the binning reads instead of the 48-byte records."""
         n = max(int(n), 1)
         self.n = n
         self.rec = torch.empty(n * G.REC_FLOATS, dtype=F32, device=device)
@@ -70,8 +72,8 @@ class ProjBuffers:
         self.tiles = torch.empty(n, dtype=I32, device=device)
         self.clamp = torch.empty(n, dtype=U8, device=device)
         self.soa = soa
+        self.mean2d = torch.empty(2, n, dtype=F32, device=device) if (soa or centre) else None
         if soa:
-            self.mean2d = torch.empty(2, n, dtype=F32, device=device)
             self.conic = torch.empty(3, n, dtype=F32, device=device)
             self.opacity = torch.empty(n, dtype=F32, device=device)
             self.rgb = torch.empty(3, n, dtype=F32, device=device)
@@ -80,7 +82,7 @@ class ProjBuffers:
         if self.soa:
             return G.projected(self.rec, self.depth, self.radius, self.tiles, self.clamp, self.mean2d, self.conic,
                                self.opacity, self.rgb)
-        return G.projected(self.rec, self.depth, self.radius, self.tiles, self.clamp)
+        return G.projected(self.rec, self.depth, self.radius, self.tiles, self.clamp, self.mean2d)
 
 
 @dataclasses.dataclass

@@ -37,9 +37,11 @@ def tiles_touched(pr, width, height):
     return np.where(r > 0, (x1 - x0) * (y1 - y0), 0)
 
 
-def upload_projection(pr, width, height, dev):
+def upload_projection(pr, width, height, dev, centre=True):
     """Packed render records (12 floats per Gaussian) built from a reference
-    projection rounded to float32, with depth, radius and tile counts."""
+    projection rounded to float32, with depth, radius and tile counts, and,
+    with centre, the component-major screen centres (the binning then reads
+    those instead of the records)."""
     from paper_2605_13794_amd.raster import ProjBuffers
     n = pr.n
     rec = np.zeros((n, 12), dtype=np.float32)
@@ -50,8 +52,10 @@ def upload_projection(pr, width, height, dev):
     rec[:, 5] = f32(pr.opacity)
     rec[:, 6:9] = f32(pr.rgb).T
     rec[:, 9] = pr.depth
-    pb = ProjBuffers(n, dev)
+    pb = ProjBuffers(n, dev, centre=centre)
     pb.rec.copy_(torch.from_numpy(rec.reshape(-1)))
+    if centre:
+        pb.mean2d.copy_(torch.from_numpy(np.ascontiguousarray(f32(pr.mean2d))))
     pb.depth.copy_(torch.from_numpy(f32(pr.depth)))
     pb.radius.copy_(torch.from_numpy(pr.radius.astype(np.int32)))
     pb.tiles.copy_(torch.from_numpy(tiles_touched(pr, width, height).astype(np.int32)))

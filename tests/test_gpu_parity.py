@@ -118,13 +118,15 @@ def test_bin_sort_bitexact(oracle, case):
     sc, cam = make_case(case)
     _, pr, prf, K, keys, vals, ranges = _ref_sorted(oracle, sc, cam)
     fr = _frame([cam], sc.n, dev, capacity=K + 777)
-    fr.proj[0] = upload_projection(prf, cam.width, cam.height, dev)
-    Kg = fr.bin_sort()
-    torch.cuda.synchronize()
-    assert Kg == K
-    np.testing.assert_array_equal(to_np(fr.keys[:K]).view(np.uint64), keys)
-    np.testing.assert_array_equal(u32(fr.vals[:K]), vals)
-    assert_same_ranges(u32(fr.ranges), ranges)
+    # rectangles from the records, then from the component-major centres
+    for centre in (False, True):
+        fr.proj[0] = upload_projection(prf, cam.width, cam.height, dev, centre=centre)
+        Kg = fr.bin_sort()
+        torch.cuda.synchronize()
+        assert Kg == K
+        np.testing.assert_array_equal(to_np(fr.keys[:K]).view(np.uint64), keys)
+        np.testing.assert_array_equal(u32(fr.vals[:K]), vals)
+        assert_same_ranges(u32(fr.ranges), ranges)
     # deterministic: a second run gives the same bits
     k1, v1 = fr.keys[:K].clone(), fr.vals[:K].clone()
     fr.bin_sort()
@@ -222,6 +224,46 @@ def test_bin_sort_segment_paths(oracle):
     fr.proj[0] = upload_projection(prf, cam.width, cam.height, dev)
     assert fr.bin_sort() == K
     torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(fr.keys[:K]).view(np.uint64), keys)
+    np.testing.assert_array_equal(u32(fr.vals[:K]), vals)
+    assert_same_ranges(u32(fr.ranges), ranges)
+
+
+@pytest.mark.parametrize("layout", ["one_tile_pass", "wide_tile_ids"])
+def test_bin_sort_depth_first_layouts(oracle, layout):
+    """Long-list (depth-first) binning, forced by a pair capacity above 256
+    per tile, in the two layouts of its tile passes: a 256-tile image (one
+    tile pass over 16-bit tile ids that writes the full pairs), and three 4K
+    views in one batch, whose 97,200 global tile ids need 17 bits (three
+    passes over the full 64-bit keys).  Bit-exact against the reference,
+    camera by camera, with each camera's list after the previous ones."""
+    dev = device()
+    G = gsmi()
+    if layout == "one_tile_pass":
+        sc = S.cube_scene(6000, seed=12)
+        cams = [S.cube_camera(256, 256, f=64.0)]
+    else:
+        sc = S.city_scene(1 << 20, seed=2)
+        idx = np.nonzero((np.abs(sc.mean[0]) < 150) & (sc.mean[1] > -60) & (sc.mean[1] < 220))[0][:40000]
+        sc = sc.subset(idx)
+        cams = [S.aerial_camera(3840, 2160, h) for h in (0.0, 120.0, 240.0)]
+    refs = [_ref_sorted(oracle, sc, cam) for cam in cams]
+    tiles = [G.gs_num_tiles(c.width, c.height) for c in cams]
+    assert (sum(tiles) > 65536) == (layout == "wide_tile_ids")
+    K = sum(r[3] for r in refs)
+    print(f"[depth-first {layout}] tiles={sum(tiles)} K={K}", flush=True)
+    fr = _frame(cams, sc.n, dev, capacity=256 * sum(tiles) + 1)
+    for c, (cam, r) in enumerate(zip(cams, refs)):
+        # the one-pass case takes the rectangles' centres from the records
+        fr.proj[c] = upload_projection(r[2], cam.width, cam.height, dev, centre=layout != "one_tile_pass")
+    assert fr.bin_sort() == K
+    torch.cuda.synchronize()
+    toff = np.concatenate([[0], np.cumsum(tiles)[:-1]]).astype(np.uint64)
+    koff = np.concatenate([[0], np.cumsum([r[3] for r in refs])[:-1]]).astype(np.int64)
+    keys = np.concatenate([r[4].astype(np.uint64) + (t << np.uint64(32)) for r, t in zip(refs, toff)])
+    vals = np.concatenate([r[5] for r in refs])
+    ranges = np.concatenate([np.asarray(r[6]).reshape(2, -1).astype(np.int64) + o for r, o in zip(refs, koff)],
+                            axis=1)
     np.testing.assert_array_equal(to_np(fr.keys[:K]).view(np.uint64), keys)
     np.testing.assert_array_equal(u32(fr.vals[:K]), vals)
     assert_same_ranges(u32(fr.ranges), ranges)
