@@ -103,6 +103,20 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds4, 
     return before + inc - v;
 }
 
+// Adds v to sums[b] for every lane of the wavefront, with one atomic per
+// maximal run of lanes (in lane order) that share b; b = ~0u adds nothing.
+// Called by the whole wavefront.
+__device__ __forceinline__ void wave_run_add(uint32_t* sums, uint32_t b, uint32_t v) {
+    const uint32_t lane = lane_id();
+    const uint32_t prev = __shfl_up(b, 1, 64);
+    const uint64_t heads = ballot(lane == 0 || b != prev);
+    const uint32_t inc = wave_incl_scan(v);
+    const int start = 63 - __clzll(heads & ((2ull << lane) - 1ull));  // lane 0 is always a head
+    const uint32_t before = __shfl(inc - v, start, 64);
+    const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+    if (tail && b != ~0u) atomicAdd(&sums[b], inc - before);
+}
+
 // Per block of 256 * ITERS entries: the number of pairs and, if vis_sums is
 // set, the number of visible entries (tile count > 0).  All tile counts are
 // loaded before the first is used (index clamped to the last entry).
@@ -237,19 +251,6 @@ __device__ __forceinline__ void vis_rect_of(uint32_t tile_off, int64_t TX, int64
     *tx = uint32_t(TX);
 }
 
-__device__ __forceinline__ void vis_rect(const EmitIn& E, int c, int64_t j, uint32_t* bt, uint32_t* wd,
-                                         uint32_t* tx) {
-    float2 q;
-    if (E.use_m2d) {
-        q = make_float2(E.m2d[c][j], E.m2d[c][E.n_in + j]);
-    } else {
-        const float4 q0 = reinterpret_cast<const float4*>(E.rec[c] + j * kRec)[0];
-        q = make_float2(q0.x, q0.y);
-    }
-    vis_rect_of(E.tile_off[c], E.TX[c], E.TY[c], q, E.radius[c][j], bt, wd, tx);
-}
-
-
 // Emission: per 256 entries a block-wide scan of the tile counts gives the
 // block a contiguous run of output pairs; all 256 threads then write
 // consecutive pairs of that run (each finds its entry by binary search over the
@@ -342,8 +343,10 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
     __shared__ uint32_t lds4[4];
     __shared__ EmitLds L;
     __shared__ uint32_t h[8][256];
+    __shared__ CamPtrs P;
     const uint32_t n_s = *n_sorted;
     if (n_s == 0) return;  // nothing fits (or nothing to emit)
+    stage_cam_ptrs(E, P);
     const int64_t base = int64_t(blockIdx.x) * kScanItems;
     const uint32_t tid = threadIdx.x;
     {
@@ -353,21 +356,28 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
     for (int k = tid; k < passes * 256; k += 256) (&h[0][0])[k] = 0;
     const uint32_t run = block_offs[blockIdx.x];
     {
-        const int64_t e = base + tid;
-        int c = 0;
-        int64_t j = 0;
-        uint32_t cnt = 0;
-        if (e < n_total) {
-            c = int(e / E.n_in);
-            j = e - int64_t(c) * E.n_in;
-            cnt = E.tiles[c][j];
+        // every input of the entry loaded at once (index clamped to the last
+        // entry), whether it is visible or not
+        const int64_t e = min<int64_t>(base + tid, n_total - 1);
+        const int c = int(e / E.n_in);
+        const int64_t j = e - int64_t(c) * E.n_in;
+        uint32_t cnt = P.tiles[c][j];
+        float2 q;
+        if (E.use_m2d) {
+            q = make_float2(P.m2d[c][j], P.m2d[c][E.n_in + j]);
+        } else {
+            const float GS_GLOBAL* qp = P.rec[c] + j * kRec;
+            q = make_float2(qp[0], qp[1]);
         }
+        const int32_t rad = P.radius[c][j];
+        const uint32_t dbits = __float_as_uint(P.depth[c][j]);
+        if (base + tid >= n_total) cnt = 0;
         uint32_t tot;
         const uint32_t ex = block_excl_scan(cnt, lds4, &tot);
         uint32_t bt = 0, wd = 1, tx = 0, db = 0;
         if (cnt > 0) {
-            vis_rect(E, c, j, &bt, &wd, &tx);
-            db = __float_as_uint(E.depth[c][j]);
+            vis_rect_of(P.tile_off[c], P.TX[c], P.TY[c], q, rad, &bt, &wd, &tx);
+            db = dbits;
         }
         L.start[tid] = ex;
         L.base_tile[tid] = bt;
@@ -406,13 +416,17 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
 template <int ITERS>
 __global__ __launch_bounds__(256) void k_vis_compact(EmitIn E, int64_t n_total, const uint32_t* __restrict__ vis_offs,
                                                      const uint32_t* __restrict__ n_sorted,
-                                                     uint32_t* __restrict__ dkey, uint4* __restrict__ vrec) {
+                                                     uint32_t* __restrict__ dkey, uint4* __restrict__ vrec,
+                                                     uint32_t* __restrict__ emit_sums) {
     __shared__ uint32_t lds4[4];
     __shared__ uint32_t list[kScanThreads * ITERS];
     __shared__ uint32_t lcnt[kScanThreads * ITERS];
     __shared__ CamPtrs P;
     const uint32_t n_v = n_sorted[1];
     if (n_v == 0) return;  // nothing visible, or the pairs do not fit
+    // the pair counts per 256 depth-sorted entries, which the last depth pass
+    // accumulates
+    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < (n_v + 255) / 256; k += gridDim.x * 256) emit_sums[k] = 0;
     stage_cam_ptrs(E, P);
     const uint32_t tid = threadIdx.x;
     const int64_t base = int64_t(blockIdx.x) * (kScanThreads * ITERS);
@@ -469,21 +483,6 @@ __global__ __launch_bounds__(256) void k_vis_compact(EmitIn E, int64_t n_total, 
             vrec[o0 + k] = make_uint4(uint32_t(j), bt, wd | (tx << 16), lcnt[k]);
         }
     }
-}
-
-// Per block of 256 depth-sorted visible entries (their records in depth
-// order, written by the last depth pass): their pair count.
-__global__ __launch_bounds__(256) void k_emit_reduce(const uint4* __restrict__ srec,
-                                                     const uint32_t* __restrict__ n_sorted,
-                                                     uint32_t* __restrict__ sums) {
-    __shared__ uint32_t lds4[4];
-    const uint32_t n_v = n_sorted[1];
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x * 256u >= n_v) return;  // uniform per block
-    const uint32_t cnt = i < n_v ? srec[i].w : 0u;
-    uint32_t tot;
-    block_excl_scan(cnt, lds4, &tot);
-    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(kScanWgThreads) void k_scan_sums(uint32_t* __restrict__ sums,
@@ -564,7 +563,9 @@ struct SortLds {
 // Without vals_in the value of the key at position i is i.  With final_keys
 // set (the last tile pass of the compact layout: 16-bit tile keys, values
 // depth bits << 32 | entry) the pass writes the full pairs instead,
-// final_keys[g] = tile << 32 | depth bits and final_vals[g] = entry.
+// final_keys[g] = tile << 32 | depth bits and final_vals[g] = entry.  With
+// gsums (gather mode) it also adds the gathered records' pair counts (.w) per
+// 256 output positions into gsums (cleared beforehand).
 template <int IPT, typename KeyT, typename ValT = uint32_t>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_sort_pass(const KeyT* __restrict__ keys_in,
                                                    const ValT* __restrict__ vals_in,
@@ -577,7 +578,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                                    uint4* __restrict__ gather_dst,
                                                    const uint32_t* __restrict__ offs, uint32_t offs_stride,
                                                    uint64_t* __restrict__ final_keys,
-                                                   uint32_t* __restrict__ final_vals) {
+                                                   uint32_t* __restrict__ final_vals, uint32_t* __restrict__ gsums) {
     constexpr int kSortPerThread = IPT;
     constexpr int kPart = kSortThreads * IPT;
     __shared__ SortLds<IPT, KeyT, ValT> L;
@@ -600,7 +601,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
         // every key has the same digit: the stable pass is the identity, so
         // the pass is a copy (and clears the next pass's look-back status)
         const uint32_t stride = gridDim.x * kSortThreads;
-        for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n; i += stride) {
+        if (gsums) {
+            // a wavefront's 64 positions lie in one block of 256
+            for (uint32_t i0 = blockIdx.x * kSortThreads + (uint32_t(tid) & ~63u); i0 < n; i0 += stride) {
+                const uint32_t i = i0 + lane;
+                uint32_t wv = 0;
+                if (i < n) {
+                    keys_out[i] = keys_in[i];
+                    const uint4 r = gather_src[vals_in ? uint32_t(vals_in[i]) : i];
+                    gather_dst[i] = r;
+                    wv = r.w;
+                }
+                wave_run_add(gsums, i < n ? i >> 8 : ~0u, wv);
+            }
+        }
+        for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n && !gsums; i += stride) {
             const KeyT key = keys_in[i];
             const ValT v = vals_in ? vals_in[i] : ValT(i);
             if (final_keys) {
@@ -750,7 +765,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 
         // 5. coalesced write-out
         const uint32_t cnt = min<uint32_t>(kPart, n - part * kPart);
-        for (uint32_t i = tid; i < cnt; i += 256) {
+        if (gsums) {
+            // the records in depth order and the pair count of every block of
+            // 256 output positions (every wavefront runs all rounds)
+            for (uint32_t i0 = 0; i0 < uint32_t(kPart); i0 += 256) {
+                const uint32_t i = i0 + tid;
+                uint32_t b = ~0u, wv = 0;
+                if (i < cnt) {
+                    const KeyT key = L.keys[i];
+                    const uint32_t g = L.gbase[uint32_t(key >> shift) & 255u] + i;
+                    if (g < n) {  // always true unless a look-back wait timed out
+                        keys_out[g] = key;
+                        const uint4 r = gather_src[uint32_t(L.vals[i])];
+                        gather_dst[g] = r;
+                        b = g >> 8;
+                        wv = r.w;
+                    }
+                }
+                wave_run_add(gsums, b, wv);
+            }
+        }
+        for (uint32_t i = tid; i < cnt && !gsums; i += 256) {
             const KeyT key = L.keys[i];
             const uint32_t d = uint32_t(key >> shift) & 255u;
             const uint32_t g = L.gbase[d] + i;
@@ -1010,20 +1045,32 @@ __device__ __forceinline__ void reg_bitonic(uint64_t (&k)[E], uint32_t lane) {
 template <int E>
 __device__ __forceinline__ void seg_sort_regs(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* keys_out,
                                               uint32_t* vals_out, uint32_t start, uint32_t n, uint32_t lane) {
+    // loads unconditional (index clamped to the segment's last pair), all
+    // issued before the first use; stores guarded
+    uint32_t lo[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) lo[r] = uint32_t(keys_in[start + min(uint32_t(r) * 64 + lane, n - 1)]);
     uint64_t k[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const uint32_t i = uint32_t(r) * 64 + lane;
-        k[r] = i < n ? (uint64_t(uint32_t(keys_in[start + i])) << 32) | i : ~0ull;
+        k[r] = i < n ? (uint64_t(lo[r]) << 32) | i : ~0ull;
     }
     reg_bitonic<E>(k, lane);
+    uint64_t ko[E];
+    uint32_t vo[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t p = min(uint32_t(k[r]), n - 1);
+        ko[r] = keys_in[start + p];
+        vo[r] = vals_in[start + p];
+    }
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const uint32_t i = uint32_t(r) * 64 + lane;
         if (i < n) {
-            const uint32_t p = uint32_t(k[r]);
-            keys_out[start + i] = keys_in[start + p];
-            vals_out[start + i] = vals_in[start + p];
+            keys_out[start + i] = ko[r];
+            vals_out[start + i] = vo[r];
         }
     }
 }
@@ -1267,7 +1314,7 @@ template <int IPT, typename KeyT, typename ValT = uint32_t>
 static void rts_pass(const KeyT* kin, const ValT* vin, KeyT* kout, ValT* vout, const uint32_t* n_sorted, int shift,
                      bool few, uint32_t* counts, uint32_t stride, uint32_t* total, uint32_t* err, int64_t max_parts,
                      const uint4* gsrc, uint4* gdst, uint64_t* final_keys, uint32_t* final_vals,
-                     hipStream_t stream) {
+                     uint32_t* gsums, hipStream_t stream) {
     const int grid = int(std::max<int64_t>(1, std::min<int64_t>(max_parts, kRtsGrid)));
     launch("part_count", k_part_count<IPT, KeyT>, dim3(grid), dim3(256), 0, stream, kin, n_sorted, shift, counts,
            stride, int(few));
@@ -1276,7 +1323,7 @@ static void rts_pass(const KeyT* kin, const ValT* vin, KeyT* kout, ValT* vout, c
     launch("sort_pass", k_sort_pass<IPT, KeyT, ValT>, dim3(grid), dim3(kSortThreads), 0, stream, kin, vin, kout, vout,
            n_sorted, static_cast<const uint32_t*>(total), static_cast<uint32_t*>(nullptr),
            static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr), err, shift, gsrc, gdst,
-           static_cast<const uint32_t*>(counts), stride, final_keys, final_vals);
+           static_cast<const uint32_t*>(counts), stride, final_keys, final_vals, gsums);
 }
 
 }  // namespace gsmi
@@ -1323,13 +1370,13 @@ extern "C" int gs_voxel_levels(const float* mean, int64_t n, const float* origin
                    V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
                    static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
                    static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
-                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr));
+                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr));
         else
             launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
                    V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
                    static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
                    static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
-                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr));
+                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr));
     }
     launch("voxel_label", k_voxel_label, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream,
            static_cast<const uint64_t*>(V.keys[0]), static_cast<const uint32_t*>(V.vals[0]), n, int(n_levels),
@@ -1421,13 +1468,13 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
                    vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
                    S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
                    static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
-                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr));
+                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr));
         else
             launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
                    vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
                    S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
                    static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
-                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr));
+                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr));
     };
 
     if (!per_tile) {
@@ -1452,11 +1499,11 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
             if (scan_it == 1)
                 launch("vis_compact", k_vis_compact<1>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E,
                        n_total, static_cast<const uint32_t*>(S.vis_sums), static_cast<const uint32_t*>(S.n_sorted),
-                       dk[0], S.vrec);
+                       dk[0], S.vrec, S.emit_sums);
             else
                 launch("vis_compact", k_vis_compact<kScanItLong>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream,
                        E, n_total, static_cast<const uint32_t*>(S.vis_sums),
-                       static_cast<const uint32_t*>(S.n_sorted), dk[0], S.vrec);
+                       static_cast<const uint32_t*>(S.n_sorted), dk[0], S.vrec, S.emit_sums);
         }
         for (int p = 0; p < 4; ++p) {
             const int a = p & 1, b = a ^ 1;
@@ -1468,15 +1515,13 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
             if (small_d)
                 rts_pass<kIptSmall, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
                                               stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
-                                              stream);
+                                              p == 3 ? S.emit_sums : nullptr, stream);
             else
                 rts_pass<kIptLarge, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
                                               stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
-                                              stream);
+                                              p == 3 ? S.emit_sums : nullptr, stream);
         }
         if (nb256 > 0) {
-            launch("emit_reduce", k_emit_reduce, dim3(unsigned(nb256)), dim3(256), 0, stream,
-                   static_cast<const uint4*>(S.srec), static_cast<const uint32_t*>(S.n_sorted), S.emit_sums);
             hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanWgThreads), 0, stream, S.emit_sums,
                                static_cast<const uint32_t*>(S.n_sorted));
             launch("emit", k_emit_sorted, dim3(unsigned(nb256)), dim3(256), 0, stream, static_cast<const uint4*>(S.srec),
@@ -1503,19 +1548,19 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
                 if (small)
                     rts_pass<kIptSmall, uint16_t, uint64_t>(tin, kb[cur], tout, dvout, S.n_sorted, 8 * q, few,
                                                             counts, stride, hist, S.err, max_parts, nullptr, nullptr,
-                                                            fk, fv, stream);
+                                                            fk, fv, nullptr, stream);
                 else
                     rts_pass<kIptLarge, uint16_t, uint64_t>(tin, kb[cur], tout, dvout, S.n_sorted, 8 * q, few,
                                                             counts, stride, hist, S.err, max_parts, nullptr, nullptr,
-                                                            fk, fv, stream);
+                                                            fk, fv, nullptr, stream);
             } else if (small) {
                 rts_pass<kIptSmall, uint64_t>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, 32 + 8 * q,
                                               few, counts, stride, hist, S.err, max_parts, nullptr, nullptr,
-                                              nullptr, nullptr, stream);
+                                              nullptr, nullptr, nullptr, stream);
             } else {
                 rts_pass<kIptLarge, uint64_t>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, 32 + 8 * q,
                                               few, counts, stride, hist, S.err, max_parts, nullptr, nullptr,
-                                              nullptr, nullptr, stream);
+                                              nullptr, nullptr, nullptr, stream);
             }
             cur ^= 1;
         }

@@ -384,26 +384,43 @@ struct GradOut {
 
 // Entries visible in at least one camera, appended to `list` (order is
 // irrelevant: entries are distinct Gaussians, so their gradients are disjoint).
-// One workgroup handles kChunk entries: it counts them, reserves its slice
-// with a single atomic, then writes them (two reads of the radius values).
+// One workgroup handles kChunk entries: it reads their radii once (every load
+// of a camera issued before the first use), counts the visible ones, reserves
+// its slice with a single atomic, then writes them.
 template <int kChunk>
 __global__ __launch_bounds__(256) void k_visible_list(int64_t n_in, const int64_t* __restrict__ n_in_dev, BwdIn B,
                                                       int n_cams, uint32_t* __restrict__ list,
                                                       uint32_t* __restrict__ count) {
+    constexpr int kIt = kChunk / 256;
+    static_assert(kIt <= 32, "visibility bits per camera fit 32 bits");
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t base_s;
     int64_t cnt = n_in;
     if (n_in_dev) cnt = min(cnt, *n_in_dev);
     const int64_t j0 = int64_t(blockIdx.x) * kChunk;
+    if (j0 >= cnt) return;  // uniform
     const int w = threadIdx.x / 64;
-    uint32_t mine = 0;
-    for (int it = 0; it < kChunk / 256; ++it) {
-        const int64_t j = j0 + it * 256 + threadIdx.x;
-        bool vis = false;
-        if (j < cnt)
-            for (int c = 0; c < n_cams; ++c) vis |= B.radius[c][j] > 0;
-        mine += popc64(ballot(vis));
+    // bit it of cam_vis[c]: entry j0 + it * 256 + tid has radius > 0 in camera c
+    // (camera loops unrolled to GS_MAX_CAMS so that cam_vis stays in registers)
+    uint32_t cam_vis[GS_MAX_CAMS];
+    uint32_t any = 0;
+#pragma unroll
+    for (int c = 0; c < GS_MAX_CAMS; ++c) {
+        cam_vis[c] = 0;
+        if (c >= n_cams) continue;
+        int32_t r[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) r[it] = B.radius[c][min<int64_t>(j0 + it * 256 + threadIdx.x, cnt - 1)];
+        uint32_t bits = 0;
+#pragma unroll
+        for (int it = 0; it < kIt; ++it)
+            if (j0 + it * 256 + threadIdx.x < cnt && r[it] > 0) bits |= 1u << it;
+        cam_vis[c] = bits;
+        any |= bits;
     }
+    uint32_t mine = 0;
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) mine += popc64(ballot((any >> it) & 1u));
     if (lane_id() == 0) wsum[w] = mine;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -413,18 +430,18 @@ __global__ __launch_bounds__(256) void k_visible_list(int64_t n_in, const int64_
     __syncthreads();
     uint32_t off = base_s;
     for (int k = 0; k < w; ++k) off += wsum[k];
-    for (int it = 0; it < kChunk / 256; ++it) {
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
         const int64_t j = j0 + it * 256 + threadIdx.x;
-        bool vis = false;
-        if (j < cnt)
-            for (int c = 0; c < n_cams; ++c) vis |= B.radius[c][j] > 0;
+        const bool vis = (any >> it) & 1u;
         const uint64_t m = ballot(vis);
         if (vis) {
             list[off + popc64(m & lanemask_lt())] = uint32_t(j);
             // the blend accumulates into these records with atomics; only
             // visible entries are ever written or read, so only they are cleared
-            for (int c = 0; c < n_cams; ++c) {
-                if (B.radius[c][j] <= 0) continue;
+#pragma unroll
+            for (int c = 0; c < GS_MAX_CAMS; ++c) {
+                if (!((cam_vis[c] >> it) & 1u)) continue;
                 float4* r = reinterpret_cast<float4*>(B.d2[c] + j * kD2Stride);
                 r[0] = make_float4(0.f, 0.f, 0.f, 0.f);
                 r[1] = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -170,9 +170,12 @@ def test_bin_sort_large_persistent_grid(oracle):
     assert_same_ranges(u32(fr.ranges), ranges)
 
 
-def test_bin_sort_equal_depths(oracle):
-    """Every Gaussian at one depth: the four depth digit passes see a single
-    digit each, and the order inside a tile is the index order."""
+@pytest.mark.parametrize("path", ["per_tile", "depth_first"])
+def test_bin_sort_equal_depths(oracle, path):
+    """Every Gaussian at one depth: the order inside a tile is the index
+    order.  On the depth-first path (forced by the capacity) each of the four
+    depth passes sees a single digit, so each is a copy, the last one
+    gathering the records and their pair counts."""
     dev = device()
     sc = S.city_scene(1 << 20, seed=2)
     idx = np.nonzero((np.abs(sc.mean[0]) < 200) & (sc.mean[1] > -60) & (sc.mean[1] < 200))[0][:60000]
@@ -183,7 +186,8 @@ def test_bin_sort_equal_depths(oracle):
     prf = type(prf)(prf.mean2d, np.full_like(prf.depth, 211.25), prf.conic, prf.opacity, prf.rgb, prf.radius)
     K, keys, vals, ranges = oracle.bin_sort(prf, cam.width, cam.height)
     assert K > 20000
-    fr = _frame([cam], sc.n, dev, capacity=K)
+    cap = K if path == "per_tile" else 256 * gsmi().gs_num_tiles(cam.width, cam.height) + 1
+    fr = _frame([cam], sc.n, dev, capacity=cap)
     fr.proj[0] = upload_projection(prf, cam.width, cam.height, dev)
     assert fr.bin_sort() == K
     torch.cuda.synchronize()
