@@ -332,68 +332,55 @@ __device__ __forceinline__ void emit_block_pairs_compact(const EmitLds& L, uint3
     }
 }
 
-// The emission also builds the digit histograms of the tile radix passes (LDS,
-// then one global add per non-empty bin) and clears the look-back status of
-// the first pass, so the sort needs no separate read of the keys.
+// Emission in entry order (the per-tile path): per block of 256 entries,
+// the block's pairs as one contiguous run; with tile16 set in the compact
+// layout of the tile passes (tile16, dv) instead of keys/vals.
 __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const uint32_t* __restrict__ block_offs,
                                               const uint32_t* __restrict__ n_sorted,
                                               uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                              int passes, int shift0, int part, uint32_t* __restrict__ hist,
-                                              uint32_t* __restrict__ status0) {
+                                              uint16_t* __restrict__ tile16, uint64_t* __restrict__ dv) {
     __shared__ uint32_t lds4[4];
     __shared__ EmitLds L;
-    __shared__ uint32_t h[8][256];
     __shared__ CamPtrs P;
     const uint32_t n_s = *n_sorted;
     if (n_s == 0) return;  // nothing fits (or nothing to emit)
     stage_cam_ptrs(E, P);
     const int64_t base = int64_t(blockIdx.x) * kScanItems;
     const uint32_t tid = threadIdx.x;
-    {
-        const uint32_t n_parts = (n_s + uint32_t(part) - 1) / uint32_t(part);
-        for (uint32_t k = blockIdx.x * 256 + tid; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
-    }
-    for (int k = tid; k < passes * 256; k += 256) (&h[0][0])[k] = 0;
     const uint32_t run = block_offs[blockIdx.x];
-    {
-        // every input of the entry loaded at once (index clamped to the last
-        // entry), whether it is visible or not
-        const int64_t e = min<int64_t>(base + tid, n_total - 1);
-        const int c = int(e / E.n_in);
-        const int64_t j = e - int64_t(c) * E.n_in;
-        uint32_t cnt = P.tiles[c][j];
-        float2 q;
-        if (E.use_m2d) {
-            q = make_float2(P.m2d[c][j], P.m2d[c][E.n_in + j]);
-        } else {
-            const float GS_GLOBAL* qp = P.rec[c] + j * kRec;
-            q = make_float2(qp[0], qp[1]);
-        }
-        const int32_t rad = P.radius[c][j];
-        const uint32_t dbits = __float_as_uint(P.depth[c][j]);
-        if (base + tid >= n_total) cnt = 0;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(cnt, lds4, &tot);
-        uint32_t bt = 0, wd = 1, tx = 0, db = 0;
-        if (cnt > 0) {
-            vis_rect_of(P.tile_off[c], P.TX[c], P.TY[c], q, rad, &bt, &wd, &tx);
-            db = dbits;
-        }
-        L.start[tid] = ex;
-        L.base_tile[tid] = bt;
-        L.w[tid] = wd;
-        L.tx[tid] = tx;
-        L.dbits[tid] = db;
-        L.j[tid] = uint32_t(j);
-        if (tid == 0) L.start[kScanThreads] = tot;
-        __syncthreads();
-        emit_block_pairs(L, h, tot, run, keys, vals, passes, shift0);
-        __syncthreads();
+    // every input of the entry loaded at once (index clamped to the last
+    // entry), whether it is visible or not
+    const int64_t e = min<int64_t>(base + tid, n_total - 1);
+    const int c = int(e / E.n_in);
+    const int64_t j = e - int64_t(c) * E.n_in;
+    uint32_t cnt = P.tiles[c][j];
+    float2 q;
+    if (E.use_m2d) {
+        q = make_float2(P.m2d[c][j], P.m2d[c][E.n_in + j]);
+    } else {
+        const float GS_GLOBAL* qp = P.rec[c] + j * kRec;
+        q = make_float2(qp[0], qp[1]);
     }
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t v = h[p][tid];
-        if (v) atomicAdd(&hist[p * 256 + tid], v);
+    const int32_t rad = P.radius[c][j];
+    const uint32_t dbits = __float_as_uint(P.depth[c][j]);
+    if (base + tid >= n_total) cnt = 0;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(cnt, lds4, &tot);
+    uint32_t bt = 0, wd = 1, tx = 0, db = 0;
+    if (cnt > 0) {
+        vis_rect_of(P.tile_off[c], P.TX[c], P.TY[c], q, rad, &bt, &wd, &tx);
+        db = dbits;
     }
+    L.start[tid] = ex;
+    L.base_tile[tid] = bt;
+    L.w[tid] = wd;
+    L.tx[tid] = tx;
+    L.dbits[tid] = db;
+    L.j[tid] = uint32_t(j);
+    if (tid == 0) L.start[kScanThreads] = tot;
+    __syncthreads();
+    if (tile16) emit_block_pairs_compact(L, tot, run, tile16, dv);
+    else emit_block_pairs(L, nullptr, tot, run, keys, vals, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1459,77 +1446,17 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     const bool small = capacity <= kSmallSortCapacity;
     const int part = kSortThreads * (small ? kIptSmall : kIptLarge);
     const int64_t max_parts = (capacity + part - 1) / part;
-    int grid = int(std::min<int64_t>(max_parts, 256 * (small ? 6 : 3)));
-    if (grid < 1) grid = 1;
-    auto tile_pass = [&](int q, int cur, int hist_slot, int counter, bool last) {
-        uint32_t* st_next = last ? nullptr : S.status[(q + 1) & 1];
-        if (small)
-            launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
-                   vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
-                   S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
-                   static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
-                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr));
-        else
-            launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream, kb[cur],
-                   vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, S.hist + hist_slot * 256, S.status[q & 1], st_next,
-                   S.counters + counter, S.err, 32 + 8 * q, static_cast<const uint4*>(nullptr),
-                   static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
-                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr));
-    };
-
-    if (!per_tile) {
-        // Depth-first path.  The emission writes into buffer z and the tile
-        // passes ping-pong from there, ending in the caller's keys/vals; the
-        // depth sort runs in the other buffer x (its 32-bit keys in the
-        // first half of the key array), ending where it started.  Every pass
-        // takes the reduce-then-scan form; its partition counts live in the
-        // first status array (rows of `stride` partitions, enough for any
-        // pass: visible entries and pairs are both at most the capacity).
-        const int z = tile_passes & 1, x = z ^ 1;
-        // compact layout of the tile passes: tile ids fit 16 bits
-        const bool compact = tile_passes >= 1 && tile_bits <= 16;
-        uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(kb[x]), reinterpret_cast<uint32_t*>(kb[z])};
-        uint32_t* dv[2] = {vb[x], vb[z]};
-        const bool small_d = n_total <= kSmallSortCapacity;
-        const int part_d = kSortThreads * (small_d ? kIptSmall : kIptLarge);
-        const uint32_t stride = uint32_t((capacity + kPartMin - 1) / kPartMin + 1);
-        const int64_t parts_d = (std::min(n_total, capacity) + part_d - 1) / part_d;
-        uint32_t* counts = S.status[0];
-        if (nb > 0) {
-            if (scan_it == 1)
-                launch("vis_compact", k_vis_compact<1>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E,
-                       n_total, static_cast<const uint32_t*>(S.vis_sums), static_cast<const uint32_t*>(S.n_sorted),
-                       dk[0], S.vrec, S.emit_sums);
-            else
-                launch("vis_compact", k_vis_compact<kScanItLong>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream,
-                       E, n_total, static_cast<const uint32_t*>(S.vis_sums),
-                       static_cast<const uint32_t*>(S.n_sorted), dk[0], S.vrec, S.emit_sums);
-        }
-        for (int p = 0; p < 4; ++p) {
-            const int a = p & 1, b = a ^ 1;
-            // the last pass writes the records in depth order instead of the ranks
-            const uint4* gsrc = p == 3 ? static_cast<const uint4*>(S.vrec) : nullptr;
-            uint4* gdst = p == 3 ? S.srec : nullptr;
-            // the first pass ranks by position (the compaction stores no values)
-            const uint32_t* vin = p == 0 ? nullptr : dv[a];
-            if (small_d)
-                rts_pass<kIptSmall, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
-                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
-                                              p == 3 ? S.emit_sums : nullptr, stream);
-            else
-                rts_pass<kIptLarge, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
-                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
-                                              p == 3 ? S.emit_sums : nullptr, stream);
-        }
-        if (nb256 > 0) {
-            hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanWgThreads), 0, stream, S.emit_sums,
-                               static_cast<const uint32_t*>(S.n_sorted));
-            launch("emit", k_emit_sorted, dim3(unsigned(nb256)), dim3(256), 0, stream, static_cast<const uint4*>(S.srec),
-                   static_cast<const uint32_t*>(dk[0]), static_cast<const uint32_t*>(S.n_sorted),
-                   static_cast<const uint32_t*>(S.emit_sums), kb[z], vb[z],
-                   compact ? reinterpret_cast<uint16_t*>(vb[z]) : nullptr, compact ? kb[z] : nullptr);
-        }
-        int cur = z;
+    // Reduce-then-scan passes over the tile bits, from buffer `cur`; returns
+    // the buffer that holds the result.  The partition counts live in the
+    // first status array (rows of `stride` partitions, enough for any pass:
+    // visible entries and pairs are both at most the capacity).  Compact
+    // layout (tile ids fit 16 bits): 16-bit tile keys in the value arrays,
+    // depth << 32 | entry in the key arrays; the last pass writes the full
+    // pairs.
+    const uint32_t stride = uint32_t((capacity + kPartMin - 1) / kPartMin + 1);
+    uint32_t* counts = S.status[0];
+    const bool compact = tile_passes >= 1 && tile_bits <= 16;
+    auto tile_passes_rts = [&](int cur) {
         for (int q = 0; q < tile_passes; ++q) {
             const bool last = q + 1 == tile_passes;
             // wave-aggregated counting for the top digit, whose few values
@@ -1564,6 +1491,56 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
             }
             cur ^= 1;
         }
+        return cur;
+    };
+
+    if (!per_tile) {
+        // Depth-first path.  The emission writes into buffer z and the tile
+        // passes ping-pong from there, ending in the caller's keys/vals; the
+        // depth sort runs in the other buffer x (its 32-bit keys in the
+        // first half of the key array), ending where it started.  Every pass
+        // takes the reduce-then-scan form.
+        const int z = tile_passes & 1, x = z ^ 1;
+        uint32_t* dk[2] = {reinterpret_cast<uint32_t*>(kb[x]), reinterpret_cast<uint32_t*>(kb[z])};
+        uint32_t* dv[2] = {vb[x], vb[z]};
+        const bool small_d = n_total <= kSmallSortCapacity;
+        const int part_d = kSortThreads * (small_d ? kIptSmall : kIptLarge);
+        const int64_t parts_d = (std::min(n_total, capacity) + part_d - 1) / part_d;
+        if (nb > 0) {
+            if (scan_it == 1)
+                launch("vis_compact", k_vis_compact<1>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E,
+                       n_total, static_cast<const uint32_t*>(S.vis_sums), static_cast<const uint32_t*>(S.n_sorted),
+                       dk[0], S.vrec, S.emit_sums);
+            else
+                launch("vis_compact", k_vis_compact<kScanItLong>, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream,
+                       E, n_total, static_cast<const uint32_t*>(S.vis_sums),
+                       static_cast<const uint32_t*>(S.n_sorted), dk[0], S.vrec, S.emit_sums);
+        }
+        for (int p = 0; p < 4; ++p) {
+            const int a = p & 1, b = a ^ 1;
+            // the last pass writes the records in depth order instead of the ranks
+            const uint4* gsrc = p == 3 ? static_cast<const uint4*>(S.vrec) : nullptr;
+            uint4* gdst = p == 3 ? S.srec : nullptr;
+            // the first pass ranks by position (the compaction stores no values)
+            const uint32_t* vin = p == 0 ? nullptr : dv[a];
+            if (small_d)
+                rts_pass<kIptSmall, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
+                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
+                                              p == 3 ? S.emit_sums : nullptr, stream);
+            else
+                rts_pass<kIptLarge, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
+                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
+                                              p == 3 ? S.emit_sums : nullptr, stream);
+        }
+        if (nb256 > 0) {
+            hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanWgThreads), 0, stream, S.emit_sums,
+                               static_cast<const uint32_t*>(S.n_sorted));
+            launch("emit", k_emit_sorted, dim3(unsigned(nb256)), dim3(256), 0, stream, static_cast<const uint4*>(S.srec),
+                   static_cast<const uint32_t*>(dk[0]), static_cast<const uint32_t*>(S.n_sorted),
+                   static_cast<const uint32_t*>(S.emit_sums), kb[z], vb[z],
+                   compact ? reinterpret_cast<uint16_t*>(vb[z]) : nullptr, compact ? kb[z] : nullptr);
+        }
+        tile_passes_rts(z);
         if ((rc = check_launch("gs_bin_sort sort"))) return rc;
         launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream,
                static_cast<const uint64_t*>(kb[0]), S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err,
@@ -1576,11 +1553,9 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     int cur = (tile_passes + 1) & 1;
     if (nb > 0)
         launch("emit", k_emit, dim3(unsigned(nb)), dim3(kScanThreads), 0, stream, E, n_total, S.block_sums,
-               S.n_sorted, kb[cur], vb[cur], tile_passes, 32, part, S.hist, S.status[0]);
-    for (int q = 0; q < tile_passes; ++q) {
-        tile_pass(q, cur, q, q, q + 1 == tile_passes);
-        cur ^= 1;
-    }
+               S.n_sorted, kb[cur], vb[cur], compact ? reinterpret_cast<uint16_t*>(vb[cur]) : nullptr,
+               compact ? kb[cur] : nullptr);
+    cur = tile_passes_rts(cur);
     if ((rc = check_launch("gs_bin_sort sort"))) return rc;
     // cur == 1: the tile-ordered pairs are in the workspace copy
     launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream,
