@@ -230,9 +230,9 @@ int gs_project(const gs_scene* scene, const int32_t* active_idx, int64_t n_in,
  * Reads rec (or, when every camera has it, the mean2d copy), depth, radius
  * and tiles_touched of the projection.
  * *n_pairs_dev = number of pairs K.  If K > capacity nothing is sorted and
- * every tile range is empty; the caller re-runs with capacity >= K.  A
- * negative count reports an internal failure of the sort (a bounded wait
- * between workgroups timed out); the lists are then invalid.
+ * every tile range is empty; the caller re-runs with capacity >= K.  No
+ * workgroup waits for another (the radix passes take the reduce-then-scan
+ * form), so the call cannot stall.
  * keys/vals hold `capacity` entries (capacity <= GS_MAX_PAIRS).
  * Workspace: GS_OP_BIN_SORT with n_pairs = capacity.
  */
@@ -419,8 +419,7 @@ int gs_adam_step(float* const* params, float* const* grads, float* const* m,
  * Gaussian per occupied cube of edge delta0 / 2^L.  The finest cell of a point
  * is floor((mean - origin) * s) per axis in float32 with s = 2^(n_levels-1) /
  * delta0 (NaN -> 0, clamped to [0, 2^21)).  mean [3][n]; lod [n] (written).
- * n_levels in [1, 22].  If the internal sort fails (a bounded wait timed out)
- * every label is 255.  Workspace: GS_OP_VOXEL_LEVELS.
+ * n_levels in [1, 22].  Workspace: GS_OP_VOXEL_LEVELS.
  */
 int gs_voxel_levels(const float* mean, int64_t n, const float* origin, float delta0, int32_t n_levels,
                     uint8_t* lod, void* ws, size_t ws_bytes, hipStream_t stream);

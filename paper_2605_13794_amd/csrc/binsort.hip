@@ -1,6 +1,8 @@
-// Tile binning: scan of per-entry tile counts fused with key emission, an
-// LSD onesweep radix sort of the 64-bit (tile | depth) keys, and tile-range
-// detection.  All counts stay on the device (no host synchronisation).
+// Tile binning: scan of per-entry tile counts, pair emission, LSD radix
+// passes (reduce-then-scan form) over the tile bits, the depth order inside
+// each tile (a per-tile sort, or for long lists a depth sort of the visible
+// entries before the emission), and tile-range detection.  All counts stay on
+// the device (no host synchronisation).
 #include "common.h"
 
 namespace gsmi {
@@ -9,12 +11,6 @@ namespace gsmi {
 // Emission
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = 256;
-// Look-back status words: 2 flag bits (aggregate / inclusive prefix) over a
-// 30-bit count; a bounded number of polls before a wait reports failure.
-constexpr uint32_t kFlagAgg = 1u << 30;
-constexpr uint32_t kFlagInc = 2u << 30;
-constexpr uint32_t kValMask = (1u << 30) - 1u;
-constexpr uint32_t kSpinLimit = 1u << 24;
 
 constexpr int kScanItems = kScanThreads;  // entries per block (per round of a larger block)
 constexpr int kScanItLong = 8;            // rounds per block of a long depth-first input
@@ -206,24 +202,23 @@ __device__ uint64_t scan_sums_1wg(uint32_t* __restrict__ sums, int64_t nb, uint3
     return *carry_s;
 }
 
-// Partition-claim counters of the sort: one per radix pass.
+// Counters of the sort (counters[7]: the long tile segments).
 constexpr int kCounters = 8;
 
 // One workgroup: exclusive scan of the block sums, total pair count; also
-// clears the sort's histograms, partition counters and error flag.  With
+// clears the digit totals of the radix passes and the counters.  With
 // vis_sums (depth-first path) it also scans the visible-entry counts and
 // writes their total to n_sorted[1] (0 if the pairs do not fit).
 __global__ __launch_bounds__(kScanWgThreads) void k_scan_blocks(uint32_t* __restrict__ block_sums, int64_t n_blocks,
                                                      int64_t* __restrict__ n_pairs, int64_t capacity,
                                                      uint32_t* __restrict__ n_sorted, uint32_t* __restrict__ hist,
-                                                     uint32_t* __restrict__ counters, uint32_t* __restrict__ err,
+                                                     uint32_t* __restrict__ counters,
                                                      uint32_t* __restrict__ vis_sums) {
     __shared__ uint32_t lds4[kScanWgThreads / 64];
     __shared__ uint64_t carry_s;
     __shared__ uint32_t stage[kScanStage];
     for (int k = threadIdx.x; k < 8 * 256; k += kScanWgThreads) hist[k] = 0;
     if (threadIdx.x < kCounters) counters[threadIdx.x] = 0;
-    if (threadIdx.x == 0) *err = 0;
     const uint64_t K = scan_sums_1wg(block_sums, n_blocks, lds4, &carry_s, stage);
     const bool fits = int64_t(K) <= capacity;
     uint64_t nv = 0;
@@ -517,7 +512,7 @@ __global__ __launch_bounds__(256) void k_emit_sorted(const uint4* __restrict__ s
 }
 
 // ---------------------------------------------------------------------------
-// Onesweep LSD radix sort, 8-bit digits
+// LSD radix passes, 8-bit digits
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 256;
 constexpr int kWaves = kSortThreads / 64;
@@ -527,7 +522,6 @@ constexpr int kIptLarge = 15;
 constexpr int kIptSmall = 5;
 constexpr int64_t kSmallSortCapacity = 2 << 20;
 constexpr int kPartMin = kSortThreads * kIptSmall;
-constexpr int kLookWin = 8;  // predecessors read per look-back round trip
 
 template <int IPT, typename KeyT, typename ValT>
 struct SortLds {
@@ -538,7 +532,6 @@ struct SortLds {
     uint32_t gbase[256];
     uint32_t dig_off[256];
     uint32_t scan4[4];
-    uint32_t part;
 };
 
 // At least three wavefronts per SIMD (the 3,840-key instance would take
@@ -559,11 +552,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                                                    KeyT* __restrict__ keys_out, ValT* __restrict__ vals_out,
                                                    const uint32_t* __restrict__ n_sorted,
                                                    const uint32_t* __restrict__ hist_pass,
-                                                   uint32_t* __restrict__ status, uint32_t* __restrict__ status_next,
-                                                   uint32_t* __restrict__ counter, uint32_t* __restrict__ err,
+                                                   const uint32_t* __restrict__ offs, uint32_t offs_stride,
                                                    int shift, const uint4* __restrict__ gather_src,
                                                    uint4* __restrict__ gather_dst,
-                                                   const uint32_t* __restrict__ offs, uint32_t offs_stride,
                                                    uint64_t* __restrict__ final_keys,
                                                    uint32_t* __restrict__ final_vals, uint32_t* __restrict__ gsums) {
     constexpr int kSortPerThread = IPT;
@@ -586,7 +577,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     }
     if (trivial) {
         // every key has the same digit: the stable pass is the identity, so
-        // the pass is a copy (and clears the next pass's look-back status)
+        // the pass is a copy
         const uint32_t stride = gridDim.x * kSortThreads;
         if (gsums) {
             // a wavefront's 64 positions lie in one block of 256
@@ -614,27 +605,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             if (gather_src) gather_dst[i] = gather_src[v];
             else vals_out[i] = v;
         }
-        if (status_next)
-            for (uint32_t i = blockIdx.x * kSortThreads + tid; i < n_parts * 256u; i += stride) status_next[i] = 0;
         return;
     }
-    // With at least as many workgroups as partitions, the first n_parts
-    // workgroups claim one partition each and the rest leave at once, so the
-    // claim counter sees n_parts atomics; a smaller grid loops.
-    // A smaller grid loops, claiming one partition at a time.
-    // With offs (the reduce-then-scan form) partitions are independent and
-    // taken in grid-stride order.
-    if (blockIdx.x >= n_parts) return;
-    const bool one_each = gridDim.x >= n_parts;
-    uint32_t next_part = blockIdx.x;
-    for (;;) {
-        if (tid == 0) L.part = offs ? next_part : atomicAdd(counter, 1u);
-        next_part += gridDim.x;
+    // Partitions are independent (their offsets come scanned): taken in
+    // grid-stride order.
+    for (uint32_t part = blockIdx.x; part < n_parts; part += gridDim.x) {
         for (int k = tid; k < kWaves * 256; k += 256) (&L.wcnt[0][0])[k] = 0;
         __syncthreads();
-        const uint32_t part = L.part;
-        if (part >= n_parts) break;
-        if (status_next) status_next[part * 256 + tid] = 0;  // next pass starts clean
 
         // 1. load (wave-striped) and rank within the wavefront, stably
         const uint32_t wbase = part * kPart + uint32_t(w) * (kSortPerThread * 64);
@@ -685,14 +662,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             L.bin_start[tid] = ex;
         }
 
-        // 3a. publish this partition's count of bin tid at once (successors
-        // may be waiting for it); partition 0's count is already inclusive
-        uint32_t* st = offs ? nullptr : status + size_t(part) * 256 + tid;
-        if (!offs) st_agent(st, (part == 0 ? kFlagInc : kFlagAgg) | total);
+        // 3. this partition's first output position per bin: the digit's
+        // global offset plus the scanned counts of the earlier partitions
+        L.gbase[tid] = L.dig_off[tid] + offs[size_t(tid) * offs_stride + part] - L.bin_start[tid];
         __syncthreads();
 
-        // 4. stage in LDS in (digit, input order) order (before the look-back,
-        // so that the loaded keys are no longer live during the wait)
+        // 4. stage in LDS in (digit, input order) order
 #pragma unroll
         for (int it = 0; it < kSortPerThread; ++it) {
             const uint32_t idx = wbase + uint32_t(it) * 64 + lane;
@@ -702,51 +677,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                 L.keys[lp] = k_[it];
                 L.vals[lp] = v_[it];
             }
-        }
-
-        // 3b. decoupled look-back for bin tid
-        {
-            uint32_t excl = 0;
-            if (offs) {
-                // the partitions before this one: their counts of bin tid, scanned
-                excl = offs[size_t(tid) * offs_stride + part];
-            } else if (part > 0) {
-                // Walk back kLookWin predecessors per round trip: their status
-                // words are loaded together, then consumed in order up to the
-                // first inclusive prefix (done) or the first one not yet
-                // published (poll again from there).  Partition 0 always
-                // publishes an inclusive prefix, so the walk never passes it.
-                int64_t p = int64_t(part) - 1;
-                uint32_t spins = 0;
-                bool found = false;
-                while (!found) {
-                    uint32_t sw[kLookWin];
-#pragma unroll
-                    for (int q = 0; q < kLookWin; ++q)
-                        sw[q] = (p - q >= 0) ? ld_agent(status + size_t(p - q) * 256 + tid) : 0u;
-                    int used = 0;
-                    bool stop = false;
-#pragma unroll
-                    for (int q = 0; q < kLookWin; ++q) {
-                        const uint32_t flag = sw[q] & ~kValMask;
-                        if (!stop && flag != 0u) excl += sw[q] & kValMask;
-                        found = found || (!stop && flag == kFlagInc);
-                        if (!stop && flag == kFlagAgg) used = q + 1;
-                        stop = stop || flag != kFlagAgg;
-                    }
-                    if (found) break;
-                    p -= used;
-                    if (used < kLookWin) {  // status at p not yet published
-                        if (++spins > kSpinLimit) {
-                            atomicOr(err, 1u);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
-                st_agent(st, kFlagInc | ((excl + total) & kValMask));
-            }
-            L.gbase[tid] = L.dig_off[tid] + excl - L.bin_start[tid];
         }
         __syncthreads();
 
@@ -761,13 +691,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                 if (i < cnt) {
                     const KeyT key = L.keys[i];
                     const uint32_t g = L.gbase[uint32_t(key >> shift) & 255u] + i;
-                    if (g < n) {  // always true unless a look-back wait timed out
-                        keys_out[g] = key;
-                        const uint4 r = gather_src[uint32_t(L.vals[i])];
-                        gather_dst[g] = r;
-                        b = g >> 8;
-                        wv = r.w;
-                    }
+                    keys_out[g] = key;
+                    const uint4 r = gather_src[uint32_t(L.vals[i])];
+                    gather_dst[g] = r;
+                    b = g >> 8;
+                    wv = r.w;
                 }
                 wave_run_add(gsums, b, wv);
             }
@@ -776,27 +704,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             const KeyT key = L.keys[i];
             const uint32_t d = uint32_t(key >> shift) & 255u;
             const uint32_t g = L.gbase[d] + i;
-            if (g < n) {  // always true unless a look-back wait timed out
-                if (final_keys) {
-                    final_keys[g] = (uint64_t(key) << 32) | (uint64_t(L.vals[i]) >> 32);
-                    final_vals[g] = uint32_t(L.vals[i]);
-                    continue;
-                }
-                keys_out[g] = key;
-                if (gather_src) gather_dst[g] = gather_src[L.vals[i]];
-                else vals_out[g] = L.vals[i];
+            if (final_keys) {
+                final_keys[g] = (uint64_t(key) << 32) | (uint64_t(L.vals[i]) >> 32);
+                final_vals[g] = uint32_t(L.vals[i]);
+                continue;
             }
+            keys_out[g] = key;
+            if (gather_src) gather_dst[g] = gather_src[L.vals[i]];
+            else vals_out[g] = L.vals[i];
         }
-        if (one_each) break;
         __syncthreads();
     }
 }
 
-// Reduce-then-scan form of a pass (depth-first path): the digit counts of
-// every partition, then one scan per digit over the partitions, then
-// k_sort_pass with offs set ranks and scatters each partition independently.
-// Every partition waits for nothing, where the look-back form serialises on
-// a chain of round trips between partitions resident at the same time.
+// A radix pass in reduce-then-scan form: the digit counts of every partition,
+// then one scan per digit over the partitions, then k_sort_pass ranks and
+// scatters each partition independently.  No partition waits for another: a
+// decoupled look-back serialises on a chain of round trips between the
+// partitions resident at the same time, up to a thousand on this chip.
 // counts is digit-major: counts[d * stride + partition] (the scan reads a
 // digit's counts contiguously; a partition-major table made it 2.4x slower).
 template <int IPT, typename KeyT>
@@ -869,14 +794,11 @@ __global__ __launch_bounds__(kScanWgThreads) void k_part_scan(uint32_t* __restri
 // Tile ranges from the sorted keys: boundary b (0 <= b <= n_tiles) is the
 // first position whose tile id is >= b, found by binary search; tile t spans
 // [boundary t, boundary t+1).  Empty tiles get start == end, and when nothing
-// was sorted every range is empty.  Thread 0 also turns a timed-out look-back
-// wait of the sort into a negative pair count.
+// was sorted every range is empty.
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys,
                                                      const uint32_t* __restrict__ n_sorted, uint32_t n_tiles,
-                                                     uint32_t* __restrict__ ranges, const uint32_t* __restrict__ err,
-                                                     int64_t* __restrict__ n_pairs) {
+                                                     uint32_t* __restrict__ ranges) {
     const uint32_t b = blockIdx.x * 256 + threadIdx.x;
-    if (b == 0 && *err) *n_pairs = -1;
     if (b > n_tiles) return;
     const uint32_t n = *n_sorted;
     uint32_t lo = 0, hi = n;  // first index with tile >= b
@@ -1126,10 +1048,9 @@ struct SortWs {
     uint4* vrec;          // depth-first path only: records in entry order
     uint4* srec;          // depth-first path only: records in depth order
     uint32_t* n_sorted;
-    uint32_t* hist;
+    uint32_t* hist;      // digit totals of the radix passes (256 per pass)
     uint32_t* counters;
-    uint32_t* err;
-    uint32_t* status[2];
+    uint32_t* counts;    // partition counts of a radix pass, 256 rows of np
     uint64_t* keys_alt;
     uint32_t* vals_alt;
     uint32_t* long_list;
@@ -1156,10 +1077,8 @@ static SortWs carve_sort(void* ws, int64_t n_total, int64_t capacity, int64_t n_
     s.srec = depth_first ? cv.take<uint4>(size_t(n_total > 0 ? n_total : 1)) : nullptr;
     s.n_sorted = cv.take<uint32_t>(4);
     s.hist = cv.take<uint32_t>(8 * 256);
-    s.counters = cv.take<uint32_t>(8);
-    s.err = cv.take<uint32_t>(4);
-    s.status[0] = cv.take<uint32_t>(size_t(np) * 256);
-    s.status[1] = cv.take<uint32_t>(size_t(np) * 256);
+    s.counters = cv.take<uint32_t>(kCounters);
+    s.counts = cv.take<uint32_t>(size_t(np) * 256);
     s.keys_alt = cv.take<uint64_t>(size_t(capacity > 0 ? capacity : 1));
     s.vals_alt = cv.take<uint32_t>(size_t(capacity > 0 ? capacity : 1));
     s.long_list = cv.take<uint32_t>(size_t(n_tiles > 0 ? n_tiles : 1));
@@ -1197,12 +1116,8 @@ __device__ __forceinline__ uint32_t fine_cell(float m, float o, float sc) {
     return uint32_t(fminf(fmaxf(q, 0.f), 2097151.f));
 }
 
-__global__ void k_voxel_init(uint32_t* __restrict__ hist, uint32_t* __restrict__ counters,
-                             uint32_t* __restrict__ err, uint32_t* __restrict__ n_sorted, uint32_t n) {
-    for (int k = threadIdx.x; k < 8 * 256; k += blockDim.x) hist[k] = 0;
-    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+__global__ void k_voxel_init(uint32_t* __restrict__ n_sorted, uint32_t n) {
     if (threadIdx.x == 0) {
-        *err = 0;
         n_sorted[0] = n;
         n_sorted[1] = 0;
     }
@@ -1210,42 +1125,20 @@ __global__ void k_voxel_init(uint32_t* __restrict__ hist, uint32_t* __restrict__
 
 __global__ __launch_bounds__(256) void k_voxel_codes(const float* __restrict__ mean, int64_t n, float o0, float o1,
                                                      float o2, float sc, uint64_t* __restrict__ keys,
-                                                     uint32_t* __restrict__ vals, int part,
-                                                     uint32_t* __restrict__ hist, uint32_t* __restrict__ status0) {
-    __shared__ uint32_t h[8][256];
-    const uint32_t tid = threadIdx.x;
-    {
-        const uint32_t n_parts = uint32_t((n + part - 1) / part);
-        for (uint32_t k = blockIdx.x * 256 + tid; k < n_parts * 256u; k += gridDim.x * 256) status0[k] = 0;
-    }
-    for (int k = tid; k < 8 * 256; k += 256) (&h[0][0])[k] = 0;
-    __syncthreads();
-    const int64_t span = (n + 255) / 256 * 256;  // whole wavefronts iterate together
-    for (int64_t i = int64_t(blockIdx.x) * 256 + tid; i < span; i += int64_t(gridDim.x) * 256) {
-        const bool valid = i < n;
-        uint64_t code = 0;
-        if (valid) {
-            const uint32_t cx = fine_cell(mean[i], o0, sc);
-            const uint32_t cy = fine_cell(mean[n + i], o1, sc);
-            const uint32_t cz = fine_cell(mean[2 * n + i], o2, sc);
-            code = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
-            keys[i] = code;
-            vals[i] = uint32_t(i);
-        }
-        hist_add(h, code, valid, 8, 0);
-    }
-    __syncthreads();
-    for (int p = 0; p < 8; ++p) {
-        const uint32_t v = h[p][tid];
-        if (v) atomicAdd(&hist[p * 256 + tid], v);
-    }
+                                                     uint32_t* __restrict__ vals) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t cx = fine_cell(mean[i], o0, sc);
+    const uint32_t cy = fine_cell(mean[n + i], o1, sc);
+    const uint32_t cz = fine_cell(mean[2 * n + i], o2, sc);
+    keys[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+    vals[i] = uint32_t(i);
 }
 
-// Label of the point at sorted position p from its predecessor's code; a
-// timed-out look-back wait of the sort writes 255 (no valid level).
+// Label of the point at sorted position p from its predecessor's code.
 __global__ __launch_bounds__(256) void k_voxel_label(const uint64_t* __restrict__ keys,
                                                      const uint32_t* __restrict__ vals, int64_t n, int n_levels,
-                                                     const uint32_t* __restrict__ err, uint8_t* __restrict__ lod) {
+                                                     uint8_t* __restrict__ lod) {
     const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (p >= n) return;
     int label = 0;
@@ -1258,17 +1151,16 @@ __global__ __launch_bounds__(256) void k_voxel_label(const uint64_t* __restrict_
             label = max(0, n_levels - 1 - h / 3);
         }
     }
-    lod[vals[p]] = *err ? uint8_t(255) : uint8_t(label);
+    lod[vals[p]] = uint8_t(label);
 }
 
 struct VoxWs {
     uint64_t* keys[2];
     uint32_t* vals[2];
-    uint32_t* status[2];
-    uint32_t* hist;
-    uint32_t* counters;
-    uint32_t* err;
+    uint32_t* counts;  // partition counts of a radix pass, 256 rows of np
+    uint32_t* hist;    // digit totals of the eight passes
     uint32_t* n_sorted;
+    uint32_t np;
     size_t bytes;
 };
 
@@ -1280,12 +1172,11 @@ static VoxWs carve_vox(void* ws, int64_t n) {
     for (int b = 0; b < 2; ++b) {
         s.keys[b] = cv.take<uint64_t>(m);
         s.vals[b] = cv.take<uint32_t>(m);
-        s.status[b] = cv.take<uint32_t>(size_t(np) * 256);
     }
+    s.counts = cv.take<uint32_t>(size_t(np) * 256);
     s.hist = cv.take<uint32_t>(8 * 256);
-    s.counters = cv.take<uint32_t>(8);
-    s.err = cv.take<uint32_t>(4);
     s.n_sorted = cv.take<uint32_t>(4);
+    s.np = uint32_t(np);
     s.bytes = cv.used();
     return s;
 }
@@ -1299,7 +1190,7 @@ constexpr int64_t kRtsGrid = 2048;
 // partitions), their scan (digit totals into total), then the ranking scatter.
 template <int IPT, typename KeyT, typename ValT = uint32_t>
 static void rts_pass(const KeyT* kin, const ValT* vin, KeyT* kout, ValT* vout, const uint32_t* n_sorted, int shift,
-                     bool few, uint32_t* counts, uint32_t stride, uint32_t* total, uint32_t* err, int64_t max_parts,
+                     bool few, uint32_t* counts, uint32_t stride, uint32_t* total, int64_t max_parts,
                      const uint4* gsrc, uint4* gdst, uint64_t* final_keys, uint32_t* final_vals,
                      uint32_t* gsums, hipStream_t stream) {
     const int grid = int(std::max<int64_t>(1, std::min<int64_t>(max_parts, kRtsGrid)));
@@ -1308,9 +1199,8 @@ static void rts_pass(const KeyT* kin, const ValT* vin, KeyT* kout, ValT* vout, c
     hipLaunchKernelGGL(k_part_scan, dim3(256), dim3(kScanWgThreads), 0, stream, counts, stride, n_sorted,
                        int(kSortThreads * IPT), total);
     launch("sort_pass", k_sort_pass<IPT, KeyT, ValT>, dim3(grid), dim3(kSortThreads), 0, stream, kin, vin, kout, vout,
-           n_sorted, static_cast<const uint32_t*>(total), static_cast<uint32_t*>(nullptr),
-           static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr), err, shift, gsrc, gdst,
-           static_cast<const uint32_t*>(counts), stride, final_keys, final_vals, gsums);
+           n_sorted, static_cast<const uint32_t*>(total), static_cast<const uint32_t*>(counts), stride, shift, gsrc,
+           gdst, final_keys, final_vals, gsums);
 }
 
 }  // namespace gsmi
@@ -1340,34 +1230,25 @@ extern "C" int gs_voxel_levels(const float* mean, int64_t n, const float* origin
     const float sc = float(1u << (n_levels - 1)) / delta0;
     const bool small = n <= kSmallSortCapacity;
     const int part = kSortThreads * (small ? kIptSmall : kIptLarge);
-    int grid = int(std::min<int64_t>((n + part - 1) / part, 256 * (small ? 6 : 3)));
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_voxel_init, dim3(1), dim3(256), 0, stream, V.hist, V.counters, V.err, V.n_sorted,
-                       uint32_t(n));
-    // few workgroups, so that the LDS histograms reach the global ones with
-    // few atomics
-    const int cb = int(std::min<int64_t>((n + 255) / 256, 256));
-    launch("voxel_codes", k_voxel_codes, dim3(cb), dim3(256), 0, stream, mean, n, origin[0], origin[1], origin[2], sc,
-           V.keys[0], V.vals[0], part, V.hist, V.status[0]);
+    const int64_t parts = (n + part - 1) / part;
+    hipLaunchKernelGGL(k_voxel_init, dim3(1), dim3(64), 0, stream, V.n_sorted, uint32_t(n));
+    launch("voxel_codes", k_voxel_codes, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream, mean, n, origin[0],
+           origin[1], origin[2], sc, V.keys[0], V.vals[0]);
+    // eight passes over the 64-bit codes (their digits may take few values:
+    // wave-aggregated counting), ending in buffer 0
     for (int p = 0; p < 8; ++p) {
         const int a = p & 1, b = a ^ 1;
-        uint32_t* st_next = p < 7 ? V.status[b] : nullptr;
         if (small)
-            launch("sort_pass", k_sort_pass<kIptSmall, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
-                   V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
-                   static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
-                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
-                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr));
+            rts_pass<kIptSmall, uint64_t>(V.keys[a], V.vals[a], V.keys[b], V.vals[b], V.n_sorted, 8 * p, true,
+                                          V.counts, V.np, V.hist + p * 256, parts, nullptr, nullptr, nullptr, nullptr,
+                                          nullptr, stream);
         else
-            launch("sort_pass", k_sort_pass<kIptLarge, uint64_t>, dim3(grid), dim3(kSortThreads), 0, stream,
-                   V.keys[a], V.vals[a], V.keys[b], V.vals[b], static_cast<const uint32_t*>(V.n_sorted),
-                   static_cast<const uint32_t*>(V.hist + p * 256), V.status[a], st_next, V.counters + p, V.err, 8 * p,
-                   static_cast<const uint4*>(nullptr), static_cast<uint4*>(nullptr), static_cast<const uint32_t*>(nullptr), 0u,
-                   static_cast<uint64_t*>(nullptr), static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr));
+            rts_pass<kIptLarge, uint64_t>(V.keys[a], V.vals[a], V.keys[b], V.vals[b], V.n_sorted, 8 * p, true,
+                                          V.counts, V.np, V.hist + p * 256, parts, nullptr, nullptr, nullptr, nullptr,
+                                          nullptr, stream);
     }
     launch("voxel_label", k_voxel_label, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream,
-           static_cast<const uint64_t*>(V.keys[0]), static_cast<const uint32_t*>(V.vals[0]), n, int(n_levels),
-           static_cast<const uint32_t*>(V.err), lod);
+           static_cast<const uint64_t*>(V.keys[0]), static_cast<const uint32_t*>(V.vals[0]), n, int(n_levels), lod);
     return check_launch("gs_voxel_levels");
 }
 
@@ -1435,7 +1316,7 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
                    n_total, S.block_sums, S.vis_sums);
     }
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanWgThreads), 0, stream, S.block_sums, nb, n_pairs_dev, capacity,
-                       S.n_sorted, S.hist, S.counters, S.err, per_tile ? nullptr : S.vis_sums);
+                       S.n_sorted, S.hist, S.counters, per_tile ? nullptr : S.vis_sums);
     if ((rc = check_launch("gs_bin_sort scan"))) return rc;
     if (capacity == 0) {
         rc = fill_u32(tile_ranges, 0u, size_t(2 * total_tiles), stream);
@@ -1448,13 +1329,13 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     const int64_t max_parts = (capacity + part - 1) / part;
     // Reduce-then-scan passes over the tile bits, from buffer `cur`; returns
     // the buffer that holds the result.  The partition counts live in the
-    // first status array (rows of `stride` partitions, enough for any pass:
+    // counts array (rows of `stride` partitions, enough for any pass:
     // visible entries and pairs are both at most the capacity).  Compact
     // layout (tile ids fit 16 bits): 16-bit tile keys in the value arrays,
     // depth << 32 | entry in the key arrays; the last pass writes the full
     // pairs.
     const uint32_t stride = uint32_t((capacity + kPartMin - 1) / kPartMin + 1);
-    uint32_t* counts = S.status[0];
+    uint32_t* counts = S.counts;
     const bool compact = tile_passes >= 1 && tile_bits <= 16;
     auto tile_passes_rts = [&](int cur) {
         for (int q = 0; q < tile_passes; ++q) {
@@ -1474,19 +1355,19 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
                 uint32_t* fv = last ? vb[cur ^ 1] : nullptr;
                 if (small)
                     rts_pass<kIptSmall, uint16_t, uint64_t>(tin, kb[cur], tout, dvout, S.n_sorted, 8 * q, few,
-                                                            counts, stride, hist, S.err, max_parts, nullptr, nullptr,
+                                                            counts, stride, hist, max_parts, nullptr, nullptr,
                                                             fk, fv, nullptr, stream);
                 else
                     rts_pass<kIptLarge, uint16_t, uint64_t>(tin, kb[cur], tout, dvout, S.n_sorted, 8 * q, few,
-                                                            counts, stride, hist, S.err, max_parts, nullptr, nullptr,
+                                                            counts, stride, hist, max_parts, nullptr, nullptr,
                                                             fk, fv, nullptr, stream);
             } else if (small) {
                 rts_pass<kIptSmall, uint64_t>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, 32 + 8 * q,
-                                              few, counts, stride, hist, S.err, max_parts, nullptr, nullptr,
+                                              few, counts, stride, hist, max_parts, nullptr, nullptr,
                                               nullptr, nullptr, nullptr, stream);
             } else {
                 rts_pass<kIptLarge, uint64_t>(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], S.n_sorted, 32 + 8 * q,
-                                              few, counts, stride, hist, S.err, max_parts, nullptr, nullptr,
+                                              few, counts, stride, hist, max_parts, nullptr, nullptr,
                                               nullptr, nullptr, nullptr, stream);
             }
             cur ^= 1;
@@ -1525,11 +1406,11 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
             const uint32_t* vin = p == 0 ? nullptr : dv[a];
             if (small_d)
                 rts_pass<kIptSmall, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
-                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
+                                              stride, S.hist + p * 256, parts_d, gsrc, gdst, nullptr, nullptr,
                                               p == 3 ? S.emit_sums : nullptr, stream);
             else
                 rts_pass<kIptLarge, uint32_t>(dk[a], vin, dk[b], dv[b], S.n_sorted + 1, 8 * p, p == 3, counts,
-                                              stride, S.hist + p * 256, S.err, parts_d, gsrc, gdst, nullptr, nullptr,
+                                              stride, S.hist + p * 256, parts_d, gsrc, gdst, nullptr, nullptr,
                                               p == 3 ? S.emit_sums : nullptr, stream);
         }
         if (nb256 > 0) {
@@ -1543,8 +1424,7 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
         tile_passes_rts(z);
         if ((rc = check_launch("gs_bin_sort sort"))) return rc;
         launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream,
-               static_cast<const uint64_t*>(kb[0]), S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err,
-               n_pairs_dev);
+               static_cast<const uint64_t*>(kb[0]), S.n_sorted, uint32_t(total_tiles), tile_ranges);
         return check_launch("gs_bin_sort ranges");
     }
 
@@ -1559,7 +1439,7 @@ extern "C" int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int 
     if ((rc = check_launch("gs_bin_sort sort"))) return rc;
     // cur == 1: the tile-ordered pairs are in the workspace copy
     launch("tile_ranges", k_tile_ranges, dim3(unsigned((total_tiles + 1 + 255) / 256)), dim3(256), 0, stream,
-           static_cast<const uint64_t*>(kb[cur]), S.n_sorted, uint32_t(total_tiles), tile_ranges, S.err, n_pairs_dev);
+           static_cast<const uint64_t*>(kb[cur]), S.n_sorted, uint32_t(total_tiles), tile_ranges);
     if ((rc = check_launch("gs_bin_sort ranges"))) return rc;
     // counters[7] (cleared by the scan) counts the long segments
     uint32_t* long_count = S.counters + 7;

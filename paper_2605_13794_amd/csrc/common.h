@@ -173,15 +173,6 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Agent-scope relaxed atomics for cross-workgroup flags (L2 is per XCD, so
-// the compiler emits the coherent forms for this scope).
-__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Small fill kernel launcher (graph-capture friendly, unlike memset nodes).
 int fill_u32(void* dst, uint32_t value, size_t count, hipStream_t s);
 
