@@ -260,70 +260,55 @@ struct EmitLds {
     uint32_t j[kScanThreads];
 };
 
-// Adds one key's digits to the per-pass LDS histograms; a digit shared by the
-// whole wavefront is added once.
-__device__ __forceinline__ void hist_add(uint32_t (*h)[256], uint64_t key, bool valid, int passes, int shift0) {
-    if (passes == 0) return;
-    const uint64_t vm = ballot(valid);
-    if (!vm) return;
-    const int first = __ffsll((unsigned long long)vm) - 1;
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t d = uint32_t(key >> (shift0 + 8 * p)) & 255u;
-        const uint32_t d0 = __shfl(d, first, 64);
-        if (__all(!valid || d == d0)) {
-            if (lane_id() == uint32_t(first)) atomicAdd(&h[p][d0], popc64(vm));
-        } else if (valid) {
-            atomicAdd(&h[p][d], 1u);
+// Writes a block's `tot` pairs from position run on: output o belongs to the
+// last entry l with start[l] <= o (zero-count entries share the next start);
+// its tile is the (o - start[l])-th of the entry's rectangle in row-major
+// order.  Each thread takes kEmitIlp outputs at a time and interleaves their
+// binary searches (always 8 steps over the 256 starts): a block whose entries
+// cover thousands of tiles (6,150 pairs in one block of the 1M view, against
+// 121 on average) runs its rounds a quarter as long.  COMPACT: the layout of
+// the tile passes (at most 65,536 tiles), tile id as 16 bits in out16 and
+// depth bits << 32 | entry in out64; else keys out64 = tile << 32 | depth
+// bits and values out32 = entry.
+constexpr int kEmitIlp = 4;
+
+template <bool COMPACT>
+__device__ __forceinline__ void emit_block_pairs(const EmitLds& L, uint32_t tot, uint32_t run,
+                                                 uint64_t* __restrict__ out64, uint32_t* __restrict__ out32,
+                                                 uint16_t* __restrict__ out16) {
+    for (uint32_t o0 = threadIdx.x; o0 < tot; o0 += kEmitIlp * kScanThreads) {
+        uint32_t lo[kEmitIlp], hi[kEmitIlp];
+#pragma unroll
+        for (int u = 0; u < kEmitIlp; ++u) {
+            lo[u] = 0;
+            hi[u] = kScanThreads;
         }
-    }
-}
-
-// Output o of a block belongs to the last entry l with start[l] <= o
-// (zero-count entries share the next start); its tile is the
-// (o - start[l])-th of the entry's rectangle in row-major order.  Returns l.
-__device__ __forceinline__ uint32_t block_pair(const EmitLds& L, uint32_t o, uint32_t* tile) {
-    uint32_t lo = 0, hi = kScanThreads;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (L.start[mid] <= o) lo = mid;
-        else hi = mid;
-    }
-    const uint32_t local = o - L.start[lo];
-    const uint32_t ww = L.w[lo];
-    const uint32_t dy = local / ww, dx = local - dy * ww;
-    *tile = L.base_tile[lo] + dy * L.tx[lo] + dx;
-    return lo;
-}
-
-// Writes a block's `tot` pairs at keys/vals[run ...].  The whole block
-// iterates together (the histogram ballots).
-__device__ __forceinline__ void emit_block_pairs(const EmitLds& L, uint32_t (*h)[256], uint32_t tot, uint32_t run,
-                                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, int passes,
-                                                 int shift0) {
-    const uint32_t span = (tot + kScanThreads - 1) / kScanThreads * kScanThreads;
-    for (uint32_t o = threadIdx.x; o < span; o += kScanThreads) {
-        const bool valid = o < tot;
-        uint64_t key = 0;
-        if (valid) {
-            uint32_t tile;
-            const uint32_t l = block_pair(L, o, &tile);
-            key = (uint64_t(tile) << 32) | uint64_t(L.dbits[l]);
-            keys[run + o] = key;
-            vals[run + o] = L.j[l];
+#pragma unroll
+        for (int step = 0; step < 8; ++step) {
+#pragma unroll
+            for (int u = 0; u < kEmitIlp; ++u) {
+                const uint32_t mid = (lo[u] + hi[u]) >> 1;
+                if (L.start[mid] <= o0 + u * kScanThreads) lo[u] = mid;
+                else hi[u] = mid;
+            }
         }
-        hist_add(h, key, valid, passes, shift0);
-    }
-}
-
-// The same pairs in the compact layout of the tile passes (at most 65,536
-// tiles): the tile id as 16 bits, and depth bits << 32 | entry as the value.
-__device__ __forceinline__ void emit_block_pairs_compact(const EmitLds& L, uint32_t tot, uint32_t run,
-                                                         uint16_t* __restrict__ tile16, uint64_t* __restrict__ dv) {
-    for (uint32_t o = threadIdx.x; o < tot; o += kScanThreads) {
-        uint32_t tile;
-        const uint32_t l = block_pair(L, o, &tile);
-        tile16[run + o] = uint16_t(tile);
-        dv[run + o] = (uint64_t(L.dbits[l]) << 32) | uint64_t(L.j[l]);
+#pragma unroll
+        for (int u = 0; u < kEmitIlp; ++u) {
+            const uint32_t o = o0 + u * kScanThreads;
+            if (o >= tot) break;
+            const uint32_t l = lo[u];
+            const uint32_t local = o - L.start[l];
+            const uint32_t ww = L.w[l];
+            const uint32_t dy = local / ww, dx = local - dy * ww;
+            const uint32_t tile = L.base_tile[l] + dy * L.tx[l] + dx;
+            if (COMPACT) {
+                out16[run + o] = uint16_t(tile);
+                out64[run + o] = (uint64_t(L.dbits[l]) << 32) | uint64_t(L.j[l]);
+            } else {
+                out64[run + o] = (uint64_t(tile) << 32) | uint64_t(L.dbits[l]);
+                out32[run + o] = L.j[l];
+            }
+        }
     }
 }
 
@@ -374,8 +359,8 @@ __global__ __launch_bounds__(256) void k_emit(EmitIn E, int64_t n_total, const u
     L.j[tid] = uint32_t(j);
     if (tid == 0) L.start[kScanThreads] = tot;
     __syncthreads();
-    if (tile16) emit_block_pairs_compact(L, tot, run, tile16, dv);
-    else emit_block_pairs(L, nullptr, tot, run, keys, vals, 0, 0);
+    if (tile16) emit_block_pairs<true>(L, tot, run, dv, nullptr, tile16);
+    else emit_block_pairs<false>(L, tot, run, keys, vals, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -507,8 +492,8 @@ __global__ __launch_bounds__(256) void k_emit_sorted(const uint4* __restrict__ s
     L.j[tid] = r.x;
     if (tid == 0) L.start[kScanThreads] = tot;
     __syncthreads();
-    if (tile16) emit_block_pairs_compact(L, tot, offs[blockIdx.x], tile16, dv);
-    else emit_block_pairs(L, nullptr, tot, offs[blockIdx.x], keys, vals, 0, 0);
+    if (tile16) emit_block_pairs<true>(L, tot, offs[blockIdx.x], dv, nullptr, tile16);
+    else emit_block_pairs<false>(L, tot, offs[blockIdx.x], keys, vals, nullptr);
 }
 
 // ---------------------------------------------------------------------------
