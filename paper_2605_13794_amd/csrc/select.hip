@@ -317,6 +317,8 @@ __device__ void init_state(SelState& s, int mode, double total, float frac, uint
     }
 }
 
+constexpr int kSelIlp = 8;
+
 // Histogram of digit pass `pass` (shift 24 - 8 pass) over the elements whose
 // higher digits match the picks of the earlier passes (replayed per block).
 // mode 0 also sums the total mass in pass 0.
@@ -345,15 +347,25 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ v, i
     const uint32_t pre = st.prefix;
     const uint32_t hi_mask = shift >= 24 ? 0u : (0xffffffffu << (shift + 8));
     double tsum = 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-        const float x = v[i];
-        if (mode == 0 && !(x > 0.f)) continue;
-        if (mode == 0 && pass == 0) tsum += double(x);
-        const uint32_t b = __float_as_uint(x);
-        if ((b & hi_mask) != (pre & hi_mask)) continue;
-        const uint32_t d = (b >> shift) & 255u;
-        atomicAdd(&lc[d], 1u);
-        if (mode == 0) atomicAdd(&lm[d], double(x));
+    // kSelIlp values per thread per round, loaded before the first is used
+    // (index clamped to the last value)
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    for (int64_t i0 = int64_t(blockIdx.x) * 256 + threadIdx.x; i0 < n; i0 += stride * kSelIlp) {
+        float xs[kSelIlp];
+#pragma unroll
+        for (int u = 0; u < kSelIlp; ++u) xs[u] = v[min(i0 + u * stride, n - 1)];
+#pragma unroll
+        for (int u = 0; u < kSelIlp; ++u) {
+            const float x = xs[u];
+            if (i0 + u * stride >= n) continue;
+            if (mode == 0 && !(x > 0.f)) continue;
+            if (mode == 0 && pass == 0) tsum += double(x);
+            const uint32_t b = __float_as_uint(x);
+            if ((b & hi_mask) != (pre & hi_mask)) continue;
+            const uint32_t d = (b >> shift) & 255u;
+            atomicAdd(&lc[d], 1u);
+            if (mode == 0) atomicAdd(&lm[d], double(x));
+        }
     }
     __syncthreads();
     if (lc[threadIdx.x]) {
