@@ -233,14 +233,16 @@ def test_bin_sort_segment_paths(oracle):
     assert_same_ranges(u32(fr.ranges), ranges)
 
 
+@pytest.mark.parametrize("path", ["depth_first", "per_tile"])
 @pytest.mark.parametrize("layout", ["one_tile_pass", "wide_tile_ids"])
-def test_bin_sort_depth_first_layouts(oracle, layout):
-    """Long-list (depth-first) binning, forced by a pair capacity above 256
-    per tile, in the two layouts of its tile passes: a 256-tile image (one
-    tile pass over 16-bit tile ids that writes the full pairs), and three 4K
-    views in one batch, whose 97,200 global tile ids need 17 bits (three
-    passes over the full 64-bit keys).  Bit-exact against the reference,
-    camera by camera, with each camera's list after the previous ones."""
+def test_bin_sort_layouts(oracle, layout, path):
+    """Both binning paths (depth-first forced by a pair capacity above 256
+    per tile, per-tile by the smallest capacity) in the two layouts of their
+    tile passes: a 256-tile image (one tile pass over 16-bit tile ids that
+    writes the full pairs), and three 4K views in one batch, whose 97,200
+    global tile ids need 17 bits (three passes over the full 64-bit keys).
+    Bit-exact against the reference, camera by camera, with each camera's
+    list after the previous ones."""
     dev = device()
     G = gsmi()
     if layout == "one_tile_pass":
@@ -255,8 +257,8 @@ def test_bin_sort_depth_first_layouts(oracle, layout):
     tiles = [G.gs_num_tiles(c.width, c.height) for c in cams]
     assert (sum(tiles) > 65536) == (layout == "wide_tile_ids")
     K = sum(r[3] for r in refs)
-    print(f"[depth-first {layout}] tiles={sum(tiles)} K={K}", flush=True)
-    fr = _frame(cams, sc.n, dev, capacity=256 * sum(tiles) + 1)
+    print(f"[{path} {layout}] tiles={sum(tiles)} K={K}", flush=True)
+    fr = _frame(cams, sc.n, dev, capacity=256 * sum(tiles) + 1 if path == "depth_first" else K)
     for c, (cam, r) in enumerate(zip(cams, refs)):
         # the one-pass case takes the rectangles' centres from the records
         fr.proj[c] = upload_projection(r[2], cam.width, cam.height, dev, centre=layout != "one_tile_pass")
