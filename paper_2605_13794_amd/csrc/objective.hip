@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ X, c
     }
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (uint32_t o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ X, c
     }
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (uint32_t o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_photo_final(const double* __restrict__ 
     r0[threadIdx.x] = a;
     r1[threadIdx.x] = b;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (uint32_t o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) { r0[threadIdx.x] += r0[threadIdx.x + o]; r1[threadIdx.x] += r1[threadIdx.x + o]; }
         __syncthreads();
     }
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void k_scale_reg_sum(const float* __restrict__
     rs[threadIdx.x] = s;
     rc[threadIdx.x] = cnt;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (uint32_t o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) { rs[threadIdx.x] += rs[threadIdx.x + o]; rc[threadIdx.x] += rc[threadIdx.x + o]; }
         __syncthreads();
     }
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_scale_reg_final(const double* __restric
     rs[threadIdx.x] = s;
     rc[threadIdx.x] = c;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (uint32_t o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) { rs[threadIdx.x] += rs[threadIdx.x + o]; rc[threadIdx.x] += rc[threadIdx.x + o]; }
         __syncthreads();
     }

@@ -196,11 +196,11 @@ __device__ __forceinline__ uint32_t maybe_visible(const CamSet& C, const float m
 //
 // Chunk sizes of the list-building kernels: small inputs use 512 entries per
 // workgroup (more workgroups in flight: 15 -> 10 us for the cull and 17 -> 7 us
-// for the visible list on a 0.6M-entry view); large ones use bigger chunks so
-// that the single counter sees at most a few thousand atomics.
+// for the visible list on a 0.6M-entry view); the visible list of a large
+// input uses 4,096 so that the single counter sees at most a few thousand
+// atomics (a large projection takes the single pass and builds no list).
 constexpr int64_t kSmallListInput = 2 << 20;
 constexpr int kChunkSmall = 512;
-constexpr int kCullChunkLarge = 2048;
 constexpr int kVisChunkLarge = 4096;
 
 template <int kChunk>
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void k_export_d2(const float* __restrict__ d2,
     for (int k = 0; k < 9; ++k) out[int64_t(k) * n_in + j] = d2[j * kD2Stride + k];
 }
 
-__global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __restrict__ active, int64_t n_in,
+__global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __restrict__ active, int64_t /*n_in*/,
                                                      const uint32_t* __restrict__ list,
                                                      const uint32_t* __restrict__ count, CamSet C, BwdIn B,
                                                      GradOut GO) {
@@ -599,7 +599,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(SceneP P, const int32_t* __
 // old values before storing any, so the loads of a thread are all in flight
 // together.
 __global__ __launch_bounds__(256) void k_project_bwd_sh(SceneP P, const int32_t* __restrict__ active,
-                                                        int64_t n_in, const uint32_t* __restrict__ list,
+                                                        int64_t /*n_in*/, const uint32_t* __restrict__ list,
                                                         const uint32_t* __restrict__ count, CamSet C, BwdIn B,
                                                         GradOut GO) {
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_gate_compact(GateArgs G, int64_t chunk,
     red[1][threadIdx.x] = sa;
     red[2][threadIdx.x] = sk;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (uint32_t o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o)
             for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
         __syncthreads();
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_gate_compact(GateArgs G, int64_t chunk,
     __syncthreads();
     red[0][threadIdx.x] = fb ? pk : pa;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (uint32_t o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[0][threadIdx.x] += red[0][threadIdx.x + o];
         __syncthreads();
     }
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void k_sel_hist(const float* __restrict__ v, i
     if (mode == 0 && pass == 0) {
         sd[threadIdx.x] = tsum;
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
+        for (uint32_t o = 128; o > 0; o >>= 1) {
             if (threadIdx.x < o) sd[threadIdx.x] += sd[threadIdx.x + o];
             __syncthreads();
         }
