@@ -170,6 +170,36 @@ def test_bin_sort_large_persistent_grid(oracle):
     assert_same_ranges(u32(fr.ranges), ranges)
 
 
+def test_bin_sort_partition_loop(oracle):
+    """More than 2,048 partitions of 3,840 keys in a pass (7.9M pairs), so
+    every workgroup of the counts and the scatter loops over partitions: a
+    synthetic projection of 2.5M entries over a 1080p view (centres uniform
+    over the image and a margin, radii 2-14 px, 10 % culled, depths from 400
+    values so that equal keys occur), ~9M pairs on the depth-first path,
+    bit-exact against the reference's sort of the same records."""
+    dev = device()
+    rng = np.random.default_rng(77)
+    n, W, H = 2_500_000, 1920, 1080
+    mean2d = np.stack([rng.uniform(-40.0, W + 40.0, n), rng.uniform(-40.0, H + 40.0, n)])
+    mean2d = mean2d.astype(np.float32).astype(np.float64)
+    radius = rng.integers(2, 15, n).astype(np.int32)
+    radius[rng.random(n) < 0.1] = 0
+    depth = (rng.integers(0, 400, n) * 0.75 + 10.0).astype(np.float32)
+    conic = np.tile(np.array([[1.0], [0.0], [1.0]]), (1, n))
+    prf = oracle.Projected(mean2d, depth, conic, np.full(n, 0.5), np.full((3, n), 0.5), radius)
+    K, keys, vals, ranges = oracle.bin_sort(prf, W, H)
+    print(f"[partition loop] K={K}", flush=True)
+    assert K > 2048 * 3840
+    cam = S.aerial_camera(W, H)
+    fr = _frame([cam], n, dev, capacity=K)
+    fr.proj[0] = upload_projection(prf, W, H, dev)
+    assert fr.bin_sort() == K
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(fr.keys[:K]).view(np.uint64), keys)
+    np.testing.assert_array_equal(u32(fr.vals[:K]), vals)
+    assert_same_ranges(u32(fr.ranges), ranges)
+
+
 @pytest.mark.parametrize("path", ["per_tile", "depth_first"])
 def test_bin_sort_equal_depths(oracle, path):
     """Every Gaussian at one depth: the order inside a tile is the index
