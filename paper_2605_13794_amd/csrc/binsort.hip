@@ -62,12 +62,6 @@ __device__ __forceinline__ void stage_cam_ptrs(const EmitIn& E, CamPtrs& P) {
     __syncthreads();
 }
 
-__device__ __forceinline__ uint32_t tiles_of(const EmitIn& E, int64_t e) {
-    const int c = int(e / E.n_in);
-    const int64_t j = e - int64_t(c) * E.n_in;
-    return E.tiles[c][j];
-}
-
 // Inclusive prefix sum over the wavefront (Hillis-Steele with DPP-free
 // cross-lane reads via __shfl_up; 6 steps).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -519,10 +513,12 @@ struct SortLds {
     uint32_t scan4[4];
 };
 
-// At least three wavefronts per SIMD (the 3,840-key instance would take
-// 170 VGPRs, two wavefronts; 168 and three match its LDS limit of three
-// workgroups per compute unit): 142 -> 121 us per pass at 13.5M pairs.
-// KeyT: uint64_t (pairs) or uint32_t (depth keys of the depth-first path).
+// The scatter of a reduce-then-scan pass: ranks every partition stably
+// (eight ballots per key), stages it in LDS in (digit, input order) and writes
+// it at the scanned offsets.  At least three wavefronts per SIMD, which the
+// LDS of the 3,840-key instance allows (three workgroups per compute unit).
+// KeyT: uint64_t (full pairs), uint16_t (tile ids of the compact layout, with
+// 64-bit values) or uint32_t (depth keys of the depth-first path).
 // With gather_src set, the pass writes gather_dst[g] = gather_src[value]
 // instead of the value (the last depth pass: the records in depth order).
 // Without vals_in the value of the key at position i is i.  With final_keys
