@@ -350,7 +350,10 @@ def hbm_fractions(ds, cam, n, capacity, dev, reps=5):
     Bytes: projection 12 N (means, read to cull) + 224 N_vis (the rest) + 49 N
     (outputs); binning 8 N (scan) + 20 N_vis + 12 K (emission) + K (8 + 24 d)
     (d = 8-bit passes of a full-key radix sort over the 32 depth and the tile
-    bits) + 8 K + 8 tiles (ranges); projection backward 557 N_vis."""
+    bits) + 8 K + 8 tiles (ranges); projection backward 557 N_vis; gate and
+    active-set compaction 24 N + N/8 + 4 N_active; compaction of parameters
+    and Adam moments 708 N (read: at a 60 % keep density every 128-byte line
+    of a row holds kept columns) + 708 N_keep (written) + N/8."""
     import torch
 
     from paper_2605_13794_amd import gsmi as G
@@ -394,11 +397,56 @@ def hbm_fractions(ds, cam, n, capacity, dev, reps=5):
         torch.cuda.synchronize()
         t_pbwd += sum(e0.elapsed_ms(e1) for e0, e1 in evs) / reps
     b_pbwd = (236 + 49 + 36 + 236) * n_vis
+    # the active set and the compaction after a simplification pass, with one
+    # seeded keep mask (60 % of the shard): the gate (radius mode, 0.5 px) and
+    # its compaction read the means and log-scales (24 B) and the keep bits,
+    # and write the active indices (4 B each); gs_compact reads every line of
+    # the parameters and both Adam moments (708 B per Gaussian), writes the
+    # kept columns (708 B each) and reads the keep bits
+    import numpy as np
+    rng = np.random.default_rng(11)
+    keep_np = rng.random(n) < 0.6
+    # bit i % 32 of word i / 32
+    words = np.packbits(np.pad(keep_np, (0, (-n) % 32)).reshape(-1, 32), axis=1, bitorder="little")
+    keep_w = torch.from_numpy(np.ascontiguousarray(words).view("<u4").view(np.int32).reshape(-1).copy()).to(dev)
+    n_keep = int(keep_np.sum())
+    active = torch.empty(n, dtype=torch.int32, device=dev)
+    n_act = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws_lod = torch.empty(G.gs_workspace_size(G.GS_OP_LOD_MASK, n), dtype=torch.uint8, device=dev)
+    lodp = G.lod_params(G.GS_LOD_RADIUS, fallback_ratio=0.95, radius_min_px=0.5, radius_sigma_k=1.0)
+    camc = G.camera(cam)
+    G.gs_lod_mask(ds.struct(), camc, lodp, keep_w, active, n_act, ws_lod)
+    for _ in range(2):
+        e[0].record()
+        for _ in range(reps):
+            G.gs_lod_mask(ds.struct(), camc, lodp, keep_w, active, n_act, ws_lod)
+        e[1].record()
+        torch.cuda.synchronize()
+    t_gate = e[0].elapsed_time(e[1]) / reps
+    n_active = int(n_act.item())
+    b_gate = 24 * n + (n + 7) // 8 + 4 * n_active
+    params = [p.detach() for p in ds.params()]
+    src = params + [torch.zeros_like(p) for p in params] + [torch.zeros_like(p) for p in params]
+    dst = [torch.empty(*(p.shape[:-1] + (n_keep,)), dtype=p.dtype, device=dev) for p in src]
+    ws_c = torch.empty(G.gs_workspace_size(G.GS_OP_SIMPLIFY, n), dtype=torch.uint8, device=dev)
+    G.gs_compact(src, dst, n, n_keep, keep_w, ws_c)
+    torch.cuda.synchronize()
+    e[0].record()
+    for _ in range(reps):
+        G.gs_compact(src, dst, n, n_keep, keep_w, ws_c)
+    e[1].record()
+    torch.cuda.synchronize()
+    t_comp = e[0].elapsed_time(e[1]) / reps
+    per_g = sum(int(t.element_size()) * (t.numel() // n) for t in src)
+    b_comp = per_g * (n + n_keep) + (n + 7) // 8
+    del src, dst
     res = {}
-    for name, b, t in (("project", b_proj, t_proj), ("bin_sort", b_sort, t_sort), ("project_bwd", b_pbwd, t_pbwd)):
+    for name, b, t in (("project", b_proj, t_proj), ("bin_sort", b_sort, t_sort), ("project_bwd", b_pbwd, t_pbwd),
+                       ("lod_mask", b_gate, t_gate), ("compact", b_comp, t_comp)):
         gbs = b / (t * 1e-3) / 1e9
         res[name] = {"ms": t, "bytes": b, "GB_per_s": gbs, "frac": gbs / PEAK_HBM_GBS}
     res["n"], res["n_visible"], res["pairs"] = n, n_vis, K
+    res["n_active"], res["n_keep"] = n_active, n_keep
     res["sort_path"] = "per-tile depth sort" if f.capacity <= 256 * tiles else "depth-first"
     return res
 

@@ -512,33 +512,89 @@ struct CompactArgs {
     int n_arrays;
 };
 
+#define GS_GLOBAL __attribute__((address_space(1)))
+
+// Columns per thread in the compaction (kBlk apart, so that every load of a
+// row is one coalesced dword per lane) and rows whose loads are issued
+// together before the first store.
+constexpr int kCompJ = 4;
+constexpr int kCompCols = kBlk * kCompJ;
+constexpr int kCompRows = 8;
+
+// Kept elements per block of kBlk * J elements.
+template <int J>
 __global__ __launch_bounds__(256) void k_keep_count(const uint32_t* __restrict__ keep, int64_t n,
                                                     uint32_t* __restrict__ cnt) {
     __shared__ uint32_t w4[4];
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    uint32_t tot;
-    block_rank(i < n && bit_of(keep, i), w4, &tot);
-    if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+    const int64_t i0 = int64_t(blockIdx.x) * (kBlk * J) + threadIdx.x;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int64_t i = i0 + int64_t(j) * kBlk;
+        uint32_t tot;
+        block_rank(i < n && bit_of(keep, i), w4, &tot);
+        sum += tot;
+    }
+    if (threadIdx.x == 0) cnt[blockIdx.x] = sum;
+}
+
+// One array's rows for this thread's kCompJ columns: kCompRows x kCompJ
+// loads (row index clamped, column clamped in range) issued before the
+// stores of the kept columns. The row base is wave-uniform and the column
+// and destination offsets fit 32 bits (n < 2^31).
+template <typename T>
+__device__ __forceinline__ void compact_rows(const T GS_GLOBAL* s, T GS_GLOBAL* d, int rows, int64_t n,
+                                             int64_t n_keep, const uint32_t (&col)[kCompJ],
+                                             const uint32_t (&r)[kCompJ], const bool (&k)[kCompJ]) {
+    for (int c = 0; c < rows; c += kCompRows) {
+        T v[kCompRows][kCompJ];
+#pragma unroll
+        for (int u = 0; u < kCompRows; ++u) {
+            const T GS_GLOBAL* sr = s + int64_t(min(c + u, rows - 1)) * n;
+#pragma unroll
+            for (int j = 0; j < kCompJ; ++j) v[u][j] = sr[col[j]];
+        }
+#pragma unroll
+        for (int u = 0; u < kCompRows; ++u) {
+            T GS_GLOBAL* dr = d + int64_t(c + u) * n_keep;
+#pragma unroll
+            for (int j = 0; j < kCompJ; ++j)
+                if (k[j] && c + u < rows) dr[r[j]] = v[u][j];
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_compact_arrays(CompactArgs A, const uint32_t* __restrict__ keep, int64_t n,
                                                         int64_t n_keep, const uint32_t* __restrict__ offs) {
     __shared__ uint32_t w4[4];
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    const bool k = i < n && bit_of(keep, i);
-    uint32_t tot;
-    const int64_t r = int64_t(offs[blockIdx.x]) + block_rank(k, w4, &tot);
-    if (!k || r >= n_keep) return;
+    const int64_t i0 = int64_t(blockIdx.x) * kCompCols + threadIdx.x;
+    uint32_t word[kCompJ], col[kCompJ], r[kCompJ];
+    bool k[kCompJ];
+#pragma unroll
+    for (int j = 0; j < kCompJ; ++j) {
+        col[j] = uint32_t(min(i0 + int64_t(j) * kBlk, n - 1));
+        word[j] = keep[col[j] >> 5];
+    }
+    int64_t run = offs[blockIdx.x];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < kCompJ; ++j) {
+        const bool kj = i0 + int64_t(j) * kBlk < n && ((word[j] >> (col[j] & 31)) & 1u);
+        uint32_t tot;
+        const int64_t rj = run + block_rank(kj, w4, &tot);
+        run += tot;
+        k[j] = kj && rj < n_keep;
+        r[j] = uint32_t(rj);
+        any |= k[j];
+    }
+    if (!any) return;
     for (int a = 0; a < A.n_arrays; ++a) {
-        if (A.bytes[a] == 4) {
-            const float* s = static_cast<const float*>(A.src[a]);
-            float* d = static_cast<float*>(A.dst[a]);
-            for (int c = 0; c < A.rows[a]; ++c) d[int64_t(c) * n_keep + r] = s[int64_t(c) * n + i];
-        } else {
-            const uint8_t* s = static_cast<const uint8_t*>(A.src[a]);
-            uint8_t* d = static_cast<uint8_t*>(A.dst[a]);
-            for (int c = 0; c < A.rows[a]; ++c) d[int64_t(c) * n_keep + r] = s[int64_t(c) * n + i];
-        }
+        if (A.bytes[a] == 4)
+            compact_rows<float>((const float GS_GLOBAL*)A.src[a], (float GS_GLOBAL*)A.dst[a], A.rows[a], n, n_keep,
+                                col, r, k);
+        else
+            compact_rows<uint8_t>((const uint8_t GS_GLOBAL*)A.src[a], (uint8_t GS_GLOBAL*)A.dst[a], A.rows[a], n,
+                                  n_keep, col, r, k);
     }
 }
 
@@ -843,9 +899,9 @@ extern "C" int gs_compact(const void* const* src, void* const* dst, const int32_
     SelWs S = carve_sel(cv, n);
     (void)S;
     cv.take<float>(size_t(n));
-    const int64_t nb = (n + kBlk - 1) / kBlk;
+    const int64_t nb = (n + kCompCols - 1) / kCompCols;
     uint32_t* cnt = cv.take<uint32_t>(size_t(nb + 1));
-    hipLaunchKernelGGL(k_keep_count, dim3(unsigned(nb)), dim3(256), 0, stream, keep_bits, n, cnt);
+    hipLaunchKernelGGL(k_keep_count<kCompJ>, dim3(unsigned(nb)), dim3(256), 0, stream, keep_bits, n, cnt);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, cnt, nb, static_cast<uint64_t*>(nullptr),
                        static_cast<const SelState*>(nullptr));
     hipLaunchKernelGGL(k_compact_arrays, dim3(unsigned(nb)), dim3(256), 0, stream, A, keep_bits, n, n_keep, cnt);
@@ -940,7 +996,7 @@ extern "C" int gs_spawn_gate(const uint8_t* lod, const int32_t* clone_parent, co
         hipLaunchKernelGGL(k_keep_bits, dim3(unsigned(nb)), dim3(256), 0, stream, scores[set], n,
                            static_cast<const SelState*>(S.st), static_cast<const uint32_t*>(S.eq_cnt), keep, 1, 0,
                            static_cast<unsigned long long*>(nullptr));
-        hipLaunchKernelGGL(k_keep_count, dim3(unsigned(nb)), dim3(256), 0, stream, static_cast<const uint32_t*>(keep),
+        hipLaunchKernelGGL(k_keep_count<1>, dim3(unsigned(nb)), dim3(256), 0, stream, static_cast<const uint32_t*>(keep),
                            n, cnt);
         hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, stream, cnt, nb, static_cast<uint64_t*>(nullptr),
                            static_cast<const SelState*>(nullptr));

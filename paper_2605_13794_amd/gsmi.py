@@ -309,9 +309,11 @@ def gs_sample_keep_bits(score, uniforms, n, n_keep, keep_bits, ws, stream=None):
 
 
 def gs_compact(src, dst, n, n_keep, keep_bits, ws, stream=None):
-    """src/dst: lists of tensors [rows, n] / [rows, n_keep] (float32 or uint8)."""
+    """src/dst: lists of contiguous tensors [..., n] / [..., n_keep] (float32
+    or uint8); every leading dimension counts as rows (e.g. [16][3][n] SH is
+    48 rows)."""
     k = len(src)
-    rows = (ctypes.c_int32 * k)(*[1 if t.dim() == 1 else int(t.shape[0]) for t in src])
+    rows = (ctypes.c_int32 * k)(*[int(t.numel() // max(int(t.shape[-1]), 1)) if t.shape[-1] else 0 for t in src])
     eb = (ctypes.c_int32 * k)(*[int(t.element_size()) for t in src])
     _check(lib().gs_compact(_ptr_array(src), _ptr_array(dst), rows, eb, k, int(n), int(n_keep), ptr(keep_bits),
                             ptr(ws), ws.numel(), stream_handle(stream)), "gs_compact")

@@ -69,7 +69,8 @@ def test_compact_matches_reference(oracle):
     G = gsmi()
     n = 100_003
     rng = np.random.default_rng(2)
-    arrays = [rng.standard_normal((3, n)).astype(np.float32), rng.standard_normal((48, n)).astype(np.float32),
+    # the SH layout [16][3][n]: its leading dimensions together are the rows
+    arrays = [rng.standard_normal((3, n)).astype(np.float32), rng.standard_normal((16, 3, n)).astype(np.float32),
               rng.standard_normal(n).astype(np.float32), rng.integers(0, 8, n).astype(np.uint8)]
     keep = rng.random(n) < 0.61
     n_keep = int(keep.sum())
