@@ -145,55 +145,85 @@ __global__ __launch_bounds__(256) void k_gate(GateArgs G, int64_t chunk, uint32_
     }
 }
 
-// Pass 2 (same grid): every workgroup reduces the nb <= 2048 block counts
-// itself — the total gated count decides the fallback, and the counts of the
-// workgroups before it give its output offset — then writes its active
-// indices in ascending order.  Workgroup 0 stores the active count.
+// Pass 2 (same grid): every workgroup sums the nb <= 2048 block counts itself
+// (wavefront sums, one barrier) — the total gated count decides the fallback,
+// and the counts of the workgroups before it give its output offset.  It then
+// takes its Gaussians 32 at a time as words (gate bits and keep bits), ranks
+// the words by a block scan of their popcounts, expands the indices of the set
+// bits in LDS and writes them out coalesced, in ascending order.  Workgroup 0
+// stores the active count.  A round takes `rw` <= 256 words (one per thread);
+// the LDS stage holds 32 indices per word, sized at launch (2 KB for 512
+// Gaussians per workgroup), since the gate runs beside the blends of another
+// stream and a larger stage would hold LDS they could use.
+constexpr int kGateWords = 256;  // most words per round of the compaction
+
 __global__ __launch_bounds__(256) void k_gate_compact(GateArgs G, int64_t chunk, int64_t nb,
                                                       const uint32_t* __restrict__ gate_words,
                                                       const uint32_t* __restrict__ c_gate,
                                                       const uint32_t* __restrict__ c_act,
                                                       const uint32_t* __restrict__ c_keep,
                                                       int32_t* __restrict__ out, int64_t* __restrict__ n_active) {
-    __shared__ uint32_t w4[4];
-    __shared__ uint64_t red[3][256];
-    uint64_t sg = 0, sa = 0, sk = 0, pa = 0, pk = 0;
+    __shared__ uint32_t part[5][4];
+    __shared__ uint32_t wsum[4];
+    extern __shared__ int32_t stage[];  // rw * 32 indices
+    const int64_t rw = min<int64_t>(kGateWords, chunk / 32);
+    const int w = threadIdx.x / 64;
+    // gated, active and kept in all workgroups; active and kept before this one
+    uint32_t s[5] = {0u, 0u, 0u, 0u, 0u};
     for (int64_t b = threadIdx.x; b < nb; b += 256) {
         const uint32_t g = c_gate[b], a = c_act[b], k = c_keep[b];
-        sg += g; sa += a; sk += k;
-        if (b < int64_t(blockIdx.x)) { pa += a; pk += k; }
+        const bool before = b < int64_t(blockIdx.x);
+        s[0] += g;
+        s[1] += a;
+        s[2] += k;
+        s[3] += before ? a : 0u;
+        s[4] += before ? k : 0u;
     }
-    red[0][threadIdx.x] = sg;
-    red[1][threadIdx.x] = sa;
-    red[2][threadIdx.x] = sk;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) s[q] = wave_sum_to_last_u32(s[q]);
+    if (lane_id() == 63)
+        for (int q = 0; q < 5; ++q) part[q][w] = s[q];
     __syncthreads();
-    for (uint32_t o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o)
-            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) s[q] = part[q][0] + part[q][1] + part[q][2] + part[q][3];
+    const bool fb = G.n > 0 && double(s[0]) >= double(G.fallback) * double(G.n);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_active = int64_t(fb ? s[2] : s[1]);
+    uint32_t off = fb ? s[4] : s[3];
+    const int64_t nw = (G.n + 31) / 32;
+    const int64_t w_end = min<int64_t>(nw, (int64_t(blockIdx.x) + 1) * (chunk / 32));
+    for (int64_t w0 = int64_t(blockIdx.x) * (chunk / 32); w0 < w_end; w0 += rw) {
+        const int64_t wi = w0 + threadIdx.x;
+        uint32_t m = 0u;
+        if (int64_t(threadIdx.x) < rw && wi < w_end) {
+            m = fb ? ~0u : gate_words[wi];
+            if (G.keep) m &= G.keep[wi];
+            const int64_t rem = G.n - wi * 32;  // >= 1 for wi < nw
+            if (rem < 32) m &= (1u << rem) - 1u;
+        }
+        const uint32_t c = __popc(m);
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane_id() >= uint32_t(o)) inc += t;
+        }
+        if (lane_id() == 63) wsum[w] = inc;
         __syncthreads();
-    }
-    const bool fb = G.n > 0 && double(red[0][0]) >= double(G.fallback) * double(G.n);
-    const uint64_t total = fb ? red[2][0] : red[1][0];
-    __syncthreads();
-    red[0][threadIdx.x] = fb ? pk : pa;
-    __syncthreads();
-    for (uint32_t o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[0][threadIdx.x] += red[0][threadIdx.x + o];
+        uint32_t before = 0, tot = 0;
+        for (int k = 0; k < 4; ++k) {
+            before += k < w ? wsum[k] : 0u;
+            tot += wsum[k];
+        }
+        uint32_t pos = before + inc - c;
+        const int32_t i0 = int32_t(wi * 32);
+        while (m) {
+            stage[pos++] = i0 + (__ffs(m) - 1);
+            m &= m - 1u;
+        }
         __syncthreads();
-    }
-    uint32_t off = uint32_t(red[0][0]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *n_active = int64_t(total);
-    for (int64_t base = int64_t(blockIdx.x) * chunk; base < min<int64_t>(G.n, int64_t(blockIdx.x + 1) * chunk);
-         base += kBlk) {
-        const int64_t i = base + threadIdx.x;
-        const bool in = i < G.n;
-        const bool gate = in && (fb || bit_of(gate_words, i));
-        const bool keep = in && (G.keep ? bit_of(G.keep, i) : true);
-        const bool act = gate && keep;
-        uint32_t tot;
-        const uint32_t r = block_rank(act, w4, &tot);
-        if (act) out[off + r] = int32_t(i);
+        for (uint32_t t = threadIdx.x; t < tot; t += 256) out[off + t] = stage[t];
         off += tot;
+        __syncthreads();  // stage and wsum are reused by the next round
     }
 }
 
@@ -713,7 +743,8 @@ static int lod_mask_launch(const gs_scene* scene, const gs_camera* cam, const gs
         return check_launch("gs_lod_mask");
     }
     launch("gate", k_gate, dim3(unsigned(nb)), dim3(256), 0, stream, G, chunk, words, c_gate, c_act, c_keep);
-    launch("compact", k_gate_compact, dim3(unsigned(nb)), dim3(256), 0, stream, G, chunk, nb,
+    const size_t stage_bytes = size_t(std::min<int64_t>(kGateWords, chunk / 32)) * 32 * sizeof(int32_t);
+    launch("compact", k_gate_compact, dim3(unsigned(nb)), dim3(256), stage_bytes, stream, G, chunk, nb,
            static_cast<const uint32_t*>(words), static_cast<const uint32_t*>(c_gate),
            static_cast<const uint32_t*>(c_act), static_cast<const uint32_t*>(c_keep), active_idx, n_active_dev);
     return check_launch("gs_lod_mask");

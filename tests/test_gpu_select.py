@@ -207,6 +207,46 @@ def test_lod_mask_matches_reference(oracle, mode, with_keep, n):
     assert sym.size <= max(5, 1e-4 * n)
 
 
+def test_lod_mask_several_rounds_per_workgroup(oracle):
+    """Above 2,048 x 8,192 Gaussians every compaction workgroup takes its
+    words in several rounds of 256: random means and log-scales, radius gate
+    with keep bits, then the same input with a fallback that the gate trips."""
+    dev = device()
+    G = gsmi()
+    n = 2048 * 8192 + 12345
+    rng = np.random.default_rng(21)
+    mean = np.empty((3, n), dtype=np.float32)
+    mean[:2] = rng.uniform(-500.0, 500.0, (2, n))
+    mean[2] = rng.uniform(0.0, 80.0, n)
+    log_scale = rng.normal(np.log(0.3), 0.7, (3, n)).astype(np.float32)
+    keepm = rng.random(n) < 0.7
+    bits = oracle.pack_bits(keepm)
+    cam = S.aerial_camera(1920, 1080, 20.0)
+    campos = cam.position.astype(np.float32).astype(np.float64)
+    gate, r = oracle.lod_gate_radius(mean.astype(np.float64), log_scale, campos, cam.fx, 2.0)
+    amb = np.abs(r - 2.0) <= 1e-5 * 2.0
+    assert 0.2 < gate.mean() < 0.8
+    mean_t, ls_t = torch.from_numpy(mean).to(dev), torch.from_numpy(log_scale).to(dev)
+    scene = G.scene(mean_t, ls_t, None, None, None)
+    kb = torch.from_numpy(bits.view(np.int32).copy()).to(dev)
+    active = torch.empty(n, dtype=torch.int32, device=dev)
+    n_act = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(G.gs_workspace_size(G.GS_OP_LOD_MASK, n), dtype=torch.uint8, device=dev)
+    for fb in (0.95, 0.1):
+        ref = oracle.active_set(gate, bits, fallback_ratio=fb)
+        params = G.lod_params(G.GS_LOD_RADIUS, fallback_ratio=fb, radius_min_px=2.0, radius_sigma_k=1.0)
+        G.gs_lod_mask(scene, G.camera(cam), params, kb, active, n_act, ws)
+        torch.cuda.synchronize()
+        m = int(n_act.item())
+        got = to_np(active[:m]).astype(np.int64)
+        assert (np.diff(got) > 0).all()
+        sym = np.setxor1d(got, ref)
+        assert amb[sym].all(), sym[~amb[sym]][:10]
+        assert sym.size <= max(5, 1e-4 * n)
+        if fb < 0.5:
+            np.testing.assert_array_equal(got, np.nonzero(keepm)[0])
+
+
 def test_lod_mask_fallback_and_empty(oracle):
     dev = device()
     G = gsmi()
