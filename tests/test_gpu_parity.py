@@ -318,6 +318,24 @@ def test_bin_sort_empty_and_overflow(oracle):
     assert int(fr.n_pairs.item()) == K
     rg = u32(fr.ranges).reshape(2, -1)
     assert (rg[0] == rg[1]).all()
+    # the depth-first path (a capacity above 256 pairs per tile) overflows the
+    # same way, and a later call that fits sorts in full
+    tiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+    cap = 256 * tiles + 100
+    assert cap < K
+    fr3 = _frame([cam], sc.n, dev, capacity=cap)
+    fr3.proj[0] = upload_projection(prf, cam.width, cam.height, dev)
+    assert fr3.bin_sort(check=False) is None
+    torch.cuda.synchronize()
+    assert int(fr3.n_pairs.item()) == K
+    rg = u32(fr3.ranges).reshape(2, -1)
+    assert (rg[0] == rg[1]).all()
+    fr4 = _frame([cam], sc.n, dev, capacity=K + 1)
+    fr4.proj[0] = upload_projection(prf, cam.width, cam.height, dev)
+    assert fr4.bin_sort() == K
+    np.testing.assert_array_equal(to_np(fr4.keys[:K]).view(np.uint64), keys)
+    np.testing.assert_array_equal(u32(fr4.vals[:K]), vals)
+    assert_same_ranges(u32(fr4.ranges), ranges)
     # nothing visible: K = 0
     behind = S.cube_scene(300, seed=5)
     behind.mean[2] -= 10.0
