@@ -247,6 +247,43 @@ def test_lod_mask_several_rounds_per_workgroup(oracle):
             np.testing.assert_array_equal(got, np.nonzero(keepm)[0])
 
 
+@pytest.mark.parametrize("n", [1, 31, 33, 511, 513, 2049])
+def test_lod_mask_small_sizes(oracle, n):
+    """Ragged sizes around the 32-Gaussian words and the 512-Gaussian chunks of
+    the gate: level gate with keep bits against the reference."""
+    dev = device()
+    G = gsmi()
+    rng = np.random.default_rng(100 + n)
+    mean = rng.uniform(-50.0, 50.0, (3, n)).astype(np.float32)
+    lod = rng.integers(0, 8, n).astype(np.uint8)
+    keepm = rng.random(n) < 0.7
+    bits = oracle.pack_bits(keepm)
+    cam = S.aerial_camera(1920, 1080, 20.0)
+    campos = cam.position.astype(np.float32).astype(np.float64)
+    d = np.linalg.norm(mean.astype(np.float64) - campos[:, None], axis=0)
+    d0 = float(np.median(d))
+    gate = oracle.lod_gate_level(mean.astype(np.float64), lod, campos, d0=d0, l_max=3)
+    x = np.log2(d0 / d) + 0.5
+    amb = np.abs(x - np.round(x)) <= 1e-5
+    mean_t = torch.from_numpy(mean).to(dev)
+    lod_t = torch.from_numpy(lod).to(dev)
+    scene = G.scene(mean_t, None, None, None, None, lod=lod_t)
+    kb = torch.from_numpy(bits.view(np.int32).copy()).to(dev)
+    active = torch.empty(n, dtype=torch.int32, device=dev)
+    n_act = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(G.gs_workspace_size(G.GS_OP_LOD_MASK, n), dtype=torch.uint8, device=dev)
+    for fb in (1.5, 0.0):  # never falls back; always falls back (keep bits alone)
+        ref = oracle.active_set(gate, bits, fallback_ratio=fb)
+        params = G.lod_params(G.GS_LOD_LEVEL, d0=d0, f=2.0, l_max=3, fallback_ratio=fb)
+        G.gs_lod_mask(scene, G.camera(cam), params, kb, active, n_act, ws)
+        torch.cuda.synchronize()
+        m = int(n_act.item())
+        got = to_np(active[:m]).astype(np.int64)
+        assert (np.diff(got) > 0).all()
+        sym = np.setxor1d(got, ref)
+        assert amb[sym].all(), sym[~amb[sym]][:10]
+
+
 def test_lod_mask_fallback_and_empty(oracle):
     dev = device()
     G = gsmi()

@@ -83,3 +83,30 @@ def test_compact_matches_reference(oracle):
     torch.cuda.synchronize()
     for r, d in zip(ref, dst):
         np.testing.assert_array_equal(to_np(d), r)
+
+
+@pytest.mark.parametrize("n", [1, 31, 1023, 1024, 1025, 4097])
+def test_compact_edge_sizes(oracle, n):
+    """Sizes around the 1,024 columns of a compaction workgroup and its
+    32-column keep words, with every column kept, none kept and a random half
+    (a float array of 9 rows, one of a single row and a byte array)."""
+    dev = device()
+    G = gsmi()
+    rng = np.random.default_rng(n)
+    arrays = [rng.standard_normal((9, n)).astype(np.float32), rng.standard_normal(n).astype(np.float32),
+              rng.integers(0, 255, (2, n)).astype(np.uint8)]
+    src = [torch.from_numpy(a).to(dev) for a in arrays]
+    ws = torch.empty(G.gs_workspace_size(G.GS_OP_SIMPLIFY, n), dtype=torch.uint8, device=dev)
+    for keep in (np.ones(n, dtype=bool), np.zeros(n, dtype=bool), rng.random(n) < 0.5):
+        n_keep = int(keep.sum())
+        ref = oracle.compact(arrays, keep)
+        dst = [torch.full((*a.shape[:-1], max(n_keep, 1)), 7, dtype=t.dtype, device=dev) for a, t in zip(arrays, src)]
+        kb = torch.from_numpy(oracle.pack_bits(keep).view(np.int32)).to(dev)
+        G.gs_compact(src, dst, n, n_keep, kb, ws)
+        torch.cuda.synchronize()
+        for r, d in zip(ref, dst):
+            if n_keep == 0:
+                assert (to_np(d) == 7).all()  # nothing written
+            else:
+                np.testing.assert_array_equal(to_np(d), r)
+
