@@ -347,10 +347,15 @@ int gs_sample_keep_bits(const float* score, const float* uniforms, int64_t n, in
 
 /*
  * Compaction after a pass: for each of n_arrays component-major arrays
- * (rows[a] x n elements of elem_bytes[a] = 4 or 1 bytes), dst[a] (rows[a] x
- * n_keep) receives the kept columns in ascending index order.  n_keep must
- * equal the number of set bits (read from gs_mass_keep_bits or known).
- * n_arrays <= 16.  Workspace: GS_OP_SIMPLIFY.
+ * (rows[a] x n elements of elem_bytes[a] = 4 or 1 bytes; a [16][3][n] array
+ * is 48 rows), dst[a] (rows[a] x n_keep) receives the kept columns in
+ * ascending index order.  keep_bits: ceil(n / 32) words, bit i % 32 of word
+ * i / 32 (may be null when n = 0).  n_keep must equal the number of set bits
+ * (read from gs_mass_keep_bits or known); columns ranked n_keep or later are
+ * not written.  1 <= n_arrays <= 16, rows[a] >= 1, n < 2^31; src, dst and
+ * the keep bits are device memory the caller owns, src and dst distinct.
+ * GS_ERR_INVALID_ARG for other arguments, GS_ERR_WORKSPACE for a short or
+ * unaligned workspace (GS_OP_SIMPLIFY); n = 0 or n_keep = 0 launch nothing.
  */
 int gs_compact(const void* const* src, void* const* dst, const int32_t* rows, const int32_t* elem_bytes,
                int n_arrays, int64_t n, int64_t n_keep, const uint32_t* keep_bits, void* ws,

@@ -910,7 +910,7 @@ extern "C" int gs_sample_keep_bits(const float* score, const float* uniforms, in
 extern "C" int gs_compact(const void* const* src, void* const* dst, const int32_t* rows, const int32_t* elem_bytes,
                           int n_arrays, int64_t n, int64_t n_keep, const uint32_t* keep_bits, void* ws,
                           size_t ws_bytes, hipStream_t stream) {
-    if (n_arrays < 1 || n_arrays > 16 || !src || !dst || !rows || !elem_bytes || !keep_bits)
+    if (n_arrays < 1 || n_arrays > 16 || !src || !dst || !rows || !elem_bytes || (n > 0 && !keep_bits))
         return fail(GS_ERR_INVALID_ARG, "gs_compact: bad arguments");
     if (n < 0 || n >= (int64_t(1) << 31) || n_keep < 0 || n_keep > n)
         return fail(GS_ERR_INVALID_ARG, "gs_compact: need 0 <= n_keep <= n < 2^31");

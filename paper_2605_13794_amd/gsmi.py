@@ -7,6 +7,7 @@ library has not been built.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import torch
@@ -313,7 +314,7 @@ def gs_compact(src, dst, n, n_keep, keep_bits, ws, stream=None):
     or uint8); every leading dimension counts as rows (e.g. [16][3][n] SH is
     48 rows)."""
     k = len(src)
-    rows = (ctypes.c_int32 * k)(*[int(t.numel() // max(int(t.shape[-1]), 1)) if t.shape[-1] else 0 for t in src])
+    rows = (ctypes.c_int32 * k)(*[math.prod(int(x) for x in t.shape[:-1]) for t in src])
     eb = (ctypes.c_int32 * k)(*[int(t.element_size()) for t in src])
     _check(lib().gs_compact(_ptr_array(src), _ptr_array(dst), rows, eb, k, int(n), int(n_keep), ptr(keep_bits),
                             ptr(ws), ws.numel(), stream_handle(stream)), "gs_compact")

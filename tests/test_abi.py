@@ -75,6 +75,26 @@ def test_host_side_errors(G):
     assert rc == G.GS_ERR_WORKSPACE
 
 
+def test_compact_host_side_errors(G):
+    """gs_compact checks its arguments before any launch (no device pointer is
+    dereferenced on these paths)."""
+    L = G.lib()
+    P = ctypes.c_void_p
+    src, dst = (P * 1)(256), (P * 1)(512)
+    rows, eb = (ctypes.c_int32 * 1)(3), (ctypes.c_int32 * 1)(4)
+    ws, keep, big = P(256), P(1024), 1 << 20
+    inval = G.GS_ERR_INVALID_ARG
+    assert L.gs_compact(src, dst, rows, eb, 1, 10, 5, None, ws, big, None) == inval  # no keep bits for n > 0
+    assert L.gs_compact(src, dst, rows, eb, 1, 10, 11, keep, ws, big, None) == inval  # n_keep > n
+    assert L.gs_compact(src, dst, rows, eb, 1, -1, 0, keep, ws, big, None) == inval  # negative n
+    assert L.gs_compact(src, dst, rows, eb, 0, 10, 5, keep, ws, big, None) == inval  # no arrays
+    assert L.gs_compact(src, dst, rows, eb, 17, 10, 5, keep, ws, big, None) == inval  # more than 16 arrays
+    assert L.gs_compact(src, dst, rows, (ctypes.c_int32 * 1)(2), 1, 10, 5, keep, ws, big, None) == inval
+    assert L.gs_compact(src, dst, (ctypes.c_int32 * 1)(0), eb, 1, 10, 5, keep, ws, big, None) == inval
+    assert L.gs_compact(src, dst, rows, eb, 1, 10, 5, keep, ws, 16, None) == G.GS_ERR_WORKSPACE
+    assert L.gs_compact(src, dst, rows, eb, 1, 10, 5, keep, P(260), big, None) == G.GS_ERR_WORKSPACE  # unaligned
+
+
 def test_noalloc_gate_refuses_oversized_input_on_the_host(G):
     """The allocation-free gate rejects more Gaussians than its fixed scratch
     holds before touching the device."""

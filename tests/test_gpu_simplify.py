@@ -85,6 +85,17 @@ def test_compact_matches_reference(oracle):
         np.testing.assert_array_equal(to_np(d), r)
 
 
+def test_compact_empty():
+    """n = 0 (an empty keep array, whose pointer is null) launches nothing."""
+    dev = device()
+    G = gsmi()
+    src = [torch.empty(3, 0, device=dev), torch.empty(16, 3, 0, device=dev), torch.empty(0, dtype=torch.uint8, device=dev)]
+    dst = [torch.empty_like(t) for t in src]
+    ws = torch.empty(max(G.gs_workspace_size(G.GS_OP_SIMPLIFY, 0), 256), dtype=torch.uint8, device=dev)
+    G.gs_compact(src, dst, 0, 0, torch.empty(0, dtype=torch.int32, device=dev), ws)
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("n", [1, 31, 1023, 1024, 1025, 4097])
 def test_compact_edge_sizes(oracle, n):
     """Sizes around the 1,024 columns of a compaction workgroup and its
