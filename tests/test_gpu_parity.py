@@ -488,7 +488,7 @@ def test_end_to_end_forward_backward(oracle, case):
     mask = (ref["margin"] >= 1e-3) & tile_mask(tiles, W, H) & ties
     assert bad.size <= 3 and mask.mean() > 0.95, (bad.size, ties.mean(), mask.mean())
     diff = np.abs(to_np(out.rgb[0]) - ref["rgb"])[:, mask]
-    assert diff.max() <= 5e-4, (diff.max(), ties.mean())
+    assert diff.max() <= 1e-4, (diff.max(), ties.mean())
     target = S.target_image(W, H, seed=1)
     _, g = oracle.l1_loss(ref["rgb"], target)
     g[:, ~mask] = 0.0

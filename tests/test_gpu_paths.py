@@ -11,7 +11,7 @@ the parameters, against the float64 reference, through the C ABI:
   - a batch of four cameras in one projection / sort / compositing / backward
     (the multi-view training batch).
 
-Tolerances as in the other parity tests: images max-abs 5e-4 end to end on
+Tolerances as in the other parity tests: images max-abs 1e-4 end to end on
 pixels whose decisions are not near a threshold, gradients per tensor
 max|g - g_ref| <= 1e-3 max|g_ref|, active lists bit-exact, and gradients
 exactly zero at every Gaussian outside the active list.
@@ -77,7 +77,7 @@ def _device_gate(ds, cam, params, keep, dev):
     return active, n_act
 
 
-def _check_images(fr, refs, cams, tol=5e-4):
+def _check_images(fr, refs, cams, tol=1e-4):
     """Returns per camera the comparable-pixel mask after checking the image
     there."""
     masks = []

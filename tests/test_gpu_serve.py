@@ -49,7 +49,7 @@ def test_served_4k_images_match_reference(oracle):
     """Requests of every served resolution, 3840x2160 among them, in one burst
     over three streams: each served image is bit-identical to the same view
     rendered alone, and that single-view 4K render matches the float64
-    reference (max-abs 5e-4 end to end, on the comparable pixels)."""
+    reference (max-abs 2e-4 end to end at 3840 px, on the comparable pixels)."""
     dev = device()
     gsmi()
     from paper_2605_13794_amd.raster import DeviceScene, Frame
@@ -84,4 +84,6 @@ def test_served_4k_images_match_reference(oracle):
     mask, n_bad = comparable_pixels(ref, to_np(fr.proj[0].radius), r.cam.width, r.cam.height)
     assert n_bad <= 3 and mask.mean() > 0.95, (n_bad, mask.mean())
     diff = np.abs(to_np(out.rgb[0]) - ref["rgb"])[:, mask]
-    assert diff.max() <= 5e-4, diff.max()
+    # float32 screen coordinates between 2,048 and 4,096 px are 2.4e-4 px apart
+    # (twice the spacing of a 1080p view), so the end-to-end drift doubles
+    assert diff.max() <= 2e-4, diff.max()
