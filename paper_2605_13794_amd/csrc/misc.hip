@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ rg
     if (!part) return;
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (uint32_t o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_l1_final(const double* __restrict__ par
     for (int i = threadIdx.x; i < nparts; i += 256) acc += part[i];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (uint32_t o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
