@@ -223,10 +223,14 @@ class GpuExecutor:
         return copies
 
 
-def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, keep_images=False, idle_sleep=0.0):
+def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, keep_images=False, idle_sleep=0.0,
+          max_retries: int = 8):
     """Runs the arrival trace (request.arrival in seconds from the start)
     through the scheduler and executor; returns the completed requests (with
-    t_done set) and, if asked, their images keyed by request id.
+    t_done set) and, if asked, their images keyed by request id.  A request
+    whose batch still overflows its pair buffer after max_retries re-queues
+    (pairs beyond the largest buffer the executor can give) raises
+    RuntimeError.
 
     If the executor keeps device time stamps (start_clock / device_time),
     t_done is the completion of the request's batch on the device clock,
@@ -250,6 +254,10 @@ def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, kee
             if executor.done(slot):
                 K = executor.pairs(slot)
                 if K > executor.capacity(slot):
+                    batch = scheduler.running[slot][0]
+                    if max(r.retries for r in batch) >= max_retries:
+                        raise RuntimeError(f"serve: a batch of {len(batch)} requests needs {K} pairs, more than "
+                                           f"its buffer of {executor.capacity(slot)}, after {max_retries} retries")
                     scheduler.retry(slot, K)
                     continue
                 t = clock() - t0

@@ -92,6 +92,22 @@ def test_overflow_is_retried_with_a_larger_estimate():
     assert all(r.pairs <= max(c for _, ids, c in ex.launches if r.rid in ids) for r in done)
 
 
+def test_overflow_beyond_the_largest_buffer_raises():
+    """An executor whose buffers cannot grow past a cap: the server gives up
+    after its retries instead of re-queueing forever."""
+    import pytest
+
+    class Capped(FakeExecutor):
+        def launch(self, slot, batch, capacity):
+            super().launch(slot, batch, min(capacity, 1000))
+
+    clock = FakeClock()
+    ex = Capped(clock, ppx_true=2.0)
+    sch = Scheduler(n_slots=1, max_batch=1, memory_budget=10**12, pairs_per_px=1.0)
+    with pytest.raises(RuntimeError, match="after 3 retries"):
+        serve(_reqs(2), ex, sch, clock=clock, max_retries=3)
+
+
 def test_fifo_start_order():
     clock = FakeClock()
     ex = FakeExecutor(clock)
