@@ -93,43 +93,73 @@ struct GateArgs {
     int l_max;
 };
 
+// Most gate workgroups of a call (the chunk grows with n to stay within it).
+constexpr int kGateMaxGroups = 2048;
+
 // Pass 1: each workgroup takes `chunk` consecutive Gaussians (a multiple of
-// 256), stores the gate bits and counts gated, gated-and-kept and kept ones.
+// 512), stores the gate bits and counts gated, gated-and-kept and kept ones.
+// Two rounds of 256 Gaussians per trip, every load of both rounds (index
+// clamped) issued before the first use; MODE is the call's G.mode.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_gate(GateArgs G, int64_t chunk, uint32_t* __restrict__ gate_words,
                                               uint32_t* __restrict__ c_gate, uint32_t* __restrict__ c_act,
                                               uint32_t* __restrict__ c_keep) {
     __shared__ uint32_t w4[3][4];
     uint32_t ng = 0, na = 0, nk = 0;  // per wavefront; summed over the workgroup at the end
-    for (int64_t base = int64_t(blockIdx.x) * chunk; base < min<int64_t>(G.n, int64_t(blockIdx.x + 1) * chunk);
-         base += kBlk) {
-        const int64_t i = base + threadIdx.x;
-        const bool in = i < G.n;
-        bool gate = in;
-        if (in && G.mode != GS_LOD_NONE) {
-            const float dx = G.mean[i] - G.campos[0];
-            const float dy = G.mean[G.n + i] - G.campos[1];
-            const float dz = G.mean[2 * G.n + i] - G.campos[2];
-            const float d = sqrtf(dx * dx + dy * dy + dz * dz);
-            if (G.mode == GS_LOD_LEVEL) {
-                int lv;
-                if (d < 1e-6f) {
-                    lv = G.l_max;
+    const int64_t end = min<int64_t>(G.n, int64_t(blockIdx.x + 1) * chunk);
+    for (int64_t base = int64_t(blockIdx.x) * chunk; base < end; base += 2 * kBlk) {
+        float mx[2], my[2], mz[2], s0[2], s1[2], s2[2];
+        uint32_t lod_[2], kw[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t ic = min<int64_t>(base + u * kBlk + threadIdx.x, G.n - 1);
+            mx[u] = my[u] = mz[u] = s0[u] = s1[u] = s2[u] = 0.f;
+            lod_[u] = 0u;
+            if (MODE != GS_LOD_NONE) {
+                mx[u] = G.mean[ic];
+                my[u] = G.mean[G.n + ic];
+                mz[u] = G.mean[2 * G.n + ic];
+                if (MODE == GS_LOD_LEVEL) {
+                    lod_[u] = G.lod[ic];
                 } else {
-                    const float x = floorf(log2f(G.d0 / d) * G.inv_log2f + 0.5f);
-                    lv = int(fminf(fmaxf(x, 0.f), float(G.l_max)));
+                    s0[u] = G.log_scale[ic];
+                    s1[u] = G.log_scale[G.n + ic];
+                    s2[u] = G.log_scale[2 * G.n + ic];
                 }
-                gate = int(G.lod[i]) <= lv;
-            } else {
-                const float smax = fmaxf(fmaxf(G.log_scale[i], G.log_scale[G.n + i]), G.log_scale[2 * G.n + i]);
-                gate = G.fx_k * __expf(smax) >= G.rmin * d;
             }
+            kw[u] = G.keep ? G.keep[ic >> 5] : ~0u;
         }
-        const bool keep = in && (G.keep ? bit_of(G.keep, i) : true);
-        const uint64_t mg = ballot(gate);
-        store_bits(gate_words, G.n, base + (threadIdx.x / 64) * 64, mg);
-        ng += popc64(mg);
-        na += popc64(ballot(gate && keep));
-        nk += popc64(ballot(keep));
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t i = base + u * kBlk + threadIdx.x;
+            const bool in = i < G.n;
+            bool gate = in;
+            if (MODE != GS_LOD_NONE) {
+                const float dx = mx[u] - G.campos[0];
+                const float dy = my[u] - G.campos[1];
+                const float dz = mz[u] - G.campos[2];
+                const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+                if (MODE == GS_LOD_LEVEL) {
+                    int lv;
+                    if (d < 1e-6f) {
+                        lv = G.l_max;
+                    } else {
+                        const float x = floorf(log2f(G.d0 / d) * G.inv_log2f + 0.5f);
+                        lv = int(fminf(fmaxf(x, 0.f), float(G.l_max)));
+                    }
+                    gate = in && int(lod_[u]) <= lv;
+                } else {
+                    const float smax = fmaxf(fmaxf(s0[u], s1[u]), s2[u]);
+                    gate = in && G.fx_k * __expf(smax) >= G.rmin * d;
+                }
+            }
+            const bool keep = in && ((kw[u] >> (i & 31)) & 1u);
+            const uint64_t mg = ballot(gate);
+            store_bits(gate_words, G.n, base + u * kBlk + (threadIdx.x / 64) * 64, mg);
+            ng += popc64(mg);
+            na += popc64(ballot(gate && keep));
+            nk += popc64(ballot(keep));
+        }
     }
     const int w = threadIdx.x / 64;
     if (lane_id() == 0) {
@@ -168,16 +198,30 @@ __global__ __launch_bounds__(256) void k_gate_compact(GateArgs G, int64_t chunk,
     extern __shared__ int32_t stage[];  // rw * 32 indices
     const int64_t rw = min<int64_t>(kGateWords, chunk / 32);
     const int w = threadIdx.x / 64;
-    // gated, active and kept in all workgroups; active and kept before this one
+    // gated, active and kept in all workgroups; active and kept before this
+    // one.  nb <= 2048: every count load of a thread (index clamped) is issued
+    // before the first use.
     uint32_t s[5] = {0u, 0u, 0u, 0u, 0u};
-    for (int64_t b = threadIdx.x; b < nb; b += 256) {
-        const uint32_t g = c_gate[b], a = c_act[b], k = c_keep[b];
-        const bool before = b < int64_t(blockIdx.x);
-        s[0] += g;
-        s[1] += a;
-        s[2] += k;
-        s[3] += before ? a : 0u;
-        s[4] += before ? k : 0u;
+    {
+        constexpr int kIt = kGateMaxGroups / 256;
+        uint32_t g_[kIt], a_[kIt], k_[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int64_t b = min<int64_t>(int64_t(threadIdx.x) + it * 256, nb - 1);
+            g_[it] = c_gate[b];
+            a_[it] = c_act[b];
+            k_[it] = c_keep[b];
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int64_t b = int64_t(threadIdx.x) + it * 256;
+            const bool in = b < nb, before = b < int64_t(blockIdx.x);
+            s[0] += in ? g_[it] : 0u;
+            s[1] += in ? a_[it] : 0u;
+            s[2] += in ? k_[it] : 0u;
+            s[3] += before ? a_[it] : 0u;
+            s[4] += before ? k_[it] : 0u;
+        }
     }
 #pragma unroll
     for (int q = 0; q < 5; ++q) s[q] = wave_sum_to_last_u32(s[q]);
@@ -232,7 +276,7 @@ __global__ __launch_bounds__(256) void k_gate_compact(GateArgs G, int64_t chunk,
 // 2,048 workgroups, since every compaction workgroup reduces all their counts.
 static int64_t gate_chunk(int64_t n) {
     int64_t c = 512;
-    while ((n + c - 1) / c > 2048) c *= 2;
+    while ((n + c - 1) / c > kGateMaxGroups) c *= 2;
     return c;
 }
 
@@ -742,7 +786,15 @@ static int lod_mask_launch(const gs_scene* scene, const gs_camera* cam, const gs
         if (rc) return rc;
         return check_launch("gs_lod_mask");
     }
-    launch("gate", k_gate, dim3(unsigned(nb)), dim3(256), 0, stream, G, chunk, words, c_gate, c_act, c_keep);
+    if (G.mode == GS_LOD_LEVEL)
+        launch("gate", k_gate<GS_LOD_LEVEL>, dim3(unsigned(nb)), dim3(256), 0, stream, G, chunk, words, c_gate, c_act,
+               c_keep);
+    else if (G.mode == GS_LOD_RADIUS)
+        launch("gate", k_gate<GS_LOD_RADIUS>, dim3(unsigned(nb)), dim3(256), 0, stream, G, chunk, words, c_gate,
+               c_act, c_keep);
+    else
+        launch("gate", k_gate<GS_LOD_NONE>, dim3(unsigned(nb)), dim3(256), 0, stream, G, chunk, words, c_gate, c_act,
+               c_keep);
     const size_t stage_bytes = size_t(std::min<int64_t>(kGateWords, chunk / 32)) * 32 * sizeof(int32_t);
     launch("compact", k_gate_compact, dim3(unsigned(nb)), dim3(256), stage_bytes, stream, G, chunk, nb,
            static_cast<const uint32_t*>(words), static_cast<const uint32_t*>(c_gate),
