@@ -11,9 +11,12 @@ namespace gsmi {
 constexpr int kBlk = 256;  // elements per block, one per thread
 
 // Exclusive scan of per-block counts in place (one workgroup); writes the
-// total to *total if non-null.
+// total to *total if non-null.  Each thread takes kScanPer consecutive counts
+// per round (4,096 counts a round), all loaded before the first use.
 struct SelState;
 __device__ bool ties_need_ranks(const SelState* s);
+
+constexpr int kScanPer = 16;
 
 __global__ __launch_bounds__(256) void k_scan_counts(uint32_t* __restrict__ cnt, int64_t nb,
                                                      uint64_t* __restrict__ total, const SelState* __restrict__ gate) {
@@ -22,11 +25,19 @@ __global__ __launch_bounds__(256) void k_scan_counts(uint32_t* __restrict__ cnt,
     if (gate && !ties_need_ranks(gate)) return;  // no tie ranks needed: offsets unused
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
-    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
-        const int64_t b = b0 + threadIdx.x;
-        const uint32_t v = b < nb ? cnt[b] : 0u;
-        // wave inclusive scan
-        uint32_t inc = v;
+    for (int64_t b0 = 0; b0 < nb; b0 += 256 * kScanPer) {
+        const int64_t s0 = b0 + int64_t(threadIdx.x) * kScanPer;
+        uint32_t v[kScanPer];
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) v[k] = cnt[min<int64_t>(s0 + k, nb - 1)];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            v[k] = s0 + k < nb ? v[k] : 0u;
+            sum += v[k];
+        }
+        // wave inclusive scan of the per-thread sums
+        uint32_t inc = sum;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t t = __shfl_up(inc, o, 64);
@@ -40,10 +51,14 @@ __global__ __launch_bounds__(256) void k_scan_counts(uint32_t* __restrict__ cnt,
             if (k < w) before += w4[k];
             tot += w4[k];
         }
-        const uint64_t carry = carry_s;
-        if (b < nb) cnt[b] = uint32_t(carry + before + inc - v);
+        uint64_t run = carry_s + before + inc - sum;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (s0 + k < nb) cnt[s0 + k] = uint32_t(run);
+            run += v[k];
+        }
         __syncthreads();
-        if (threadIdx.x == 0) carry_s = carry + tot;
+        if (threadIdx.x == 0) carry_s += tot;
         __syncthreads();
     }
     if (threadIdx.x == 0 && total) *total = carry_s;
