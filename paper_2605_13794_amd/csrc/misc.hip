@@ -84,11 +84,22 @@ constexpr int kL1Blocks = 1024;
 
 __device__ __forceinline__ float l1_sign(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
 
+// Sum of one double per thread over a 256-thread workgroup, in a fixed order
+// (butterfly within each wavefront, then the four wavefront sums); valid in
+// thread 0.
+__device__ __forceinline__ double block_sum_f64(double v, double* w4) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) w4[threadIdx.x / 64] = v;
+    __syncthreads();
+    return (w4[0] + w4[1]) + (w4[2] + w4[3]);
+}
+
 __global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ rgb,
                                                     const float* __restrict__ target, int64_t n,
                                                     float* __restrict__ grad, const float* __restrict__ scale,
                                                     double* __restrict__ part) {
-    __shared__ double red[256];
+    __shared__ double red[4];
     const float inv = (scale ? *scale : 1.0f) / float(n);
     double acc = 0.0;
     const int64_t stride = int64_t(gridDim.x) * 256;
@@ -114,27 +125,24 @@ __global__ __launch_bounds__(256) void k_l1_partial(const float* __restrict__ rg
         if (grad) grad[i] = l1_sign(d) * inv;
     }
     if (!part) return;
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (uint32_t o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    const double tot = block_sum_f64(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// nparts <= kL1Blocks: every load of a thread (index clamped) is issued
+// before the first use.
 __global__ __launch_bounds__(256) void k_l1_final(const double* __restrict__ part, int nparts, int64_t n,
                                                   float* __restrict__ loss) {
-    __shared__ double red[256];
+    __shared__ double red[4];
+    constexpr int kIt = kL1Blocks / 256;
+    double v[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) v[it] = part[min(int(threadIdx.x) + it * 256, nparts - 1)];
     double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 256) acc += part[i];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (uint32_t o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *loss = float(red[0] / double(n));
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) acc += int(threadIdx.x) + it * 256 < nparts ? v[it] : 0.0;
+    const double tot = block_sum_f64(acc, red);
+    if (threadIdx.x == 0) *loss = float(tot / double(n));
 }
 
 // ---------------------------------------------------------------------------
