@@ -121,3 +121,35 @@ def test_compact_edge_sizes(oracle, n):
             else:
                 np.testing.assert_array_equal(to_np(d), r)
 
+
+def test_compact_large_offsets(oracle):
+    """48 rows of 2^25 + 3 columns (6.4 GB): row offsets past 4 GB.  Values are
+    integer bit patterns (row * 2654435761 + column, 32 bits); three windows
+    of columns, the last one ragged, are compared with the reference's
+    compaction of the same window in rows 0, 1, 23 and 47."""
+    dev = device()
+    G = gsmi()
+    n, rows = (1 << 25) + 3, 48
+    src = torch.empty(rows, n, dtype=torch.int32, device=dev)
+    col = torch.arange(n, dtype=torch.int64, device=dev)
+    for r in range(rows):
+        v = (col + r * 2654435761) & 0xFFFFFFFF
+        src[r] = torch.where(v >= 1 << 31, v - (1 << 32), v).to(torch.int32)
+    del col, v
+    rng = np.random.default_rng(5)
+    words = rng.integers(0, 1 << 32, (n + 31) // 32, dtype=np.uint64).astype(np.uint32)
+    keep = oracle.unpack_bits(words, n)
+    n_keep = int(keep.sum())
+    dst = torch.empty(rows, n_keep, dtype=torch.int32, device=dev)
+    ws = torch.empty(G.gs_workspace_size(G.GS_OP_SIMPLIFY, n), dtype=torch.uint8, device=dev)
+    kb = torch.from_numpy(words.view(np.int32)).to(dev)
+    G.gs_compact([src.view(torch.float32)], [dst.view(torch.float32)], n, n_keep, kb, ws)
+    torch.cuda.synchronize()
+    before = np.concatenate([[0], np.cumsum(keep)])
+    for c0, c1 in [(0, 100_000), (n // 2 - 50_000, n // 2 + 50_000), (n - 100_003, n)]:
+        k0, k1 = int(before[c0]), int(before[c1])
+        for r in (0, 1, 23, 47):
+            window = to_np(src[r, c0:c1])
+            (ref,) = oracle.compact([window], keep[c0:c1])
+            np.testing.assert_array_equal(to_np(dst[r, k0:k1]), ref)
+
