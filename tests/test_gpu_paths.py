@@ -185,6 +185,54 @@ def test_large_input_plain_matches_reference(oracle):
         assert e <= 1e-3, (name, e)
 
 
+def test_projection_past_4gb_offsets(oracle):
+    """24 x 2^20 + 5 Gaussians, so the [16][3][n] coefficient array (4.8 GB)
+    has rows past 4 GB: an 8,192-Gaussian scene repeated along the index and
+    projected in one call (the single-pass kernel of large inputs); entries
+    at the start, middle and end are compared with the reference's
+    projection of the base scene, with the tolerances of the projection
+    parity test."""
+    dev = device()
+    G = gsmi()
+    from paper_2605_13794_amd.raster import ProjBuffers
+    base = S.cube_scene(8192, seed=7)
+    cam = S.cube_camera(128, 128, 128.0)
+    n, nb = 24 * (1 << 20) + 5, base.n
+    print(f"[projection past 4 GB] n={n}", flush=True)
+    idx = torch.arange(n, device=dev) % nb
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    mean = t(base.mean)[:, idx].contiguous()
+    log_scale = t(base.log_scale)[:, idx].contiguous()
+    quat = t(base.quat)[:, idx].contiguous()
+    opac = t(base.opacity_logit)[idx].contiguous()
+    sh = t(base.sh)[:, :, idx].contiguous()
+    del idx
+    assert sh.numel() * 4 > (1 << 32)
+    pb = ProjBuffers(n, dev, soa=True)
+    ws = torch.empty(G.gs_workspace_size(G.GS_OP_PROJECT, n), dtype=torch.uint8, device=dev)
+    G.gs_project(G.scene(mean, log_scale, quat, opac, sh), None, n, None, G.camera_array([cam]), [pb.struct()], ws)
+    torch.cuda.synchronize()
+    _, out, pr = oracle.project(base.arrays(), cam)
+    lam = out["lam"].numpy()
+    e = 3.0 * np.sqrt(np.maximum(lam, 0))
+    m2 = out["mean2d"].detach().numpy().T
+    amb = (np.abs(e - np.round(e)) < 1e-4 * np.maximum(e, 1)) | (np.abs(m2 - np.round(m2)) < 1e-3).any(0) | \
+          (np.abs(out["depth"].detach().numpy() - cam.znear) < 1e-5)
+    ok = ~amb
+    vis = ok & (pr.radius > 0)
+    scale = max(cam.width, cam.height)
+    for j0 in (0, (n // 2) // nb * nb, (n - 5) // nb * nb - nb):
+        sl = slice(j0, j0 + nb)
+        np.testing.assert_array_equal(to_np(pb.radius[sl])[ok], pr.radius[ok])
+        np.testing.assert_allclose(to_np(pb.mean2d[:, sl])[:, vis], pr.mean2d[:, vis], rtol=0, atol=2e-7 * scale * 4)
+        np.testing.assert_allclose(to_np(pb.depth[sl])[vis], pr.depth[vis], rtol=1e-6)
+        np.testing.assert_allclose(to_np(pb.rgb[:, sl])[:, vis], pr.rgb[:, vis], atol=2e-6)
+    # the last five entries repeat base Gaussians 0..4 bit for bit
+    tail = slice(n - 5, n)
+    np.testing.assert_array_equal(to_np(pb.rgb[:, tail]), to_np(pb.rgb[:, 0:5]))
+    np.testing.assert_array_equal(to_np(pb.radius[tail]), to_np(pb.radius[0:5]))
+
+
 def test_large_input_gated_matches_reference(oracle):
     """The gated path over a 2.3M-Gaussian shard (list of 2.3M entries of
     capacity, device count below it)."""
