@@ -566,6 +566,47 @@ def test_adam_matches_reference(oracle):
         np.testing.assert_allclose(to_np(t), p, rtol=2e-6, atol=1e-6)
 
 
+def test_adam_past_4gb_offsets(oracle):
+    """One group of 2^30 + 2^28 + 3 floats (5.4 GB per array): byte offsets
+    past 4 GB and a ragged tail.  Windows at the start, middle and end hold
+    random values; the rest starts at p = 0.25, g = -0.5.  Two steps with the
+    gradients cleared after each read, compared with the reference on the
+    windows and at a point of the uniform region."""
+    dev = device()
+    G = gsmi()
+    n = (1 << 30) + (1 << 28) + 3
+    print(f"[adam past 4 GB] n={n}", flush=True)
+    p = torch.full((n,), 0.25, device=dev)
+    g = torch.full((n,), -0.5, device=dev)
+    m = torch.zeros(n, device=dev)
+    v = torch.zeros(n, device=dev)
+    rng = np.random.default_rng(9)
+    wins = [(0, 4096), (n // 2 - 2048, n // 2 + 2048), (n - 4099, n)]
+    ref = {}
+    for a, b in wins:
+        x = rng.standard_normal(b - a).astype(np.float32)
+        p[a:b] = torch.from_numpy(x).to(dev)
+        ref[(a, b)] = (x.astype(np.float64), np.zeros(b - a), np.zeros(b - a))
+    probe = n // 4
+    ref_u = (np.array([0.25]), np.zeros(1), np.zeros(1))
+    for step, g_u in ((1, -0.5), (2, 0.0)):
+        gw = {}
+        for a, b in wins:
+            gw[(a, b)] = rng.standard_normal(b - a).astype(np.float32)
+            g[a:b] = torch.from_numpy(gw[(a, b)]).to(dev)
+        G.gs_adam_step([p], [g], [m], [v], [1e-2], 0.9, 0.999, 1e-15, step, clear_grads=True)
+        for w in wins:
+            ref[w] = oracle.adam_step(ref[w][0], gw[w], ref[w][1], ref[w][2], 1e-2, step)
+        ref_u = oracle.adam_step(ref_u[0], np.array([g_u]), ref_u[1], ref_u[2], 1e-2, step)
+    torch.cuda.synchronize()
+    for (a, b), (pr, mr, vr) in ref.items():
+        np.testing.assert_allclose(to_np(p[a:b]), pr, rtol=2e-6, atol=1e-6)
+        np.testing.assert_allclose(to_np(m[a:b]), mr, rtol=2e-6, atol=1e-7)
+        assert (to_np(g[a:b]) == 0).all()
+    np.testing.assert_allclose(to_np(p[probe:probe + 1]), ref_u[0], rtol=2e-6, atol=1e-6)
+    assert float(g[probe].item()) == 0.0
+
+
 def test_batched_cameras_match_single(oracle):
     """Three cameras of different resolutions in one project/sort/render
     batch give bit-identical images to three separate single-camera runs."""
