@@ -607,14 +607,20 @@ def test_adam_past_4gb_offsets(oracle):
     assert float(g[probe].item()) == 0.0
 
 
-def test_batched_cameras_match_single(oracle):
-    """Three cameras of different resolutions in one project/sort/render
-    batch give bit-identical images to three separate single-camera runs."""
+@pytest.mark.parametrize("n_cams", [3, 8])
+def test_batched_cameras_match_single(oracle, n_cams):
+    """Cameras of different resolutions in one project/sort/render batch (up
+    to the eight cameras a launch takes) give bit-identical images to separate
+    single-camera runs."""
     dev = device()
     G = gsmi()
     from paper_2605_13794_amd.raster import DeviceScene
     sc = S.city_scene(1 << 18, seed=7)
     cams = [S.aerial_camera(640, 360, 0.0), S.aerial_camera(320, 200, 90.0), S.aerial_camera(480, 272, 200.0)]
+    if n_cams == 8:
+        cams += [S.aerial_camera(w, h, a) for w, h, a in
+                 [(100, 75, 30.0), (1920, 1080, 130.0), (33, 17, 250.0), (256, 256, 300.0), (720, 405, 45.0)]]
+    assert len(cams) == n_cams <= G.GS_MAX_CAMS
     ds = DeviceScene(sc, dev)
     fb = _frame(cams, sc.n, dev)
     out, K = fb.forward(ds.struct())
