@@ -241,15 +241,18 @@ def test_large_input_gated_matches_reference(oracle):
     _gated_path(oracle, sc, cam, "radius", seed=41)
 
 
-def test_four_camera_batch_backward_matches_reference(oracle):
-    """Four views (the aerial pose at headings 0, 90, 180, 270 degrees) in
-    one batch: images per camera and parameter gradients summed over the
-    four views against the reference run per camera."""
+@pytest.mark.parametrize("headings", [(0.0, 90.0, 180.0, 270.0), tuple(45.0 * k for k in range(8))],
+                         ids=["four_views", "eight_views"])
+def test_four_camera_batch_backward_matches_reference(oracle, headings):
+    """Four views (the aerial pose at headings 0, 90, 180, 270 degrees), and
+    the eight a launch takes (every 45 degrees), in one batch: images per
+    camera and parameter gradients summed over the views against the
+    reference run per camera."""
     dev = device()
     G = gsmi()
     from paper_2605_13794_amd.raster import DeviceScene
     sc = S.city_scene(300_000, seed=23).spatially_ordered()
-    cams = [S.aerial_camera(320, 180, h) for h in (0.0, 90.0, 180.0, 270.0)]
+    cams = [S.aerial_camera(320, 180, h) for h in headings]
     ds = DeviceScene(sc, dev)
     fr = _frame(cams, sc.n, dev)
     out, K = fr.forward(ds.struct())
