@@ -150,10 +150,12 @@ const char* gs_last_error(void);
 
 /* Diagnostics: while `name` is set, every launch of that kernel (one of
  * "project_cull", "project", "visible_list", "project_bwd", "project_bwd_sh",
- * "export_d2", "scan_reduce", "emit", "sort_hist", "sort_pass", "tile_ranges", "seg_sort",
- * "seg_sort_long", "render_fwd", "render_bwd", "importance_blend",
- * "importance_fold", "sel_hist", "gate", "compact", "adam", "fill",
- * "ssim_fwd", "ssim_bwd") records `start`
+ * "export_d2", "scan_reduce", "emit", "vis_compact", "part_count", "sort_pass",
+ * "tile_ranges", "seg_sort", "seg_sort_long", "render_fwd", "render_bwd",
+ * "importance_blend", "importance_split", "importance_fold", "sel_hist",
+ * "gate", "compact" (the gate's active-set pass), "adam", "l1_partial",
+ * "l1_final", "ssim_fwd", "ssim_bwd", "voxel_codes", "voxel_label",
+ * "spawn_emit", "spawn_stub") records `start`
  * and `stop` (caller-owned HIP events) immediately around the kernel on the
  * stream it is launched on; each launch overwrites the previous record.
  * name = NULL or "" turns it off.  Per calling thread. */
